@@ -1,0 +1,168 @@
+"""Oracle-side diagnostics from the paper's equilibrium analysis (FP64, numpy).
+
+TEST INFRASTRUCTURE ONLY.  Used by the oracle's self-tests to pin it against what the paper
+fixes: the bulk equation of state (BULK), the exact mechanical balance across an interface
+(Sec. "The Stress Field on The lattice": the force is the lattice divergence of a stress, so
+the normal stress through any plane is uniform at equilibrium), the surface-stress mismatch
+of Appendix A and the coefficients C2, C4 (eqs. (C2), (C4), (finale4), (finale6)).
+
+Readings of the paper used here:
+  * A0 of Appendix A: the printed -G1(w(1) - 4 w(4)) is read as -G1(w(1) + 4 w(4)); only then
+    does a uniform state give sigma_xx = sigma_zz, and the shell-by-shell derivation of
+    sigma^(4) gives the same sign.
+  * c_s^2 = 1/3 in lattice units.
+"""
+
+import numpy as np
+
+from . import CX, CY
+
+CS2 = 1.0 / 3.0
+
+# Interaction links 1..24 in the numbering of Fig. 1 (pinned by the shell-5 extra terms of
+# Appendix A: c13 = c5 - c3 = c1 - c7, c14 = c5 - c4 = c2 - c7, c15 = c2 - c8 = c6 - c4,
+# c16 = c6 - c1 = c3 - c8).  Index 0 is unused so that LINKS[l] is link l.
+LINKS = [None,
+         (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1),
+         (2, 0), (0, 2), (-2, 0), (0, -2),
+         (2, 1), (1, 2), (-1, 2), (-2, 1), (-2, -1), (-1, -2), (1, -2), (2, -1),
+         (2, 2), (-2, 2), (-2, -2), (2, -2)]
+SHELL_OF = {1: 0, 2: 1, 4: 2, 5: 3, 8: 4}
+
+
+def pseudo(rho, psi0=1.0, rho0=1.0):
+    return psi0 * (1.0 - np.exp(-np.asarray(rho) / rho0))
+
+
+def bulk_pressure(rho, g_total, psi0=1.0, rho0=1.0):
+    """(BULK): P_b = c_s^2 rho + c_s^2 (G1 + G2)/2 psi^2."""
+    psi = pseudo(rho, psi0, rho0)
+    return CS2 * rho + CS2 * 0.5 * g_total * psi * psi
+
+
+def bulk_pressure_2c(rho_a, rho_b, params):
+    """Two-component extension of (BULK) under the cross-term reading:
+    P_b = c_s^2 (rho_A + rho_B) + c_s^2/2 sum_s (G_ss,1 + G_ss,2) psi_s^2 + c_s^2 G_AB rho_A rho_B."""
+    P = params
+    pa = pseudo(rho_a, P.psi0, P.rho0)
+    pb = pseudo(rho_b, P.psi0, P.rho0)
+    return (CS2 * (rho_a + rho_b)
+            + CS2 * 0.5 * ((P.g1[0] + P.g2[0]) * pa * pa + (P.g1[1] + P.g2[1]) * pb * pb)
+            + CS2 * P.gab * rho_a * rho_b)
+
+
+def normal_pressure_x(fstar, psi, rho, params):
+    """Normal stress P_N(x + 1/2) through the plane between columns x and x+1, averaged
+    over y, for a periodic lattice.  Kinetic part: momentum carried across the plane by the
+    post-collision populations in one streaming step.  Interaction part: minus the x-force
+    that the sites right of the plane exert on the sites left of it, from the pair form of
+    eq. (FORCE) (and of the A-B repulsion).  Returns an array over x."""
+    P = params
+    assert P.walls == 0
+    ns = P.ns
+    out = np.zeros(P.lx)
+    right = CX == 1
+    left = CX == -1
+    for s in range(ns):
+        kin = fstar[s, right].sum(axis=0) + np.roll(fstar[s, left].sum(axis=0), -1, axis=1)
+        out += kin.mean(axis=0)
+        K = P.shell_k(s)
+        for l in range(1, 25):
+            cx, cy = LINKS[l]
+            if cx <= 0:
+                continue
+            k = K[SHELL_OF[cx * cx + cy * cy]]
+            # left site at column X - j (j < cx), partner at X - j + cx, row shifted by cy
+            for jj in range(cx):
+                a = np.roll(psi[s], jj, axis=1)                           # psi(X - jj, y)
+                b = np.roll(np.roll(psi[s], jj - cx, axis=1), -cy, axis=0)  # psi(X - jj + cx, y + cy)
+                out += k * cx * (a * b).mean(axis=0)
+    if ns == 2 and P.gab != 0.0:
+        src = psi if P.cross_psi else rho
+        for l in range(1, 9):
+            cx, cy = LINKS[l]
+            if cx <= 0:
+                continue
+            t = P.t[SHELL_OF[cx * cx + cy * cy]]
+            for s in range(2):
+                a = src[s]
+                b = np.roll(np.roll(src[1 - s], -cx, axis=1), -cy, axis=0)
+                out += P.gab * t * cx * (a * b).mean(axis=0)
+    return out
+
+
+def a_coefficients(g1, g2, w, p):
+    """Appendix A coefficients A0..A3 (with the A0 sign reading) for one species."""
+    w1, w4 = w[0], w[2]
+    p1, p4, p5 = p[0], p[2], p[3]
+    a1 = g2 * (p1 / 2 - 3 * p5) + g1 * w1 / 2
+    a2 = g2 * (p4 + 1.5 * p5) + g1 * w4
+    a0 = g2 * (-p1 - 4 * p4) - g1 * (w1 + 4 * w4)
+    a3 = g2 * (2 * p4 + 3 * p5) + 2 * g1 * w4
+    return a0, a1, a2, a3
+
+
+def stress_mismatch_a(psi_x, g1, g2, w, p):
+    """(sigma^int_xx - sigma^int_zz)(x) of a 1-D periodic profile psi(x), Appendix A form."""
+    a0, a1, a2, a3 = a_coefficients(g1, g2, w, p)
+    ps = psi_x
+    p1, m1 = np.roll(ps, -1), np.roll(ps, 1)
+    p2, m2 = np.roll(ps, -2), np.roll(ps, 2)
+    return a1 * ps * (p1 + m1) + a2 * ps * (p2 + m2) + a0 * ps * ps + a3 * p1 * m1
+
+
+def stress_mismatch_shells(psi_x, g1, g2, w, p):
+    """Same quantity built shell by shell from the sigma^(1), sigma^(2), sigma^(4),
+    sigma^(5), sigma^(8) expressions of Appendix A (second, independent route)."""
+    ps = np.asarray(psi_x)
+
+    def at(off):  # psi(x + off) for an integer or half-integer offset given as 2*off
+        return np.roll(ps, -off)
+
+    def half(c):  # psi(x - c/2) psi(x + c/2) for even c_x
+        return np.roll(ps, c // 2) * np.roll(ps, -c // 2)
+
+    def dxz(c):
+        return c[0] * c[0] - c[1] * c[1]
+
+    out = np.zeros_like(ps)
+    for G, W in ((g1, w), (g2, p)):
+        # shells 1 and 2: (G/2) W psi(x) sum psi(x+c) c c
+        for l in range(1, 9):
+            c = LINKS[l]
+            q = SHELL_OF[c[0] ** 2 + c[1] ** 2]
+            out += 0.5 * G * W[q] * ps * at(c[0]) * dxz(c)
+        # shells 4 and 8: (G/4) W [psi(x) psi(x+c) + psi(x-c/2) psi(x+c/2)] c c
+        for l in list(range(9, 13)) + list(range(21, 25)):
+            c = LINKS[l]
+            q = SHELL_OF[c[0] ** 2 + c[1] ** 2]
+            out += 0.25 * G * W[q] * (ps * at(c[0]) + half(c[0])) * dxz(c)
+        # shell 5: (G/4) W(5) psi(x) psi(x+c) c c over links 13..20, plus the extra pairs
+        for l in range(13, 21):
+            c = LINKS[l]
+            out += 0.25 * G * W[3] * ps * at(c[0]) * dxz(c)
+        extra = {13: ((5, 3), (1, 7)), 14: ((5, 4), (2, 7)), 15: ((2, 8), (6, 4)), 16: ((6, 1), (3, 8))}
+        for l, pairs in extra.items():
+            c = LINKS[l]
+            acc = np.zeros_like(ps)
+            for a, b in pairs:
+                acc += at(LINKS[a][0]) * at(LINKS[b][0])
+            out += 0.25 * G * W[3] * acc * dxz(c)
+    return out
+
+
+def c2_c4_formula(g1, g2, e4w, e4p, e6w, e6p):
+    """(C2), (C4)."""
+    return -0.5 * g1 * e4w - 0.5 * g2 * e4p, 0.25 * g1 * e6w + 0.25 * g2 * e6p
+
+
+def c2_c4_from_a(g1, g2, w, p):
+    """C2 = -A1 - 4A2 - 2A3, C4 = A1/12 + 4A2/3 + 2A3/3 (Appendix A)."""
+    _, a1, a2, a3 = a_coefficients(g1, g2, w, p)
+    return -a1 - 4 * a2 - 2 * a3, a1 / 12 + 4 * a2 / 3 + 2 * a3 / 3
+
+
+def droplet_radius(rho, rho_in, rho_out):
+    """Equimolar radius of a single circular droplet: area = (M - rho_out A) / (rho_in - rho_out)."""
+    area = (rho.sum() - rho_out * rho.size) / (rho_in - rho_out)
+    return np.sqrt(abs(area) / np.pi)
