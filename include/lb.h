@@ -1,0 +1,174 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) two-belt pseudopotential lattice Boltzmann library.
+ *
+ * The library advances the one- or two-component D2Q9 BGK lattice Boltzmann equation,
+ * eq. (LB) of Sbragaglia, Benzi, Bernaschi, Succi (arXiv:1402.6019), whose forcing term is
+ * the two-belt competing pseudopotential force of eq. (FORCE): a short-range attraction
+ * (G1 < 0, weights w on links with |c|^2 <= 4) against a mid-range repulsion (G2 > 0,
+ * weights p on links with |c|^2 <= 8), with psi(rho) = psi0 (1 - exp(-rho/rho0)) and the
+ * force applied by shifting the equilibrium velocity (u_eq -> u_eq + tau F / rho).  For two
+ * components (emulsion section of the paper) each species s in {A, B} has its own
+ * populations and couplings G_ss,1, G_ss,2, and the species repel each other with strength
+ * G_AB over the first belt.  Optional planar channel: halfway bounce-back walls at
+ * y = -1/2 and y = ly - 1/2 with a uniform body force (the confined Poiseuille flows).
+ *
+ * Conventions
+ *   - Lattice units (dx = dt = 1, c_s^2 = 1/3).  x is the streamwise (periodic) direction,
+ *     y the cross-stream direction (the paper's z).
+ *   - Device pointers are HIP device addresses (e.g. torch tensors' data_ptr()).  Host
+ *     pointers are marked "host".  Dense field arrays are row-major [...][y][x], x fastest.
+ *   - Population buffers are opaque: ask lb_pop_bytes() for their size and use
+ *     lb_checkpoint()/lb_restore() to read or write populations in the canonical layout
+ *     f[species][l][y][x] (FP64, pre-collision, D2Q9 order c_0..c_8 =
+ *     (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)).
+ *   - All device work is enqueued on the HIP stream given to lb_init / lb_batch_init and is
+ *     asynchronous unless a call is documented as synchronising.
+ *
+ * Ownership: the caller allocates population buffers and output arrays and keeps them alive
+ * until lb_destroy(); the context borrows them and never frees caller memory.  The context
+ * owns small internal buffers (reduction partials, totals, staging) and frees them in
+ * lb_destroy().
+ *
+ * Errors: every int-returning call returns LB_OK (0) or a negative lb_status.  The reason is
+ * available from lb_last_error(ctx) (or lb_last_error(NULL) when no context exists yet).
+ * Asynchronous numerical failure (non-finite or non-positive density) is latched on the
+ * device by the reductions and reported as LB_EUNSTABLE by the next synchronising call.
+ * After an error the context remains valid for lb_restore() and lb_destroy().
+ *
+ * Threads: a context must not be used from two threads at once.
+ */
+#ifndef LB355_LB_H
+#define LB355_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_ctx lb_ctx;
+
+enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = -1,     /* invalid argument (sizes, tau <= 1/2, non-positive density, ...) */
+  LB_ENOMEM = -2,     /* an internal allocation failed, or a caller buffer is too small */
+  LB_EDEVICE = -3,    /* a HIP runtime call failed */
+  LB_EUNSTABLE = -4,  /* the run produced a non-finite or non-positive density */
+  LB_ESTATE = -5      /* call not valid in the current state (e.g. no walls for wall stress) */
+};
+
+/* Storage of the populations in HBM. */
+enum lb_storage {
+  LB_F64 = 0,     /* FP64 populations, FP64 arithmetic */
+  LB_F32 = 1,     /* FP32 populations, FP32 arithmetic */
+  LB_BF16DEV = 2  /* BF16 deviations f_l - W_l rho_ref[s] from the rest equilibrium, FP32 arithmetic */
+};
+
+/* Output type of lb_moments. */
+enum lb_dtype { LB_OUT_F64 = 0, LB_OUT_F32 = 1 };
+
+typedef struct {
+  int32_t lx, ly;      /* lattice size: lx, ly >= 5, ly <= 65535, lx * ly <= 2^27 */
+  int32_t n_species;   /* 1 or 2 */
+  int32_t walls;       /* 0: periodic in x and y; 1: channel, bounce-back walls below row 0 and above row ly-1 */
+  int32_t storage;     /* enum lb_storage */
+} lb_lattice;
+
+typedef struct {
+  /* eq. (FORCE) per species s: G_ss,1 (attractive, < 0) and G_ss,2 (repulsive, > 0). */
+  double g1[2], g2[2];
+  /* A-B repulsion strength G_AB (two components only). */
+  double g_ab;
+  /* Shell weights for |c|^2 = 1, 2, 4, 5, 8: w on the attractive belt (w[3] = w[4] = 0 in the
+     paper's form), p on both belts; t[0], t[1]: A-B cross weights for |c|^2 = 1, 2.
+     lb_default_couplings() fills the isotropic sets (E2 = 1/3; w sixth-order, p eighth-order
+     isotropic; t = D2Q9 weights). */
+  double w[5], p[5], t[2];
+  /* Body force per unit mass g = (g_x, g_y); species s feels rho_s g. */
+  double body_force[2];
+  /* Channel only: densities of the solid ghost rows seen by the force stencil (wetting). */
+  double rho_wall[2];
+  /* 0: A-B repulsion between densities (default); 1: between pseudopotentials. */
+  int32_t cross_uses_psi;
+  int32_t reserved_;
+} lb_couplings;
+
+typedef struct {
+  double psi0, rho0;   /* psi(rho) = psi0 (1 - exp(-rho / rho0)) */
+  double rho_ref[2];   /* LB_BF16DEV only: reference density per species for the stored deviations */
+} lb_psi_params;
+
+/* Fill *c with zero couplings and the default isotropic weights.  Pure host call. */
+int lb_default_couplings(lb_couplings *c);
+
+/* Bytes of ONE population buffer for this lattice (two are needed: ping and pong).
+   Returns 0 for an invalid lattice.  Pure host call. */
+size_t lb_pop_bytes(const lb_lattice *lat);
+
+/*
+ * Create a simulation.  Validates the lattice (lx, ly >= 5, n_species in {1,2}, walls in
+ * {0,1}, storage valid), tau[s] > 1/2, psi0 > 0, rho0 > 0, rho_init > 0 and finite, and
+ * pop_bytes >= lb_pop_bytes(lat).  rho_init (host, [n_species][ly][lx]) gives the rest
+ * equilibrium start f_l = W_l rho_init.  pop_a and pop_b are device buffers of pop_bytes
+ * each; the state starts in pop_a.  hip_stream is a hipStream_t (NULL = default stream).
+ * Synchronises the stream once (host-to-device copy of rho_init).
+ */
+int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const double tau[2],
+            const lb_psi_params *psi, const double *rho_init, void *pop_a, void *pop_b, size_t pop_bytes,
+            void *hip_stream);
+
+/* Advance n >= 0 time steps of eq. (LB) (pull streaming + two-belt force + BGK collision in
+   one fused kernel per step).  Asynchronous.  Returns LB_EUNSTABLE if an earlier reduction
+   (see lb_set_reduce_every) has already reported a bad density. */
+int lb_step(lb_ctx *ctx, int64_t n);
+
+/* Run the FP64 reductions (species mass, momentum, wall stress, flow rate, health) in the
+   epilogue of every k-th step (k = 0: never; default 0).  lb_wall_stress averages over the
+   steps that ran them.  Host call. */
+int lb_set_reduce_every(lb_ctx *ctx, int32_t k);
+
+/* Density and velocity of the current state: rho (device, [n_species][ly][lx]) and
+   u (device, [2][ly][lx]) with u = (sum_s j_s + F_s / 2) / sum_s rho_s.  dtype: lb_dtype.
+   Either pointer may be NULL.  Asynchronous. */
+int lb_moments(lb_ctx *ctx, void *rho, void *u, int32_t dtype);
+
+/* Time-averaged x-force per unit wall length on the bottom and top walls (host out[2]),
+   averaged over the reduced steps since the last reset; momentum exchange of the bounced
+   populations, 2 c_x f*.  reset != 0 clears the running average after reading.
+   Channel lattices only (LB_ESTATE otherwise).  Synchronises. */
+int lb_wall_stress(lb_ctx *ctx, double out[2], int32_t reset);
+
+/* FP64 totals of the current state (host outputs): species masses mass[s] and total
+   momentum (sum_s j_s); also the flow rate (1/lx) sum u_x if flow != NULL.  Launches one
+   reduction pass.  Synchronises; returns LB_EUNSTABLE on a bad density. */
+int lb_totals(lb_ctx *ctx, double mass[2], double momentum[2], double *flow);
+
+/* Write the current pre-collision populations f(t) in the canonical FP64 layout to dst
+   (device, n_species*9*ly*lx doubles).  Asynchronous. */
+int lb_checkpoint(lb_ctx *ctx, void *dst_f64);
+
+/* Replace the state by canonical FP64 pre-collision populations src (device).  Clears a
+   latched LB_EUNSTABLE.  Asynchronous. */
+int lb_restore(lb_ctx *ctx, const void *src_f64);
+
+/* Number of completed time steps. */
+int64_t lb_time(const lb_ctx *ctx);
+
+/* Launch shape of the step kernel: strip width tx in {64, 128, 256} columns (one workgroup
+   thread per column) and sy >= 1 rows per workgroup.  Any shape gives bitwise identical
+   results.  Host call. */
+int lb_set_tile(lb_ctx *ctx, int32_t tx, int32_t sy);
+int lb_get_tile(const lb_ctx *ctx, int32_t *tx, int32_t *sy);
+
+/* Message of the last failure on ctx (ctx = NULL: last failure of lb_init in this thread). */
+const char *lb_last_error(const lb_ctx *ctx);
+
+/* Release the context's own buffers (not the caller's). */
+void lb_destroy(lb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB355_LB_H */

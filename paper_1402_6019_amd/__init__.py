@@ -1,0 +1,156 @@
+"""MI355X-native two-belt pseudopotential lattice Boltzmann step (arXiv:1402.6019).
+
+The compute path is the HIP library ``liblb355.so`` behind the C ABI of ``include/lb.h``;
+``Sim`` is a thin wrapper that owns the device buffers as torch tensors (PyTorch is used for
+device memory and streams only) and forwards every call to the library.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import LB_BF16DEV, LB_F32, LB_F64, LbError
+
+STORAGE = {"f64": LB_F64, "f32": LB_F32, "bf16dev": LB_BF16DEV}
+
+__all__ = ["Sim", "LbError", "STORAGE", "default_weights"]
+
+
+def default_weights():
+    """(w[5], p[5], t[2]) defaults of the library (isotropic sets, E2 = 1/3)."""
+    c = B.default_couplings()
+    return list(c.w), list(c.p), list(c.t)
+
+
+def _pair(v):
+    if np.isscalar(v):
+        return (float(v), float(v))
+    v = tuple(float(x) for x in v)
+    return v if len(v) == 2 else (v[0], v[0])
+
+
+class Sim:
+    """One lattice on one GPU.
+
+    Parameters follow the paper's statement of the problem: lattice (lx, ly, species,
+    walls), couplings g1 = G_ss,1, g2 = G_ss,2, gab = G_AB, body force g, relaxation time
+    tau, pseudopotential psi0 (1 - exp(-rho / rho0)); rho_init is the initial density
+    [n_species, ly, lx] (host array), started from rest equilibrium.
+    """
+
+    def __init__(self, lx, ly, rho_init, n_species=1, walls=False, storage="f64", g1=(0.0, 0.0),
+                 g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0), rho_wall=(0.0, 0.0), tau=(1.0, 1.0), psi0=1.0,
+                 rho0=1.0, rho_ref=(0.0, 0.0), w=None, p=None, t=None, cross_psi=False, device="cuda",
+                 tile=None):
+        import torch
+        self._lib = B.load()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.lx, self.ly, self.ns = int(lx), int(ly), int(n_species)
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.lat = B.LbLattice(self.lx, self.ly, self.ns, 1 if walls else 0, self.storage)
+        cpl = B.default_couplings()
+        cpl.g1[:] = _pair(g1)
+        cpl.g2[:] = _pair(g2)
+        cpl.g_ab = float(gab)
+        if w is not None:
+            cpl.w[:] = [float(v) for v in w]
+        if p is not None:
+            cpl.p[:] = [float(v) for v in p]
+        if t is not None:
+            cpl.t[:] = [float(v) for v in t]
+        cpl.body_force[:] = _pair(body) if len(body) == 2 else body
+        cpl.rho_wall[:] = _pair(rho_wall)
+        cpl.cross_uses_psi = 1 if cross_psi else 0
+        self.cpl = cpl
+        self.tau = (ctypes.c_double * 2)(*_pair(tau))
+        self.psi = B.LbPsiParams(float(psi0), float(rho0), (ctypes.c_double * 2)(*_pair(rho_ref)))
+        nbytes = B.pop_bytes(self.lat)
+        if nbytes == 0:
+            raise LbError(B.LB_EINVAL, "invalid lattice")
+        self.pop_bytes = nbytes
+        self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        rho = np.ascontiguousarray(np.broadcast_to(rho_init, (self.ns, self.ly, self.lx)), dtype=np.float64)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self._lib.lb_init(ctypes.byref(h), ctypes.byref(self.lat), ctypes.byref(cpl), self.tau,
+                               ctypes.byref(self.psi), rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.c_void_p(self.pop_a.data_ptr()), ctypes.c_void_p(self.pop_b.data_ptr()),
+                               nbytes, ctypes.c_void_p(self.stream.cuda_stream))
+        B.check(rc, None)
+        self._h = h
+        if tile is not None:
+            self.set_tile(*tile)
+
+    # -- lifetime -------------------------------------------------------------------------
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lb_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        return B.check(rc, self._h)
+
+    # -- C ABI ----------------------------------------------------------------------------
+    @property
+    def time(self):
+        return self._lib.lb_time(self._h)
+
+    def step(self, n=1):
+        self._chk(self._lib.lb_step(self._h, int(n)))
+
+    def set_reduce_every(self, k):
+        self._chk(self._lib.lb_set_reduce_every(self._h, int(k)))
+
+    def set_tile(self, tx, sy):
+        self._chk(self._lib.lb_set_tile(self._h, int(tx), int(sy)))
+
+    def get_tile(self):
+        tx, sy = ctypes.c_int32(), ctypes.c_int32()
+        self._chk(self._lib.lb_get_tile(self._h, ctypes.byref(tx), ctypes.byref(sy)))
+        return tx.value, sy.value
+
+    def moments(self, dtype=None):
+        """(rho [ns, ly, lx], u [2, ly, lx]) device tensors of the current state."""
+        torch = self.torch
+        dtype = dtype or torch.float64
+        rho = torch.empty((self.ns, self.ly, self.lx), dtype=dtype, device=self.device)
+        u = torch.empty((2, self.ly, self.lx), dtype=dtype, device=self.device)
+        code = B.LB_OUT_F32 if dtype == torch.float32 else B.LB_OUT_F64
+        self._chk(self._lib.lb_moments(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr()), code))
+        return rho, u
+
+    def totals(self):
+        """(mass[2], momentum[2], flow) of the current state (FP64; synchronises)."""
+        m = (ctypes.c_double * 2)()
+        p = (ctypes.c_double * 2)()
+        q = ctypes.c_double()
+        self._chk(self._lib.lb_totals(self._h, m, p, ctypes.byref(q)))
+        return (m[0], m[1]), (p[0], p[1]), q.value
+
+    def wall_stress(self, reset=False):
+        out = (ctypes.c_double * 2)()
+        self._chk(self._lib.lb_wall_stress(self._h, out, 1 if reset else 0))
+        return out[0], out[1]
+
+    def checkpoint(self):
+        """Canonical FP64 pre-collision populations f[ns, 9, ly, lx] (device tensor)."""
+        f = self.torch.empty((self.ns, 9, self.ly, self.lx), dtype=self.torch.float64, device=self.device)
+        self._chk(self._lib.lb_checkpoint(self._h, ctypes.c_void_p(f.data_ptr())))
+        return f
+
+    def restore(self, f):
+        f = self.torch.as_tensor(f, dtype=self.torch.float64, device=self.device).contiguous()
+        if tuple(f.shape) != (self.ns, 9, self.ly, self.lx):
+            raise ValueError("populations must have shape (n_species, 9, ly, lx)")
+        self._keep = f  # keep alive until the asynchronous restore kernel has read it
+        self._chk(self._lib.lb_restore(self._h, ctypes.c_void_p(f.data_ptr())))

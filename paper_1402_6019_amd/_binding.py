@@ -1,0 +1,102 @@
+"""ctypes binding of the C ABI in include/lb.h (argument marshalling only).
+
+Every step of the lattice Boltzmann path runs in the HIP library ``liblb355.so``; this module
+only converts Python values to the C structures and passes raw device pointers and the
+current HIP stream.  Importing it requires the built library: there is no fallback.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblb355.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
+LB_F64, LB_F32, LB_BF16DEV = 0, 1, 2
+LB_OUT_F64, LB_OUT_F32 = 0, 1
+STATUS_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_EDEVICE",
+                LB_EUNSTABLE: "LB_EUNSTABLE", LB_ESTATE: "LB_ESTATE"}
+
+
+class LbLattice(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("n_species", ctypes.c_int32),
+                ("walls", ctypes.c_int32), ("storage", ctypes.c_int32)]
+
+
+class LbCouplings(ctypes.Structure):
+    _fields_ = [("g1", ctypes.c_double * 2), ("g2", ctypes.c_double * 2), ("g_ab", ctypes.c_double),
+                ("w", ctypes.c_double * 5), ("p", ctypes.c_double * 5), ("t", ctypes.c_double * 2),
+                ("body_force", ctypes.c_double * 2), ("rho_wall", ctypes.c_double * 2),
+                ("cross_uses_psi", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
+class LbPsiParams(ctypes.Structure):
+    _fields_ = [("psi0", ctypes.c_double), ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double * 2)]
+
+
+class LbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# Exported symbols and their signatures (name -> (restype, argtypes)).
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "lb_default_couplings": (ctypes.c_int, [ctypes.POINTER(LbCouplings)]),
+    "lb_pop_bytes": (_sz, [ctypes.POINTER(LbLattice)]),
+    "lb_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(LbLattice), ctypes.POINTER(LbCouplings), _dp,
+                               ctypes.POINTER(LbPsiParams), _dp, _vp, _vp, _sz, _vp]),
+    "lb_step": (ctypes.c_int, [_vp, _i64]),
+    "lb_set_reduce_every": (ctypes.c_int, [_vp, _i32]),
+    "lb_moments": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "lb_wall_stress": (ctypes.c_int, [_vp, _dp, _i32]),
+    "lb_totals": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "lb_checkpoint": (ctypes.c_int, [_vp, _vp]),
+    "lb_restore": (ctypes.c_int, [_vp, _vp]),
+    "lb_time": (_i64, [_vp]),
+    "lb_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
+    "lb_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "lb_last_error": (ctypes.c_char_p, [_vp]),
+    "lb_destroy": (None, [_vp]),
+}
+
+
+def load():
+    """Load liblb355.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1402_6019_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime first)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc, ctx=None):
+    if rc != LB_OK:
+        msg = load().lb_last_error(ctx)
+        raise LbError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def default_couplings():
+    c = LbCouplings()
+    check(load().lb_default_couplings(ctypes.byref(c)))
+    return c
+
+
+def pop_bytes(lattice):
+    return load().lb_pop_bytes(ctypes.byref(lattice))

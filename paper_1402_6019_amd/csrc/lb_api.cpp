@@ -1,0 +1,452 @@
+// Host runtime of the C ABI declared in include/lb.h: validation, coefficient folding,
+// ping-pong of the caller's population buffers, launches on the caller's HIP stream,
+// FP64 reductions and the latched health check.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lb.h"
+#include "lb_internal.hpp"
+#include "lb_tables.hpp"
+
+using namespace lb355;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kPitchAlign = 64;  // elements: rows start on 64-element boundaries
+constexpr int kMaxBlocks = 1 << 20;
+
+size_t elem_size(int storage) { return storage == LB_F64 ? 8 : (storage == LB_F32 ? 4 : 2); }
+int row_pitch(int lx) { return (lx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
+
+}  // namespace
+
+struct lb_ctx {
+  lb_lattice lat{};
+  lb_couplings cpl{};
+  lb_psi_params psi{};
+  double tau[2]{1.0, 1.0};
+  void *pop[2]{nullptr, nullptr};
+  int cur = 0;
+  size_t pop_bytes = 0;
+  hipStream_t stream = nullptr;
+  int pitch = 0;
+  long long plane = 0;
+  int tx = 256, sy = 16;
+  int reduce_every = 0;
+  int64_t t = 0;
+  double *d_partials = nullptr;  // [partial_cap][RED_N], grown to the largest launch
+  int partial_cap = 0;
+  double *d_totals = nullptr;    // [RED_N]
+  double *d_acc = nullptr;       // [4]: wall stress sums (bot, top), count, bad
+  double *h_acc = nullptr;       // pinned copy of d_acc for the asynchronous health check
+  hipEvent_t ev = nullptr;
+  bool check_pending = false;
+  bool unstable = false;
+  std::string err;
+};
+
+namespace {
+
+int fail(lb_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+int hip_fail(lb_ctx *c, hipError_t e, const char *what) {
+  return fail(c, LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int grid_blocks(const lb_ctx *c, int tx, int sy, int *nseg) {
+  const int nstrip = (c->lat.lx + tx - 1) / tx;
+  const int ns = (c->lat.ly + sy - 1) / sy;
+  if (nseg) *nseg = ns;
+  return nstrip * ns;
+}
+
+int ensure_partials(lb_ctx *c, int nb) {
+  if (nb <= c->partial_cap) return LB_OK;
+  if (c->d_partials) (void)hipFree(c->d_partials);
+  c->d_partials = nullptr;
+  c->partial_cap = 0;
+  hipError_t e = hipMalloc(&c->d_partials, (size_t)nb * RED_N * sizeof(double));
+  if (e != hipSuccess) return fail(c, LB_ENOMEM, std::string("partials: ") + hipGetErrorString(e));
+  c->partial_cap = nb;
+  return LB_OK;
+}
+
+void fill_step_args(const lb_ctx *c, StepArgs &a) {
+  std::memset(&a, 0, sizeof(a));
+  a.plane = c->plane;
+  a.lx = c->lat.lx;
+  a.ly = c->lat.ly;
+  a.pitch = c->pitch;
+  a.sy = c->sy;
+  a.cross_psi = c->cpl.cross_uses_psi;
+  for (int s = 0; s < 2; ++s) {
+    for (int q = 0; q < 5; ++q) a.K[s][q] = c->cpl.g1[s] * c->cpl.w[q] + c->cpl.g2[s] * c->cpl.p[q];
+    a.tau[s] = c->tau[s];
+    a.omega[s] = 1.0 / c->tau[s];
+    a.rho_w[s] = c->cpl.rho_wall[s];
+    a.psi_w[s] = c->psi.psi0 * (1.0 - std::exp(-c->cpl.rho_wall[s] / c->psi.rho0));
+    a.rho_ref[s] = c->psi.rho_ref[s];
+  }
+  a.T[0] = c->cpl.g_ab * c->cpl.t[0];
+  a.T[1] = c->cpl.g_ab * c->cpl.t[1];
+  a.body[0] = c->cpl.body_force[0];
+  a.body[1] = c->cpl.body_force[1];
+  a.psi0 = c->psi.psi0;
+  a.irho0 = 1.0 / c->psi.rho0;
+}
+
+// One launch of the fused kernel on the current buffer.
+int run_step_kernel(lb_ctx *c, int what, void *out_rho, void *out_u, int out_f32) {
+  int nseg = 0;
+  const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
+  const bool reduce = (what == WHAT_STEP_REDUCE || what == WHAT_OBSERVE);
+  if (reduce) {
+    int rc = ensure_partials(c, nb);
+    if (rc) return rc;
+  }
+  StepArgs a;
+  fill_step_args(c, a);
+  a.nseg = nseg;
+  a.src = c->pop[c->cur];
+  a.dst = c->pop[c->cur ^ 1];
+  a.partials = c->d_partials;
+  a.out_rho = out_rho;
+  a.out_u = out_u;
+  a.out_f32 = out_f32;
+  hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, what, c->tx, nb, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+  if (reduce) {
+    e = launch_reduce(c->d_partials, nb, c->d_totals, c->d_acc, what == WHAT_STEP_REDUCE ? 1 : 0,
+                      1.0 / c->lat.lx, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+  }
+  return LB_OK;
+}
+
+// Latched health check: look at the last asynchronously copied accumulator if it is ready.
+int poll_health(lb_ctx *c, bool wait) {
+  if (c->check_pending) {
+    hipError_t e = wait ? hipEventSynchronize(c->ev) : hipEventQuery(c->ev);
+    if (e == hipSuccess) {
+      c->check_pending = false;
+      if (c->h_acc[3] > 0.0) c->unstable = true;
+    } else if (e != hipErrorNotReady) {
+      return hip_fail(c, e, "health check");
+    }
+  }
+  if (c->unstable) return fail(c, LB_EUNSTABLE, "non-finite or non-positive density detected by the reductions");
+  return LB_OK;
+}
+
+int validate(const lb_lattice *lat, const lb_couplings *cpl, const double tau[2], const lb_psi_params *psi,
+             std::string &msg) {
+  if (!lat || !cpl || !tau || !psi) { msg = "null argument"; return LB_EINVAL; }
+  if (lat->lx < 5 || lat->ly < 5) { msg = "lx and ly must be >= 5"; return LB_EINVAL; }
+  if (lat->ly > 65535 || (long long)lat->lx * lat->ly > (1LL << 31) / 16) {
+    msg = "lattice too large (ly <= 65535, lx * ly <= 2^27)";
+    return LB_EINVAL;
+  }
+  if (lat->n_species != 1 && lat->n_species != 2) { msg = "n_species must be 1 or 2"; return LB_EINVAL; }
+  if (lat->walls != 0 && lat->walls != 1) { msg = "walls must be 0 or 1"; return LB_EINVAL; }
+  if (lat->storage < LB_F64 || lat->storage > LB_BF16DEV) { msg = "unknown storage"; return LB_EINVAL; }
+  for (int s = 0; s < lat->n_species; ++s) {
+    if (!(tau[s] > 0.5) || !std::isfinite(tau[s])) { msg = "tau must be finite and > 1/2"; return LB_EINVAL; }
+    if (!std::isfinite(cpl->g1[s]) || !std::isfinite(cpl->g2[s]) || !std::isfinite(cpl->rho_wall[s]) ||
+        !std::isfinite(psi->rho_ref[s])) {
+      msg = "non-finite coupling";
+      return LB_EINVAL;
+    }
+    if (lat->walls && !(cpl->rho_wall[s] >= 0.0)) { msg = "rho_wall must be >= 0"; return LB_EINVAL; }
+  }
+  if (!std::isfinite(cpl->g_ab) || !std::isfinite(cpl->body_force[0]) || !std::isfinite(cpl->body_force[1])) {
+    msg = "non-finite coupling";
+    return LB_EINVAL;
+  }
+  for (int q = 0; q < 5; ++q)
+    if (!std::isfinite(cpl->w[q]) || !std::isfinite(cpl->p[q])) { msg = "non-finite weight"; return LB_EINVAL; }
+  if (!std::isfinite(cpl->t[0]) || !std::isfinite(cpl->t[1])) { msg = "non-finite weight"; return LB_EINVAL; }
+  if (!(psi->psi0 > 0.0) || !(psi->rho0 > 0.0) || !std::isfinite(psi->psi0) || !std::isfinite(psi->rho0)) {
+    msg = "psi0 and rho0 must be finite and > 0";
+    return LB_EINVAL;
+  }
+  if (cpl->cross_uses_psi != 0 && cpl->cross_uses_psi != 1) { msg = "cross_uses_psi must be 0 or 1"; return LB_EINVAL; }
+  return LB_OK;
+}
+
+void default_tile(lb_ctx *c) {
+  const int lx = c->lat.lx;
+  c->tx = lx >= 256 ? 256 : (lx >= 128 ? 128 : 64);
+  c->sy = std::min(16, c->lat.ly);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_default_couplings(lb_couplings *c) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null argument");
+  std::memset(c, 0, sizeof(*c));
+  for (int q = 0; q < NSHELL; ++q) {
+    c->w[q] = W_ATTR[q];
+    c->p[q] = P_REP[q];
+  }
+  c->t[0] = T_CROSS[0];
+  c->t[1] = T_CROSS[1];
+  return LB_OK;
+}
+
+size_t lb_pop_bytes(const lb_lattice *lat) {
+  if (!lat || lat->lx < 5 || lat->ly < 5 || (lat->n_species != 1 && lat->n_species != 2) ||
+      lat->storage < LB_F64 || lat->storage > LB_BF16DEV)
+    return 0;
+  return (size_t)lat->n_species * 9 * (size_t)lat->ly * row_pitch(lat->lx) * elem_size(lat->storage);
+}
+
+int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const double tau[2],
+            const lb_psi_params *psi, const double *rho_init, void *pop_a, void *pop_b, size_t pop_bytes,
+            void *hip_stream) {
+  if (!out) return fail(nullptr, LB_EINVAL, "null output pointer");
+  *out = nullptr;
+  std::string msg;
+  int rc = validate(lat, cpl, tau, psi, msg);
+  if (rc) return fail(nullptr, rc, msg);
+  if (!rho_init || !pop_a || !pop_b) return fail(nullptr, LB_EINVAL, "null buffer");
+  if (pop_a == pop_b) return fail(nullptr, LB_EINVAL, "pop_a and pop_b must differ");
+  const size_t need = lb_pop_bytes(lat);
+  if (pop_bytes < need) return fail(nullptr, LB_ENOMEM, "population buffers smaller than lb_pop_bytes()");
+  const size_t nsite = (size_t)lat->lx * lat->ly;
+  for (size_t i = 0; i < (size_t)lat->n_species * nsite; ++i)
+    if (!(rho_init[i] > 0.0) || !std::isfinite(rho_init[i]))
+      return fail(nullptr, LB_EINVAL, "rho_init must be finite and > 0 everywhere");
+
+  lb_ctx *c = new (std::nothrow) lb_ctx();
+  if (!c) return fail(nullptr, LB_ENOMEM, "context allocation");
+  c->lat = *lat;
+  c->cpl = *cpl;
+  c->psi = *psi;
+  c->tau[0] = tau[0];
+  c->tau[1] = lat->n_species == 2 ? tau[1] : tau[0];
+  if (lat->n_species == 1) {  // single component: no cross term, second species unused
+    c->cpl.g_ab = 0.0;
+    c->cpl.g1[1] = c->cpl.g2[1] = 0.0;
+    c->cpl.rho_wall[1] = 0.0;
+    c->psi.rho_ref[1] = 0.0;
+  }
+  c->pop[0] = pop_a;
+  c->pop[1] = pop_b;
+  c->pop_bytes = pop_bytes;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->pitch = row_pitch(lat->lx);
+  c->plane = (long long)lat->ly * c->pitch;
+  default_tile(c);
+
+  hipError_t e;
+  if ((e = hipMalloc(&c->d_totals, RED_N * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_acc, 4 * sizeof(double))) != hipSuccess ||
+      (e = hipHostMalloc(&c->h_acc, 4 * sizeof(double), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming)) != hipSuccess) {
+    g_init_error = std::string("internal allocation: ") + hipGetErrorString(e);
+    lb_destroy(c);
+    return LB_ENOMEM;
+  }
+  std::memset(c->h_acc, 0, 4 * sizeof(double));
+  // Stage rho_init in pop_b (it is at least as large as n_species * lx * ly doubles).
+  const size_t rbytes = (size_t)lat->n_species * nsite * sizeof(double);
+  if ((e = launch_fill(c->d_acc, 0.0, 4, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(pop_b, rho_init, rbytes, hipMemcpyHostToDevice, c->stream)) != hipSuccess) {
+    g_init_error = std::string("initial copy: ") + hipGetErrorString(e);
+    lb_destroy(c);
+    return LB_EDEVICE;
+  }
+  LayoutArgs la{};
+  la.in = pop_b;
+  la.out = pop_a;
+  la.plane = c->plane;
+  la.lx = lat->lx;
+  la.ly = lat->ly;
+  la.pitch = c->pitch;
+  la.ns = lat->n_species;
+  la.rho_ref[0] = c->psi.rho_ref[0];
+  la.rho_ref[1] = c->psi.rho_ref[1];
+  if ((e = launch_init(lat->storage, lat->walls, la, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+    g_init_error = std::string("init kernel: ") + hipGetErrorString(e);
+    lb_destroy(c);
+    return LB_EDEVICE;
+  }
+  *out = c;
+  return LB_OK;
+}
+
+int lb_step(lb_ctx *c, int64_t n) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (n < 0) return fail(c, LB_EINVAL, "n must be >= 0");
+  int rc = poll_health(c, false);
+  if (rc) return rc;
+  bool reduced = false;
+  for (int64_t k = 0; k < n; ++k) {
+    const bool red = c->reduce_every > 0 && (c->t % c->reduce_every) == 0;
+    rc = run_step_kernel(c, red ? WHAT_STEP_REDUCE : WHAT_STEP, nullptr, nullptr, 0);
+    if (rc) return rc;
+    reduced |= red;
+    c->cur ^= 1;
+    ++c->t;
+  }
+  if (reduced) {
+    hipError_t e = hipMemcpyAsync(c->h_acc, c->d_acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "health readback");
+    c->check_pending = true;
+  }
+  return LB_OK;
+}
+
+int lb_set_reduce_every(lb_ctx *c, int32_t k) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (k < 0) return fail(c, LB_EINVAL, "k must be >= 0");
+  c->reduce_every = k;
+  return LB_OK;
+}
+
+int lb_moments(lb_ctx *c, void *rho, void *u, int32_t dtype) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (dtype != LB_OUT_F64 && dtype != LB_OUT_F32) return fail(c, LB_EINVAL, "dtype must be LB_OUT_F64 or LB_OUT_F32");
+  if (!rho && !u) return LB_OK;
+  return run_step_kernel(c, WHAT_MOMENTS, rho, u, dtype == LB_OUT_F32);
+}
+
+int lb_wall_stress(lb_ctx *c, double out[2], int32_t reset) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!out) return fail(c, LB_EINVAL, "null output");
+  if (!c->lat.walls) return fail(c, LB_ESTATE, "wall stress needs a channel lattice");
+  double h[4];
+  hipError_t e = hipMemcpyAsync(h, c->d_acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "wall stress readback");
+  if (h[3] > 0.0) c->unstable = true;
+  out[0] = h[2] > 0 ? h[0] / h[2] : 0.0;
+  out[1] = h[2] > 0 ? h[1] / h[2] : 0.0;
+  if (reset) {
+    const double keep[4] = {0.0, 0.0, 0.0, h[3]};
+    e = hipMemcpyAsync(c->d_acc, keep, sizeof(keep), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "wall stress reset");
+  }
+  if (c->unstable) return fail(c, LB_EUNSTABLE, "non-finite or non-positive density detected by the reductions");
+  return LB_OK;
+}
+
+int lb_totals(lb_ctx *c, double mass[2], double momentum[2], double *flow) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!mass || !momentum) return fail(c, LB_EINVAL, "null output");
+  int rc = run_step_kernel(c, WHAT_OBSERVE, nullptr, nullptr, 0);
+  if (rc) return rc;
+  double h[RED_N];
+  hipError_t e = hipMemcpyAsync(h, c->d_totals, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "totals readback");
+  mass[0] = h[RED_MASS0];
+  mass[1] = h[RED_MASS1];
+  momentum[0] = h[RED_PX];
+  momentum[1] = h[RED_PY];
+  if (flow) *flow = h[RED_FLOW];
+  rc = poll_health(c, true);
+  if (rc) return rc;
+  if (h[RED_BAD] > 0.0) {
+    c->unstable = true;
+    return fail(c, LB_EUNSTABLE, "non-finite or non-positive density in the current state");
+  }
+  return LB_OK;
+}
+
+int lb_checkpoint(lb_ctx *c, void *dst) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!dst) return fail(c, LB_EINVAL, "null destination");
+  LayoutArgs la{};
+  la.in = c->pop[c->cur];
+  la.out = dst;
+  la.plane = c->plane;
+  la.lx = c->lat.lx;
+  la.ly = c->lat.ly;
+  la.pitch = c->pitch;
+  la.ns = c->lat.n_species;
+  la.rho_ref[0] = c->psi.rho_ref[0];
+  la.rho_ref[1] = c->psi.rho_ref[1];
+  hipError_t e = launch_checkpoint(c->lat.storage, c->lat.walls, la, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "checkpoint kernel");
+  return LB_OK;
+}
+
+int lb_restore(lb_ctx *c, const void *src) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!src) return fail(c, LB_EINVAL, "null source");
+  // drop any pending health readback: it describes the state being replaced
+  if (c->check_pending) {
+    (void)hipEventSynchronize(c->ev);
+    c->check_pending = false;
+  }
+  LayoutArgs la{};
+  la.in = src;
+  la.out = c->pop[c->cur];
+  la.plane = c->plane;
+  la.lx = c->lat.lx;
+  la.ly = c->lat.ly;
+  la.pitch = c->pitch;
+  la.ns = c->lat.n_species;
+  la.rho_ref[0] = c->psi.rho_ref[0];
+  la.rho_ref[1] = c->psi.rho_ref[1];
+  hipError_t e = launch_restore(c->lat.storage, c->lat.walls, la, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "restore kernel");
+  e = launch_fill(c->d_acc, 0.0, 4, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "restore reset");
+  c->unstable = false;
+  return LB_OK;
+}
+
+int64_t lb_time(const lb_ctx *c) { return c ? c->t : -1; }
+
+int lb_set_tile(lb_ctx *c, int32_t tx, int32_t sy) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (tx != 64 && tx != 128 && tx != 256) return fail(c, LB_EINVAL, "tx must be 64, 128 or 256");
+  if (sy < 1) return fail(c, LB_EINVAL, "sy must be >= 1");
+  if (grid_blocks(c, tx, sy, nullptr) > kMaxBlocks) return fail(c, LB_EINVAL, "too many workgroups");
+  c->tx = tx;
+  c->sy = std::min<int32_t>(sy, c->lat.ly);
+  return LB_OK;
+}
+
+int lb_get_tile(const lb_ctx *c, int32_t *tx, int32_t *sy) {
+  if (!c || !tx || !sy) return LB_EINVAL;
+  *tx = c->tx;
+  *sy = c->sy;
+  return LB_OK;
+}
+
+const char *lb_last_error(const lb_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void lb_destroy(lb_ctx *c) {
+  if (!c) return;
+  if (c->check_pending && c->ev) (void)hipEventSynchronize(c->ev);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->d_partials) (void)hipFree(c->d_partials);
+  if (c->d_totals) (void)hipFree(c->d_totals);
+  if (c->d_acc) (void)hipFree(c->d_acc);
+  if (c->h_acc) (void)hipHostFree(c->h_acc);
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  delete c;
+}
+
+}  // extern "C"

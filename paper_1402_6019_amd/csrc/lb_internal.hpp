@@ -1,0 +1,68 @@
+// Internal declarations shared by the host runtime (lb_api.cpp) and the device kernels
+// (lb_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lb355 {
+
+enum StoreMode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
+
+// What one launch of the fused step kernel does.
+enum StepWhat {
+  WHAT_STEP = 0,         // stream + force + collide, store f*
+  WHAT_STEP_REDUCE = 1,  // same, plus FP64 per-workgroup partial sums
+  WHAT_MOMENTS = 2,      // write rho_s and the half-force velocity, store nothing
+  WHAT_OBSERVE = 3       // partial sums of the current state, store nothing
+};
+
+// Partial-sum slots written per workgroup (and totals after the second pass).
+enum RedSlot {
+  RED_MASS0 = 0, RED_MASS1, RED_PX, RED_PY, RED_WBOT, RED_WTOP, RED_FLOW, RED_BAD, RED_N
+};
+
+// Kernel arguments of the fused step (passed by value through the kernarg segment).
+struct StepArgs {
+  const void *src;      // post-collision populations of the previous step (pull source)
+  void *dst;            // post-collision populations of this step
+  double *partials;     // [gridDim.x][RED_N] when reducing
+  void *out_rho;        // moments: [ns][ly][lx]
+  void *out_u;          // moments: [2][ly][lx]
+  long long plane;      // elements per (species, l) plane = ly * pitch
+  int lx, ly, pitch;    // lattice and row pitch (elements)
+  int sy, nseg;         // rows per workgroup, workgroups per strip
+  int out_f32;          // moments output type
+  int cross_psi;        // A-B term between psi (1) or rho (0)
+  double K[2][5];       // folded shell couplings G_ss,1 w(q) + G_ss,2 p(q)
+  double T[2];          // G_AB t(1), G_AB t(2)
+  double body[2];       // acceleration g
+  double tau[2], omega[2];
+  double psi0, irho0;
+  double rho_w[2], psi_w[2];  // wall ghost rows (channel)
+  double rho_ref[2];          // BF16 deviation reference
+};
+
+// Arguments of the layout kernels (init / checkpoint / restore).
+struct LayoutArgs {
+  const void *in;
+  void *out;
+  long long plane;
+  int lx, ly, pitch, ns;
+  double rho_ref[2];
+};
+
+// Host-side launchers (lb_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nblocks, const StepArgs &a,
+                       hipStream_t st);
+hipError_t launch_reduce(const double *partials, int nblocks, double *totals, double *acc, int accumulate,
+                         double inv_lx, hipStream_t st);
+hipError_t launch_init(int mode, int walls, const LayoutArgs &a, hipStream_t st);
+hipError_t launch_checkpoint(int mode, int walls, const LayoutArgs &a, hipStream_t st);
+hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t st);
+
+hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+
+size_t step_lds_bytes(int mode, int ns, int tx);
+
+}  // namespace lb355

@@ -1,0 +1,667 @@
+// Device kernels of the two-belt pseudopotential D2Q9 lattice Boltzmann step (gfx950).
+//
+// One launch of step_kernel performs one full time step of eq. (LB) for every site:
+//   pull streaming (with halfway bounce-back at channel walls)  ->  moments rho_s, j_s
+//   ->  psi_s = psi0 (1 - exp(-rho_s / rho0))  ->  eq. (FORCE) two-belt force, A-B repulsion,
+//   body force  ->  velocity shift u_eq,s = u' + tau_s F_s / rho_s  ->  BGK collision
+//   ->  store of the post-collision populations (unshifted; the next step pulls them).
+//
+// Layout in HBM: populations as planes [species][l][y][pitch], x fastest (SoA), so every
+// load and store of a wavefront touches 64 consecutive elements of one row.
+//
+// Work decomposition: a workgroup owns a strip of tx columns (one thread per column) and a
+// segment of sy rows, and marches down its rows.  The force at row y needs psi at rows
+// y-2..y+2 and columns x-2..x+2, so the workgroup keeps a six-row ring of psi_s (and rho_s
+// for the A-B term) for its tx + 4 columns in LDS: each iteration computes the leading row
+// r = y + 2 of the ring (the pulled moments of tx + 4 sites), synchronises once, then
+// updates row y from the ring.  Interior columns are computed once per row; only the two
+// halo columns on each side and four extra rows per segment are recomputed by neighbours.
+// Six ring slots make one barrier per row sufficient: the slot written in iteration r+1 is
+// never among the five slots read in iteration r.
+//
+// Workgroups are dispatched round-robin over the eight XCDs; xcd_remap() gives each XCD a
+// contiguous range of (strip, segment) tiles, segments fastest, so the halo rows shared by
+// consecutive segments are re-read from that XCD's own L2.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lb_internal.hpp"
+#include "lb_tables.hpp"
+
+namespace lb355 {
+
+extern __shared__ __attribute__((aligned(16))) unsigned char lb_smem[];
+
+// ---------------------------------------------------------------------------------------
+// Storage codecs
+// ---------------------------------------------------------------------------------------
+
+template <int MODE> struct Codec;
+
+template <> struct Codec<MODE_F64> {
+  using S = double;
+  using R = double;
+  __device__ static R load(const S *p, R) { return *p; }
+  __device__ static void store(S *p, R v, R) { *p = v; }
+  __device__ static R expo(R v) { return exp(v); }
+};
+
+template <> struct Codec<MODE_F32> {
+  using S = float;
+  using R = float;
+  __device__ static R load(const S *p, R) { return *p; }
+  __device__ static void store(S *p, R v, R) { *p = v; }
+  __device__ static R expo(R v) { return __expf(v); }
+};
+
+// BF16 deviation from the rest equilibrium: stored value = bf16(f - W_l rho_ref).
+template <> struct Codec<MODE_BF16> {
+  using S = uint16_t;
+  using R = float;
+  __device__ static R load(const S *p, R wref) { return __uint_as_float(uint32_t(*p) << 16) + wref; }
+  __device__ static void store(S *p, R v, R wref) {
+    uint32_t b = __float_as_uint(v - wref);
+    // round to nearest even; NaN stays NaN
+    uint32_t r = (b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) ? (b | 0x00400000u)
+                                                                         : b + 0x7fffu + ((b >> 16) & 1u);
+    *p = uint16_t(r >> 16);
+  }
+  __device__ static R expo(R v) { return __expf(v); }
+};
+
+template <typename R, int NS>
+struct alignas(sizeof(R) * NS) Vec {
+  R v[NS];
+};
+
+__device__ inline int xcd_remap(int b, int nb) {
+  constexpr int NX = 8;
+  const int q = nb / NX, r = nb % NX;
+  const int xcd = b % NX, k = b / NX;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
+}
+
+__device__ inline int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Pulled populations f_l(x, y) = f*_l(x - c_l, y - c_l) of one species, or the reflected
+// f*_opp(l)(x, y) where (x - c_l, y - c_l) lies in a wall.  xm/xp: wrapped x-1 / x+1;
+// ro_m/ro_0/ro_p: element offsets of rows y-1, y, y+1; bb_lo/bb_hi: row y-1 / y+1 is solid.
+template <class C>
+__device__ inline void pull9(const typename C::S *base, long long plane, int x, int xm, int xp, int ro_m, int ro_0,
+                             int ro_p, bool bb_lo, bool bb_hi, const typename C::R wref[9], typename C::R f[9]) {
+  using S = typename C::S;
+  const S *p0 = base;
+  f[0] = C::load(p0 + ro_0 + x, wref[0]);
+  f[1] = C::load(p0 + 1 * plane + ro_0 + xm, wref[1]);
+  f[3] = C::load(p0 + 3 * plane + ro_0 + xp, wref[3]);
+  if (bb_lo) {  // c_y = +1 populations would come from the wall below: reflect
+    f[2] = C::load(p0 + 4 * plane + ro_0 + x, wref[4]);
+    f[5] = C::load(p0 + 7 * plane + ro_0 + x, wref[7]);
+    f[6] = C::load(p0 + 8 * plane + ro_0 + x, wref[8]);
+  } else {
+    f[2] = C::load(p0 + 2 * plane + ro_m + x, wref[2]);
+    f[5] = C::load(p0 + 5 * plane + ro_m + xm, wref[5]);
+    f[6] = C::load(p0 + 6 * plane + ro_m + xp, wref[6]);
+  }
+  if (bb_hi) {  // c_y = -1 populations would come from the wall above: reflect
+    f[4] = C::load(p0 + 2 * plane + ro_0 + x, wref[2]);
+    f[7] = C::load(p0 + 5 * plane + ro_0 + x, wref[5]);
+    f[8] = C::load(p0 + 6 * plane + ro_0 + x, wref[6]);
+  } else {
+    f[4] = C::load(p0 + 4 * plane + ro_p + x, wref[4]);
+    f[7] = C::load(p0 + 7 * plane + ro_p + xp, wref[7]);
+    f[8] = C::load(p0 + 8 * plane + ro_p + xm, wref[8]);
+  }
+}
+
+template <typename R>
+__device__ inline R sum9(const R f[9]) {
+  R r = f[0];
+#pragma unroll
+  for (int l = 1; l < 9; ++l) r += f[l];
+  return r;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused step
+// ---------------------------------------------------------------------------------------
+
+template <int MODE, int NS, bool WALLS, int WHAT>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
+  using C = Codec<MODE>;
+  using R = typename C::R;
+  using S = typename C::S;
+  using V = Vec<R, NS>;
+  constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_REDUCE);
+  constexpr bool REDUCE = (WHAT == WHAT_STEP_REDUCE || WHAT == WHAT_OBSERVE);
+
+  const int TX = blockDim.x;
+  const int W4 = TX + 4;
+  V *psi_ring = reinterpret_cast<V *>(lb_smem);      // [6][W4]
+  V *rho_ring = psi_ring + 6 * W4;                   // [6][W4] (two species only)
+  __shared__ double red_lds[4][RED_N];
+
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = logical / a.nseg;
+  const int seg = logical - strip * a.nseg;
+  const int lx = a.lx, ly = a.ly, pitch = a.pitch;
+  const long long plane = a.plane;
+  const int x0 = strip * TX;
+  const int w = min(TX, lx - x0);
+  const int yA = seg * a.sy;
+  const int yB = min(yA + a.sy, ly);
+  const int tid = threadIdx.x;
+
+  // Per-species constants in the arithmetic type.
+  R K1[NS], K2[NS], K4[NS], K5[NS], K8[NS], tau[NS], om[NS], wref[NS][9], psiw[NS], rhow[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    K1[s] = R(a.K[s][0]);
+    K2[s] = R(a.K[s][1]);
+    K4[s] = R(2.0 * a.K[s][2]);
+    K5[s] = R(a.K[s][3]);
+    K8[s] = R(2.0 * a.K[s][4]);
+    tau[s] = R(a.tau[s]);
+    om[s] = R(a.omega[s]);
+    psiw[s] = R(a.psi_w[s]);
+    rhow[s] = R(a.rho_w[s]);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) wref[s][l] = MODE == MODE_BF16 ? R(WD2Q9[l] * a.rho_ref[s]) : R(0);
+  }
+  const R T1 = R(a.T[0]), T2 = R(a.T[1]);
+  const R gx = R(a.body[0]), gy = R(a.body[1]);
+  const R psi0 = R(a.psi0), nirho0 = R(-a.irho0);
+  const S *src = static_cast<const S *>(a.src);
+  S *dst = static_cast<S *>(a.dst);
+
+  // Columns handled by this thread: interior column x (stage 2 and ring slot tid + 2).
+  const bool col_ok = tid < w;
+  const int xc = x0 + (col_ok ? tid : 0);
+  const int xcm = wrapi(xc - 1, lx), xcp = wrapi(xc + 1, lx);
+  // Halo slots: threads 0..3 also fill ring slots 0, 1, w+2, w+3 (columns x0-2, x0-1, x0+w, x0+w+1).
+  const bool halo = tid < 4;
+  const int hslot = tid < 2 ? tid : w + tid;
+  const int xh = wrapi(x0 - 2 + hslot, lx);
+  const int xhm = wrapi(xh - 1, lx), xhp = wrapi(xh + 1, lx);
+
+  double acc[RED_N];
+#pragma unroll
+  for (int k = 0; k < RED_N; ++k) acc[k] = 0.0;
+
+  // Stage 1 helper: pulled density and psi at column x of fluid row r -> ring slot.
+  auto lead = [&](V *prow, V *rrow, int slot, int x, int xm, int xp, int ro0, int rom, int rop, bool lo, bool hi) {
+    V ps, rh;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      R f[9];
+      pull9<C>(src + (long long)(s * 9) * plane, plane, x, xm, xp, rom, ro0, rop, lo, hi, wref[s], f);
+      const R r = sum9(f);
+      rh.v[s] = r;
+      ps.v[s] = psi0 * (R(1) - C::expo(r * nirho0));
+    }
+    prow[slot] = ps;
+    if (NS == 2) rrow[slot] = rh;
+  };
+
+  int lead_slot = 0;
+  for (int r = yA - 2; r < yB + 2; ++r, lead_slot = (lead_slot == 5 ? 0 : lead_slot + 1)) {
+    // ---- stage 1: ring row for r -------------------------------------------------------
+    V *prow = psi_ring + lead_slot * W4;
+    V *rrow = rho_ring + lead_slot * W4;
+    const bool ghost = WALLS && (r < 0 || r >= ly);
+    if (ghost) {
+      V ps, rh;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        ps.v[s] = psiw[s];
+        rh.v[s] = rhow[s];
+      }
+      if (col_ok) {
+        prow[tid + 2] = ps;
+        if (NS == 2) rrow[tid + 2] = rh;
+      }
+      if (halo) {
+        prow[hslot] = ps;
+        if (NS == 2) rrow[hslot] = rh;
+      }
+    } else {
+      const int rw = WALLS ? r : wrapi(r, ly);
+      const bool lo = WALLS && rw == 0;
+      const bool hi = WALLS && rw == ly - 1;
+      const int rom = (lo ? rw : wrapi(rw - 1, ly)) * pitch;
+      const int rop = (hi ? rw : wrapi(rw + 1, ly)) * pitch;
+      const int ro0 = rw * pitch;
+      if (col_ok) lead(prow, rrow, tid + 2, xc, xcm, xcp, ro0, rom, rop, lo, hi);
+      if (halo) lead(prow, rrow, hslot, xh, xhm, xhp, ro0, rom, rop, lo, hi);
+    }
+    __syncthreads();
+
+    // ---- stage 2: update row y = r - 2 ---------------------------------------------------
+    const int y = r - 2;
+    if (y < yA || !col_ok) continue;
+
+    const bool lo = WALLS && y == 0;
+    const bool hi = WALLS && y == ly - 1;
+    const int ro0 = y * pitch;
+    const int rom = (lo ? y : wrapi(y - 1, ly)) * pitch;
+    const int rop = (hi ? y : wrapi(y + 1, ly)) * pitch;
+
+    R f[NS][9], rho[NS], jx[NS], jy[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      pull9<C>(src + (long long)(s * 9) * plane, plane, xc, xcm, xcp, rom, ro0, rop, lo, hi, wref[s], f[s]);
+      rho[s] = sum9(f[s]);
+      jx[s] = (f[s][1] + f[s][5] + f[s][8]) - (f[s][3] + f[s][6] + f[s][7]);
+      jy[s] = (f[s][2] + f[s][5] + f[s][6]) - (f[s][4] + f[s][7] + f[s][8]);
+    }
+
+    // ring rows y-2 .. y+2
+    const V *rows[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      int sl = lead_slot + 2 + k;
+      sl = sl >= 6 ? sl - 6 : sl;
+      sl = sl >= 6 ? sl - 6 : sl;
+      rows[k] = psi_ring + sl * W4 + tid + 2;
+    }
+#define PS(dx, dy) (rows[(dy) + 2][(dx)])
+    const V pc = PS(0, 0);
+    const V e1 = PS(1, 0), w1 = PS(-1, 0), n1 = PS(0, 1), s1 = PS(0, -1);
+    const V ne = PS(1, 1), sw = PS(-1, -1), se = PS(1, -1), nw = PS(-1, 1);
+    const V e2 = PS(2, 0), w2 = PS(-2, 0), n2 = PS(0, 2), s2 = PS(0, -2);
+    const V qa = PS(2, 1), qA = PS(-2, -1), qb = PS(2, -1), qB = PS(-2, 1);
+    const V qc = PS(1, 2), qC = PS(-1, -2), qd = PS(1, -2), qD = PS(-1, 2);
+    const V d8a = PS(2, 2), d8A = PS(-2, -2), d8b = PS(2, -2), d8B = PS(-2, 2);
+#undef PS
+    R Fx[NS], Fy[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      // eq. (FORCE) regrouped into antisymmetric pairs over one link of each +-c pair:
+      // sum_l K(q_l) psi(x + c_l) c_l = sum_half K(q) c (psi(x + c) - psi(x - c)).
+      const R dE = e1.v[s] - w1.v[s], dN = n1.v[s] - s1.v[s];
+      const R dd1 = ne.v[s] - sw.v[s], dd2 = se.v[s] - nw.v[s];
+      const R d4x = e2.v[s] - w2.v[s], d4y = n2.v[s] - s2.v[s];
+      const R da = qa.v[s] - qA.v[s], db = qb.v[s] - qB.v[s];
+      const R dc = qc.v[s] - qC.v[s], dd = qd.v[s] - qD.v[s];
+      const R ea = d8a.v[s] - d8A.v[s], eb = d8b.v[s] - d8B.v[s];
+      const R sx = K1[s] * dE + K2[s] * (dd1 + dd2) + K4[s] * d4x + K5[s] * (R(2) * (da + db) + (dc + dd)) +
+                   K8[s] * (ea + eb);
+      const R sy = K1[s] * dN + K2[s] * (dd1 - dd2) + K4[s] * d4y + K5[s] * ((da - db) + R(2) * (dc - dd)) +
+                   K8[s] * (ea - eb);
+      Fx[s] = -pc.v[s] * sx + rho[s] * gx;
+      Fy[s] = -pc.v[s] * sy + rho[s] * gy;
+    }
+    if (NS == 2) {
+      // A-B repulsion over the first belt between the densities (or psi) of both species.
+      const V *xr[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const V *base = a.cross_psi ? psi_ring : rho_ring;
+        int sl = lead_slot + 3 + k;
+        sl = sl >= 6 ? sl - 6 : sl;
+        sl = sl >= 6 ? sl - 6 : sl;
+        xr[k] = base + sl * W4 + tid + 2;
+      }
+#define XR(dx, dy) (xr[(dy) + 1][(dx)])
+      const V c0 = XR(0, 0);
+      const V xe = XR(1, 0), xw = XR(-1, 0), xn = XR(0, 1), xs = XR(0, -1);
+      const V xne = XR(1, 1), xsw = XR(-1, -1), xse = XR(1, -1), xnw = XR(-1, 1);
+#undef XR
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int o = 1 - s;
+        const R t1 = xne.v[o] - xsw.v[o], t2 = xse.v[o] - xnw.v[o];
+        const R cx = T1 * (xe.v[o] - xw.v[o]) + T2 * (t1 + t2);
+        const R cy = T1 * (xn.v[o] - xs.v[o]) + T2 * (t1 - t2);
+        Fx[s] -= c0.v[s] * cx;
+        Fy[s] -= c0.v[s] * cy;
+      }
+    }
+
+    // common velocity u' = sum_s (j_s / tau_s) / sum_s (rho_s / tau_s)
+    R nux = jx[0] * om[0], nuy = jy[0] * om[0], den = rho[0] * om[0];
+#pragma unroll
+    for (int s = 1; s < NS; ++s) {
+      nux += jx[s] * om[s];
+      nuy += jy[s] * om[s];
+      den += rho[s] * om[s];
+    }
+    const R iden = R(1) / den;
+    const R upx = nux * iden, upy = nuy * iden;
+
+    if (WHAT == WHAT_MOMENTS) {
+      R sr = rho[0], mx = jx[0] + R(0.5) * Fx[0], my = jy[0] + R(0.5) * Fy[0];
+#pragma unroll
+      for (int s = 1; s < NS; ++s) {
+        sr += rho[s];
+        mx += jx[s] + R(0.5) * Fx[s];
+        my += jy[s] + R(0.5) * Fy[s];
+      }
+      const size_t site = (size_t)y * lx + xc;
+      const size_t nsite = (size_t)lx * ly;
+      if (a.out_rho) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (a.out_f32) static_cast<float *>(a.out_rho)[s * nsite + site] = float(rho[s]);
+          else static_cast<double *>(a.out_rho)[s * nsite + site] = double(rho[s]);
+        }
+      }
+      if (a.out_u) {
+        const R ux = mx / sr, uy = my / sr;
+        if (a.out_f32) {
+          static_cast<float *>(a.out_u)[site] = float(ux);
+          static_cast<float *>(a.out_u)[nsite + site] = float(uy);
+        } else {
+          static_cast<double *>(a.out_u)[site] = double(ux);
+          static_cast<double *>(a.out_u)[nsite + site] = double(uy);
+        }
+      }
+      continue;
+    }
+
+    double wb = 0.0, wt = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const R ir = R(1) / rho[s];
+      const R ux = upx + tau[s] * Fx[s] * ir;
+      const R uy = upy + tau[s] * Fy[s] * ir;
+      const R base = R(1) - R(1.5) * (ux * ux + uy * uy);
+      const R r9 = rho[s] * R(1.0 / 9.0), r36 = rho[s] * R(1.0 / 36.0);
+      const R o = om[s];
+      R fs[9];
+      // feq_l = W_l rho (1 + 3 cu + 9/2 cu^2 - 3/2 u.u)
+      {
+        const R cu = ux;
+        fs[1] = f[s][1] + o * (r9 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][1]);
+        fs[3] = f[s][3] + o * (r9 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][3]);
+      }
+      {
+        const R cu = uy;
+        fs[2] = f[s][2] + o * (r9 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][2]);
+        fs[4] = f[s][4] + o * (r9 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][4]);
+      }
+      {
+        const R cu = ux + uy;
+        fs[5] = f[s][5] + o * (r36 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][5]);
+        fs[7] = f[s][7] + o * (r36 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][7]);
+      }
+      {
+        const R cu = uy - ux;
+        fs[6] = f[s][6] + o * (r36 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][6]);
+        fs[8] = f[s][8] + o * (r36 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][8]);
+      }
+      // rest population closes the mass balance exactly: f*_0 = rho - sum_{l>0} f*_l
+      fs[0] = rho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
+
+      if (STORE) {
+        S *d = dst + (long long)(s * 9) * plane + ro0 + xc;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) C::store(d + l * plane, fs[l], wref[s][l]);
+      }
+      if (REDUCE && WALLS) {
+        if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7]));
+        if (y == ly - 1) wt += 2.0 * (double(fs[5]) - double(fs[6]));
+      }
+    }
+
+    if (REDUCE) {
+      R sr = rho[0], mx = jx[0] + R(0.5) * Fx[0];
+      bool bad = !(rho[0] > R(0) && rho[0] < R(INFINITY));
+#pragma unroll
+      for (int s = 1; s < NS; ++s) {
+        sr += rho[s];
+        mx += jx[s] + R(0.5) * Fx[s];
+        bad = bad || !(rho[s] > R(0) && rho[s] < R(INFINITY));
+      }
+      acc[RED_MASS0] += double(rho[0]);
+      if (NS == 2) acc[RED_MASS1] += double(rho[NS - 1]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        acc[RED_PX] += double(jx[s]);
+        acc[RED_PY] += double(jy[s]);
+      }
+      acc[RED_WBOT] += wb;
+      acc[RED_WTOP] += wt;
+      acc[RED_FLOW] += double(mx / sr);
+      acc[RED_BAD] += bad ? 1.0 : 0.0;
+    }
+  }
+
+  if (REDUCE) {
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < RED_N; ++k) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) red_lds[wv][k] = v;
+    }
+    __syncthreads();
+    if (tid < RED_N) {
+      double v = 0.0;
+      const int nw = (TX + 63) >> 6;
+      for (int i = 0; i < nw; ++i) v += red_lds[i][tid];
+      a.partials[(size_t)blockIdx.x * RED_N + tid] = v;
+    }
+  }
+}
+
+// Second reduction pass: fixed-order sum of the per-workgroup partials (deterministic).
+__global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int nblocks, double *totals, double *acc,
+                                                     int accumulate, double inv_lx) {
+  __shared__ double sm[256][RED_N];
+  const int tid = threadIdx.x;
+  double v[RED_N];
+#pragma unroll
+  for (int k = 0; k < RED_N; ++k) v[k] = 0.0;
+  for (int b = tid; b < nblocks; b += 256)
+#pragma unroll
+    for (int k = 0; k < RED_N; ++k) v[k] += partials[(size_t)b * RED_N + k];
+#pragma unroll
+  for (int k = 0; k < RED_N; ++k) sm[tid][k] = v[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h)
+#pragma unroll
+      for (int k = 0; k < RED_N; ++k) sm[tid][k] += sm[tid + h][k];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double t[RED_N];
+#pragma unroll
+    for (int k = 0; k < RED_N; ++k) t[k] = sm[0][k];
+    t[RED_WBOT] *= inv_lx;
+    t[RED_WTOP] *= inv_lx;
+    t[RED_FLOW] *= inv_lx;
+#pragma unroll
+    for (int k = 0; k < RED_N; ++k) totals[k] = t[k];
+    if (accumulate) {
+      acc[0] += t[RED_WBOT];
+      acc[1] += t[RED_WTOP];
+      acc[2] += 1.0;
+      acc[3] += t[RED_BAD];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Layout kernels: canonical pre-collision f(t) <-> internal post-collision buffer.
+// Streaming with bounce-back is a permutation of population slots:
+//   f_l(x) = g_l(x - c_l) if x - c_l is fluid, else g_opp(l)(x)
+// and its inverse g_l(z) = f_l(z + c_l) if z + c_l is fluid, else f_opp(l)(z).
+// ---------------------------------------------------------------------------------------
+
+template <int MODE, bool WALLS>
+__global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
+  using C = Codec<MODE>;
+  using S = typename C::S;
+  using R = typename C::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.lx) return;
+  const double *rho = static_cast<const double *>(a.in);
+  S *out = static_cast<S *>(a.out);
+  const size_t nsite = (size_t)a.lx * a.ly;
+  for (int s = 0; s < a.ns; ++s)
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      int zx = x + CXS[l], zy = y + CYS[l];
+      if (WALLS && (zy < 0 || zy >= a.ly)) {
+        zx = x;
+        zy = y;
+      } else {
+        zx = wrapi(zx, a.lx);
+        zy = wrapi(zy, a.ly);
+      }
+      const double v = WD2Q9[l] * rho[s * nsite + (size_t)zy * a.lx + zx];
+      C::store(out + (long long)(s * 9 + l) * a.plane + (long long)y * a.pitch + x, R(v),
+               R(WD2Q9[l] * a.rho_ref[s]));
+    }
+}
+
+template <int MODE, bool WALLS>
+__global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][lx] (FP64)
+  using C = Codec<MODE>;
+  using S = typename C::S;
+  using R = typename C::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.lx) return;
+  const double *f = static_cast<const double *>(a.in);
+  S *out = static_cast<S *>(a.out);
+  const size_t nsite = (size_t)a.lx * a.ly;
+  for (int s = 0; s < a.ns; ++s)
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      int zx = x + CXS[l], zy = y + CYS[l], lsrc = l;
+      if (WALLS && (zy < 0 || zy >= a.ly)) {
+        zx = x;
+        zy = y;
+        lsrc = OPPS[l];
+      } else {
+        zx = wrapi(zx, a.lx);
+        zy = wrapi(zy, a.ly);
+      }
+      const double v = f[(size_t)(s * 9 + lsrc) * nsite + (size_t)zy * a.lx + zx];
+      C::store(out + (long long)(s * 9 + l) * a.plane + (long long)y * a.pitch + x, R(v),
+               R(WD2Q9[l] * a.rho_ref[s]));
+    }
+}
+
+template <int MODE, bool WALLS>
+__global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][ly][lx] (FP64)
+  using C = Codec<MODE>;
+  using S = typename C::S;
+  using R = typename C::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.lx) return;
+  const S *in = static_cast<const S *>(a.in);
+  double *f = static_cast<double *>(a.out);
+  const size_t nsite = (size_t)a.lx * a.ly;
+  for (int s = 0; s < a.ns; ++s)
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      int zx = x - CXS[l], zy = y - CYS[l], lsrc = l;
+      if (WALLS && (zy < 0 || zy >= a.ly)) {
+        zx = x;
+        zy = y;
+        lsrc = OPPS[l];
+      } else {
+        zx = wrapi(zx, a.lx);
+        zy = wrapi(zy, a.ly);
+      }
+      const R v = C::load(in + (long long)(s * 9 + lsrc) * a.plane + (long long)zy * a.pitch + zx,
+                          R(WD2Q9[lsrc] * a.rho_ref[s]));
+      f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] = double(v);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------
+
+size_t step_lds_bytes(int mode, int ns, int tx) {
+  const size_t r = mode == MODE_F64 ? 8 : 4;
+  return 6 * (size_t)(tx + 4) * ns * r * (ns == 2 ? 2 : 1);
+}
+
+template <int MODE, int NS, bool WALLS>
+static hipError_t launch_step_t(int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
+  const size_t lds = step_lds_bytes(MODE, NS, tx);
+  switch (what) {
+    case WHAT_STEP: hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(nb), dim3(tx), lds, st, a); break;
+    case WHAT_STEP_REDUCE:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_MOMENTS:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_MOMENTS>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_OBSERVE:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_OBSERVE>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_step_m(int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
+  if (ns == 1) return walls ? launch_step_t<MODE, 1, true>(what, tx, nb, a, st) : launch_step_t<MODE, 1, false>(what, tx, nb, a, st);
+  return walls ? launch_step_t<MODE, 2, true>(what, tx, nb, a, st) : launch_step_t<MODE, 2, false>(what, tx, nb, a, st);
+}
+
+hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
+  switch (mode) {
+    case MODE_F64: return launch_step_m<MODE_F64>(ns, walls, what, tx, nb, a, st);
+    case MODE_F32: return launch_step_m<MODE_F32>(ns, walls, what, tx, nb, a, st);
+    case MODE_BF16: return launch_step_m<MODE_BF16>(ns, walls, what, tx, nb, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+__global__ void fill_kernel(double *p, double v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(double *p, double v, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partials, int nblocks, double *totals, double *acc, int accumulate,
+                         double inv_lx, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, totals, acc, accumulate, inv_lx);
+  return hipGetLastError();
+}
+
+#define LB_LAYOUT_LAUNCHER(NAME, KERNEL)                                                            \
+  template <int MODE>                                                                              \
+  static hipError_t NAME##_m(int walls, const LayoutArgs &a, hipStream_t st) {                     \
+    const dim3 grid((a.lx + 127) / 128, a.ly), block(128);                                         \
+    if (walls) hipLaunchKernelGGL((KERNEL<MODE, true>), grid, block, 0, st, a);                    \
+    else hipLaunchKernelGGL((KERNEL<MODE, false>), grid, block, 0, st, a);                         \
+    return hipGetLastError();                                                                      \
+  }                                                                                                \
+  hipError_t NAME(int mode, int walls, const LayoutArgs &a, hipStream_t st) {                      \
+    switch (mode) {                                                                                \
+      case MODE_F64: return NAME##_m<MODE_F64>(walls, a, st);                                      \
+      case MODE_F32: return NAME##_m<MODE_F32>(walls, a, st);                                      \
+      case MODE_BF16: return NAME##_m<MODE_BF16>(walls, a, st);                                    \
+    }                                                                                              \
+    return hipErrorInvalidValue;                                                                   \
+  }
+
+LB_LAYOUT_LAUNCHER(launch_init, init_kernel)
+LB_LAYOUT_LAUNCHER(launch_restore, restore_kernel)
+LB_LAYOUT_LAUNCHER(launch_checkpoint, checkpoint_kernel)
+
+#undef LB_LAYOUT_LAUNCHER
+
+}  // namespace lb355

@@ -1,0 +1,100 @@
+"""CPU-side checks of the C ABI library: it loads, exports every symbol that include/lb.h
+declares, its default weights equal the oracle's independently derived isotropic sets, and
+lb_init rejects invalid input before touching the device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1402_6019_amd import _binding
+    return _binding
+
+
+def header_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(lb_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return names
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = B.load()
+    names = header_functions()
+    assert "lb_init" in names and "lb_step" in names and "lb_moments" in names and "lb_wall_stress" in names
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in B.SIGNATURES, f"binding misses {n}"
+
+
+def test_default_weights_match_oracle_derivation(B):
+    from oracle import weights as wt
+    c = B.default_couplings()
+    np.testing.assert_array_equal(list(c.w), wt.as_float_list(wt.weights_w()))
+    np.testing.assert_array_equal(list(c.p), wt.as_float_list(wt.weights_p()))
+    t = wt.weights_t()
+    np.testing.assert_array_equal(list(c.t), [float(t[1]), float(t[2])])
+
+
+@pytest.mark.parametrize("storage,es", [(0, 8), (1, 4), (2, 2)])
+def test_pop_bytes(B, storage, es):
+    for lx, ly, ns in ((5, 5, 1), (64, 7, 2), (1000, 33, 2)):
+        lat = B.LbLattice(lx, ly, ns, 0, storage)
+        pitch = (lx + 63) // 64 * 64
+        assert B.pop_bytes(lat) == ns * 9 * ly * pitch * es
+    assert B.pop_bytes(B.LbLattice(4, 10, 1, 0, storage)) == 0
+    assert B.pop_bytes(B.LbLattice(10, 10, 3, 0, storage)) == 0
+
+
+def _init(B, lat, tau=(1.0, 1.0), rho=None, nbytes=None, psi=(1.0, 1.0)):
+    lib = B.load()
+    cpl = B.default_couplings()
+    t = (ctypes.c_double * 2)(*tau)
+    pp = B.LbPsiParams(psi[0], psi[1], (ctypes.c_double * 2)(0.0, 0.0))
+    if rho is None:
+        rho = np.ones((max(lat.n_species, 1), max(lat.ly, 1), max(lat.lx, 1)))
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    h = ctypes.c_void_p()
+    rc = lib.lb_init(ctypes.byref(h), ctypes.byref(lat), ctypes.byref(cpl), t, ctypes.byref(pp),
+                     rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                     nbytes if nbytes is not None else (1 << 40), None)
+    return rc, lib.lb_last_error(None).decode()
+
+
+def test_init_rejects_invalid_arguments_on_host(B):
+    ok = B.LbLattice(16, 16, 1, 0, 0)
+    assert _init(B, ok, tau=(0.5, 1.0))[0] == B.LB_EINVAL
+    assert "tau" in _init(B, ok, tau=(0.5, 1.0))[1]
+    assert _init(B, B.LbLattice(4, 16, 1, 0, 0))[0] == B.LB_EINVAL
+    assert _init(B, B.LbLattice(16, 16, 3, 0, 0))[0] == B.LB_EINVAL
+    assert _init(B, B.LbLattice(16, 16, 1, 2, 0))[0] == B.LB_EINVAL
+    assert _init(B, B.LbLattice(16, 16, 1, 0, 7))[0] == B.LB_EINVAL
+    assert _init(B, B.LbLattice(16, 70000, 1, 0, 0))[0] == B.LB_EINVAL
+    bad = np.ones((1, 16, 16))
+    bad[0, 3, 4] = 0.0
+    assert _init(B, ok, rho=bad)[0] == B.LB_EINVAL
+    bad[0, 3, 4] = np.nan
+    assert _init(B, ok, rho=bad)[0] == B.LB_EINVAL
+    assert _init(B, ok, psi=(1.0, 0.0))[0] == B.LB_EINVAL
+    assert _init(B, ok, nbytes=100)[0] == B.LB_ENOMEM
+
+
+def test_product_package_does_not_reach_the_oracle():
+    """The product package imports nothing from oracle/ (and fails loudly without its library)."""
+    pkg = os.path.join(ROOT, "paper_1402_6019_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text and "lb_oracle" not in text, f
