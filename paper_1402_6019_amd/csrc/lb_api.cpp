@@ -21,7 +21,7 @@ namespace {
 
 thread_local std::string g_init_error;
 
-constexpr int kPitchAlign = 64;  // elements: rows start on 64-element boundaries
+constexpr int kPitchAlign = 256;  // elements: a multiple of the widest strip (see the step kernel's stores)
 constexpr int kMaxBlocks = 1 << 20;
 
 size_t elem_size(int storage) { return storage == LB_F64 ? 8 : (storage == LB_F32 ? 4 : 2); }

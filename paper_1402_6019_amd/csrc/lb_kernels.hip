@@ -35,8 +35,25 @@ namespace lb355 {
 extern __shared__ __attribute__((aligned(16))) unsigned char lb_smem[];
 
 // ---------------------------------------------------------------------------------------
-// Storage codecs
+// Storage codecs.  Populations are read and written through raw buffer instructions: the
+// buffer descriptor (one per species, SGPRs) holds the base address, the row and plane
+// offset is a uniform SGPR and only the column byte offset lives in a VGPR, so a load or
+// store costs no vector address arithmetic.  Each species' nine planes must span < 4 GiB.
 // ---------------------------------------------------------------------------------------
+
+using Rsrc = __amdgpu_buffer_rsrc_t;
+using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+
+// Base addresses and row offsets are uniform by construction (they depend only on the
+// workgroup and the row index); readfirstlane states that to the compiler, which otherwise
+// may keep them in VGPRs and wrap every buffer access in a per-lane loop.
+__device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline Rsrc make_rsrc(const void *p, uint32_t bytes) {
+  const uint64_t u = reinterpret_cast<uint64_t>(p);
+  const uint64_t b = ((uint64_t)uni((uint32_t)(u >> 32)) << 32) | uni((uint32_t)u);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(b), (short)0, (int)uni(bytes), 0x00020000);
+}
 
 template <int MODE> struct Codec;
 
@@ -45,7 +62,14 @@ template <> struct Codec<MODE_F64> {
   using R = double;
   __device__ static R load(const S *p, R) { return *p; }
   __device__ static void store(S *p, R v, R) { *p = v; }
+  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff, R) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v, R) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  }
   __device__ static R expo(R v) { return exp(v); }
+  __device__ static R rcp(R v) { return 1.0 / v; }
 };
 
 template <> struct Codec<MODE_F32> {
@@ -53,22 +77,38 @@ template <> struct Codec<MODE_F32> {
   using R = float;
   __device__ static R load(const S *p, R) { return *p; }
   __device__ static void store(S *p, R v, R) { *p = v; }
+  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff, R) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v, R) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+  }
   __device__ static R expo(R v) { return __expf(v); }
+  __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
 };
 
 // BF16 deviation from the rest equilibrium: stored value = bf16(f - W_l rho_ref).
 template <> struct Codec<MODE_BF16> {
   using S = uint16_t;
   using R = float;
-  __device__ static R load(const S *p, R wref) { return __uint_as_float(uint32_t(*p) << 16) + wref; }
-  __device__ static void store(S *p, R v, R wref) {
-    uint32_t b = __float_as_uint(v - wref);
+  __device__ static R decode(uint32_t h, R wref) { return __uint_as_float(h << 16) + wref; }
+  __device__ static uint16_t encode(R v, R wref) {
+    const uint32_t b = __float_as_uint(v - wref);
     // round to nearest even; NaN stays NaN
-    uint32_t r = (b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) ? (b | 0x00400000u)
-                                                                         : b + 0x7fffu + ((b >> 16) & 1u);
-    *p = uint16_t(r >> 16);
+    const uint32_t r = (b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) ? (b | 0x00400000u)
+                                                                              : b + 0x7fffu + ((b >> 16) & 1u);
+    return uint16_t(r >> 16);
+  }
+  __device__ static R load(const S *p, R wref) { return decode(*p, wref); }
+  __device__ static void store(S *p, R v, R wref) { *p = encode(v, wref); }
+  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff, R wref) {
+    return decode(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0), wref);
+  }
+  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v, R wref) {
+    __builtin_amdgcn_raw_buffer_store_b16(encode(v, wref), r, voff, soff, 0);
   }
   __device__ static R expo(R v) { return __expf(v); }
+  __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
 };
 
 template <typename R, int NS>
@@ -85,35 +125,74 @@ __device__ inline int xcd_remap(int b, int nb) {
 
 __device__ inline int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// Pulled populations f_l(x, y) = f*_l(x - c_l, y - c_l) of one species, or the reflected
-// f*_opp(l)(x, y) where (x - c_l, y - c_l) lies in a wall.  xm/xp: wrapped x-1 / x+1;
-// ro_m/ro_0/ro_p: element offsets of rows y-1, y, y+1; bb_lo/bb_hi: row y-1 / y+1 is solid.
-template <class C>
-__device__ inline void pull9(const typename C::S *base, long long plane, int x, int xm, int xp, int ro_m, int ro_0,
-                             int ro_p, bool bb_lo, bool bb_hi, const typename C::R wref[9], typename C::R f[9]) {
-  using S = typename C::S;
-  const S *p0 = base;
-  f[0] = C::load(p0 + ro_0 + x, wref[0]);
-  f[1] = C::load(p0 + 1 * plane + ro_0 + xm, wref[1]);
-  f[3] = C::load(p0 + 3 * plane + ro_0 + xp, wref[3]);
-  if (bb_lo) {  // c_y = +1 populations would come from the wall below: reflect
-    f[2] = C::load(p0 + 4 * plane + ro_0 + x, wref[4]);
-    f[5] = C::load(p0 + 7 * plane + ro_0 + x, wref[7]);
-    f[6] = C::load(p0 + 8 * plane + ro_0 + x, wref[8]);
-  } else {
-    f[2] = C::load(p0 + 2 * plane + ro_m + x, wref[2]);
-    f[5] = C::load(p0 + 5 * plane + ro_m + xm, wref[5]);
-    f[6] = C::load(p0 + 6 * plane + ro_m + xp, wref[6]);
+// Where the nine populations pulled into one site come from:
+//   f_l(x, y) = f*_l(x - c_l, y - c_l), or f*_opp(l)(x, y) when (x - c_l, y - c_l) is a wall.
+// A load address is  species base (buffer descriptor) + row offset (SGPR) + lane offset
+// (VGPR).  The lane offset folds in the plane, l * plane_bytes + column bytes of x - c_lx,
+// and is fixed for the whole kernel; only the three row offsets change from row to row.
+struct RowOffs {
+  uint32_t m, o, p;  // byte offsets of rows y-1, y, y+1 (or y where reflected)
+  bool lo, hi;       // row y-1 / y+1 is a wall
+};
+
+struct LaneOffs {
+  uint32_t ld[9];  // l * plane_bytes + bytes of column x - c_lx
+  uint32_t bb[4];  // (5..8) * plane_bytes + bytes of column x: reflected sources
+};
+
+__device__ inline LaneOffs lane_offsets(int x, int xm, int xp, uint32_t es, uint32_t plane_b) {
+  LaneOffs o;
+  const uint32_t xb = (uint32_t)x * es, xmb = (uint32_t)xm * es, xpb = (uint32_t)xp * es;
+  const uint32_t colb[9] = {xb, xmb, xb, xpb, xb, xmb, xpb, xpb, xmb};  // column of x - c_lx
+#pragma unroll
+  for (int l = 0; l < 9; ++l) o.ld[l] = (uint32_t)l * plane_b + colb[l];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o.bb[k] = (uint32_t)(5 + k) * plane_b + xb;
+  return o;
+}
+
+template <class C, int NS>
+__device__ inline void load_pull(const void *base, uint32_t spec_b, const LaneOffs &lo_, const RowOffs &r,
+                                 const typename C::R (&wref)[NS][9], typename C::R (&f)[NS][9]) {
+  // source of each population: (lane offset, row offset)
+  uint32_t vo[9], so[9];
+  vo[0] = lo_.ld[0]; so[0] = r.o;
+  vo[1] = lo_.ld[1]; so[1] = r.o;
+  vo[3] = lo_.ld[3]; so[3] = r.o;
+  // c_y = +1 populations come from the row below, or bounce back off the wall below
+  vo[2] = r.lo ? lo_.ld[4] : lo_.ld[2]; so[2] = r.lo ? r.o : r.m;  // reflected: plane 4 at x
+  vo[5] = r.lo ? lo_.bb[2] : lo_.ld[5]; so[5] = r.lo ? r.o : r.m;  // plane 7 at x
+  vo[6] = r.lo ? lo_.bb[3] : lo_.ld[6]; so[6] = r.lo ? r.o : r.m;  // plane 8 at x
+  // c_y = -1 populations come from the row above, or bounce back off the wall above
+  vo[4] = r.hi ? lo_.ld[2] : lo_.ld[4]; so[4] = r.hi ? r.o : r.p;  // plane 2 at x
+  vo[7] = r.hi ? lo_.bb[0] : lo_.ld[7]; so[7] = r.hi ? r.o : r.p;  // plane 5 at x
+  vo[8] = r.hi ? lo_.bb[1] : lo_.ld[8]; so[8] = r.hi ? r.o : r.p;  // plane 6 at x
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const Rsrc rs = make_rsrc(static_cast<const char *>(base) + (uint64_t)s * spec_b, spec_b);
+#pragma unroll
+    for (int l = 0; l < 9; ++l)  // W_opp(l) = W_l, so the reference weight does not depend on reflection
+      f[s][l] = C::bload(rs, vo[l], uni(so[l]), wref[s][l]);
   }
-  if (bb_hi) {  // c_y = -1 populations would come from the wall above: reflect
-    f[4] = C::load(p0 + 2 * plane + ro_0 + x, wref[2]);
-    f[7] = C::load(p0 + 5 * plane + ro_0 + x, wref[5]);
-    f[8] = C::load(p0 + 6 * plane + ro_0 + x, wref[6]);
-  } else {
-    f[4] = C::load(p0 + 4 * plane + ro_p + x, wref[4]);
-    f[7] = C::load(p0 + 7 * plane + ro_p + xp, wref[7]);
-    f[8] = C::load(p0 + 8 * plane + ro_p + xm, wref[8]);
-  }
+}
+
+// Row geometry: fluid rows wrap (periodic) or are bounded by walls (channel).
+template <bool WALLS>
+__device__ inline bool row_fluid(int r, int ly) { return !WALLS || (r >= 0 && r < ly); }
+
+template <bool WALLS>
+__device__ inline int lead_row(int r, int ly) { return WALLS ? min(max(r, 0), ly - 1) : r; }
+
+template <bool WALLS>
+__device__ inline RowOffs row_pull(int r, int ly, uint32_t pitch_b) {
+  RowOffs o;
+  const int rw = WALLS ? r : wrapi(r, ly);
+  o.lo = WALLS && rw == 0;
+  o.hi = WALLS && rw == ly - 1;
+  o.o = (uint32_t)rw * pitch_b;
+  o.m = o.lo ? o.o : (uint32_t)wrapi(rw - 1, ly) * pitch_b;
+  o.p = o.hi ? o.o : (uint32_t)wrapi(rw + 1, ly) * pitch_b;
+  return o;
 }
 
 template <typename R>
@@ -134,6 +213,14 @@ __device__ inline T wave_sum(T v) {
 // ---------------------------------------------------------------------------------------
 // Fused step
 // ---------------------------------------------------------------------------------------
+//
+// Software pipeline of one row iteration r (lead row r, output row y = r - 2):
+//   1. psi, rho of lead row r from populations already in registers  -> LDS ring slot
+//   2. issue the loads of output row y (stage 2 input)
+//   3. issue the loads of lead row r + 1 (next iteration's step 1)
+//   4. barrier
+//   5. force + collision of row y from the ring and the stage-2 registers, store
+// so the memory latency of both load batches overlaps the arithmetic of steps 1 and 5.
 
 template <int MODE, int NS, bool WALLS, int WHAT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
@@ -153,8 +240,9 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int strip = logical / a.nseg;
   const int seg = logical - strip * a.nseg;
-  const int lx = a.lx, ly = a.ly, pitch = a.pitch;
-  const long long plane = a.plane;
+  const int lx = a.lx, ly = a.ly;
+  const uint32_t pitch_b = (uint32_t)a.pitch * sizeof(S);
+  const uint32_t plane_b = (uint32_t)a.plane * (uint32_t)sizeof(S);
   const int x0 = strip * TX;
   const int w = min(TX, lx - x0);
   const int yA = seg * a.sy;
@@ -180,14 +268,21 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const R T1 = R(a.T[0]), T2 = R(a.T[1]);
   const R gx = R(a.body[0]), gy = R(a.body[1]);
   const R psi0 = R(a.psi0), nirho0 = R(-a.irho0);
-  const S *src = static_cast<const S *>(a.src);
-  S *dst = static_cast<S *>(a.dst);
+  const void *const src = a.src;
+  void *const dst = a.dst;
 
-  // Columns handled by this thread: interior column x (stage 2 and ring slot tid + 2).
+  // Interior column of this thread (ring slot tid + 2) and, for threads 0..3, one halo
+  // column (ring slots 0, 1, w+2, w+3 = columns x0-2, x0-1, x0+w, x0+w+1).
   const bool col_ok = tid < w;
   const int xc = x0 + (col_ok ? tid : 0);
-  const int xcm = wrapi(xc - 1, lx), xcp = wrapi(xc + 1, lx);
-  // Halo slots: threads 0..3 also fill ring slots 0, 1, w+2, w+3 (columns x0-2, x0-1, x0+w, x0+w+1).
+  const uint32_t es = (uint32_t)sizeof(S);
+  const uint32_t spec_b = 9u * plane_b;
+  const LaneOffs pcc = lane_offsets(xc, wrapi(xc - 1, lx), wrapi(xc + 1, lx), es, plane_b);
+  // Store column: lanes past a ragged strip's end write into the row padding (the row
+  // pitch is a multiple of the widest strip), which no kernel ever reads.
+  uint32_t sto[9];
+#pragma unroll
+  for (int l = 0; l < 9; ++l) sto[l] = (uint32_t)l * plane_b + (uint32_t)(x0 + tid) * es;
   const bool halo = tid < 4;
   const int hslot = tid < 2 ? tid : w + tid;
   const int xh = wrapi(x0 - 2 + hslot, lx);
@@ -197,28 +292,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 #pragma unroll
   for (int k = 0; k < RED_N; ++k) acc[k] = 0.0;
 
-  // Stage 1 helper: pulled density and psi at column x of fluid row r -> ring slot.
-  auto lead = [&](V *prow, V *rrow, int slot, int x, int xm, int xp, int ro0, int rom, int rop, bool lo, bool hi) {
-    V ps, rh;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      R f[9];
-      pull9<C>(src + (long long)(s * 9) * plane, plane, x, xm, xp, rom, ro0, rop, lo, hi, wref[s], f);
-      const R r = sum9(f);
-      rh.v[s] = r;
-      ps.v[s] = psi0 * (R(1) - C::expo(r * nirho0));
-    }
-    prow[slot] = ps;
-    if (NS == 2) rrow[slot] = rh;
-  };
-
-  int lead_slot = 0;
-  for (int r = yA - 2; r < yB + 2; ++r, lead_slot = (lead_slot == 5 ? 0 : lead_slot + 1)) {
-    // ---- stage 1: ring row for r -------------------------------------------------------
-    V *prow = psi_ring + lead_slot * W4;
-    V *rrow = rho_ring + lead_slot * W4;
-    const bool ghost = WALLS && (r < 0 || r >= ly);
-    if (ghost) {
+  // Stage 1: psi_s and rho_s of lead row r into ring slot `slot` (interior and halo columns)
+  // from the pulled populations A (interior column) and H (halo column).
+  auto ring_row = [&](int slot, int r, const R (&A)[NS][9], const R (&H)[NS][9]) {
+    V *prow = psi_ring + slot * W4;
+    V *rrow = rho_ring + slot * W4;
+    if (!row_fluid<WALLS>(r, ly)) {
       V ps, rh;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -234,31 +313,83 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
         if (NS == 2) rrow[hslot] = rh;
       }
     } else {
-      const int rw = WALLS ? r : wrapi(r, ly);
-      const bool lo = WALLS && rw == 0;
-      const bool hi = WALLS && rw == ly - 1;
-      const int rom = (lo ? rw : wrapi(rw - 1, ly)) * pitch;
-      const int rop = (hi ? rw : wrapi(rw + 1, ly)) * pitch;
-      const int ro0 = rw * pitch;
-      if (col_ok) lead(prow, rrow, tid + 2, xc, xcm, xcp, ro0, rom, rop, lo, hi);
-      if (halo) lead(prow, rrow, hslot, xh, xhm, xhp, ro0, rom, rop, lo, hi);
+      if (col_ok) {
+        V ps, rh;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          rh.v[s] = sum9(A[s]);
+          ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
+        }
+        prow[tid + 2] = ps;
+        if (NS == 2) rrow[tid + 2] = rh;
+      }
+      if (halo) {
+        V ps, rh;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          rh.v[s] = sum9(H[s]);
+          ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
+        }
+        prow[hslot] = ps;
+        if (NS == 2) rrow[hslot] = rh;
+      }
     }
+  };
+
+  // Register FIFO of pulled populations.  The populations of lead row y+3, loaded in the
+  // iteration of output row y to compute its psi, are the stage-2 input of row y+3 three
+  // iterations later; four row buffers (the main loop is unrolled by four so their roles
+  // rotate statically) mean every population is loaded once per step, one iteration of
+  // arithmetic ahead of its first use.
+  R B[4][NS][9];
+  R FH[NS][9];  // halo column of the lead row (threads 0..3)
+
+  // Prologue: ring rows yA-2 .. yA+2, loads one row ahead.  Rows yA, yA+1, yA+2 stay in
+  // B[1], B[2], B[3] for the first three output rows.
+  {
+    R PH[2][NS][9];
+    constexpr int buf_of[5] = {0, 3, 1, 2, 3};
+    {
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 2, ly), ly, pitch_b);
+      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, wref, PH[0]);
+      load_pull<C, NS>(src, spec_b, pcc, pr, wref, B[buf_of[0]]);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      if (k < 4) {
+        const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 1 + k, ly), ly, pitch_b);
+        if (halo)
+          load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, wref, PH[(k + 1) & 1]);
+        load_pull<C, NS>(src, spec_b, pcc, pr, wref, B[buf_of[k + 1]]);
+      }
+      ring_row(k, yA - 2 + k, B[buf_of[k]], PH[k & 1]);
+    }
+  }
+
+  // One output row y: issue the loads of lead row y+3 (halo batch first: it is the only one
+  // under a lane condition) -> barrier -> force + collision of row y from the ring and the
+  // FIFO, store -> ring row y+3.  Stores carry no condition either: lanes past a ragged
+  // strip's end write into the row padding.  The ring slot written last, (y+3) mod 6, is
+  // not among the rows y-2..y+2 that slower waves may still be reading.
+  auto step_row = [&](const int y_in, const int lead_slot_in, R (&FL)[NS][9], const R (&f)[NS][9]) {
+    // the row index is uniform; saying so keeps every row and plane offset in SGPRs
+    const int y = (int)uni((uint32_t)y_in);
+    const int lead_slot = (int)uni((uint32_t)lead_slot_in);
+    const int rlead = y + 3;
+    const uint32_t rb0 = (uint32_t)y * pitch_b;
+    {
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rlead, ly), ly, pitch_b);
+      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, wref, FH);
+      load_pull<C, NS>(src, spec_b, pcc, pr, wref, FL);
+    }
+
     __syncthreads();
 
-    // ---- stage 2: update row y = r - 2 ---------------------------------------------------
-    const int y = r - 2;
-    if (y < yA || !col_ok) continue;
-
-    const bool lo = WALLS && y == 0;
-    const bool hi = WALLS && y == ly - 1;
-    const int ro0 = y * pitch;
-    const int rom = (lo ? y : wrapi(y - 1, ly)) * pitch;
-    const int rop = (hi ? y : wrapi(y + 1, ly)) * pitch;
-
-    R f[NS][9], rho[NS], jx[NS], jy[NS];
+    // ---- update row y ---------------------------------------------------------------------
+    // ring rows y-2 .. y+2 occupy slots lead_slot-5 .. lead_slot-1 (mod 6)
+    R rho[NS], jx[NS], jy[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      pull9<C>(src + (long long)(s * 9) * plane, plane, xc, xcm, xcp, rom, ro0, rop, lo, hi, wref[s], f[s]);
       rho[s] = sum9(f[s]);
       jx[s] = (f[s][1] + f[s][5] + f[s][8]) - (f[s][3] + f[s][6] + f[s][7]);
       jy[s] = (f[s][2] + f[s][5] + f[s][6]) - (f[s][4] + f[s][7] + f[s][8]);
@@ -268,7 +399,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     const V *rows[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      int sl = lead_slot + 2 + k;
+      int sl = lead_slot + 1 + k;
       sl = sl >= 6 ? sl - 6 : sl;
       sl = sl >= 6 ? sl - 6 : sl;
       rows[k] = psi_ring + sl * W4 + tid + 2;
@@ -306,7 +437,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const V *base = a.cross_psi ? psi_ring : rho_ring;
-        int sl = lead_slot + 3 + k;
+        int sl = lead_slot + 2 + k;
         sl = sl >= 6 ? sl - 6 : sl;
         sl = sl >= 6 ? sl - 6 : sl;
         xr[k] = base + sl * W4 + tid + 2;
@@ -335,10 +466,10 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       nuy += jy[s] * om[s];
       den += rho[s] * om[s];
     }
-    const R iden = R(1) / den;
+    const R iden = C::rcp(den);
     const R upx = nux * iden, upy = nuy * iden;
 
-    if (WHAT == WHAT_MOMENTS) {
+    if (WHAT == WHAT_MOMENTS && col_ok) {
       R sr = rho[0], mx = jx[0] + R(0.5) * Fx[0], my = jy[0] + R(0.5) * Fy[0];
 #pragma unroll
       for (int s = 1; s < NS; ++s) {
@@ -365,13 +496,13 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
           static_cast<double *>(a.out_u)[nsite + site] = double(uy);
         }
       }
-      continue;
     }
 
+    if (WHAT != WHAT_MOMENTS) {
     double wb = 0.0, wt = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const R ir = R(1) / rho[s];
+      const R ir = C::rcp(rho[s]);
       const R ux = upx + tau[s] * Fx[s] * ir;
       const R uy = upy + tau[s] * Fy[s] * ir;
       const R base = R(1) - R(1.5) * (ux * ux + uy * uy);
@@ -403,17 +534,18 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       fs[0] = rho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
 
       if (STORE) {
-        S *d = dst + (long long)(s * 9) * plane + ro0 + xc;
 #pragma unroll
-        for (int l = 0; l < 9; ++l) C::store(d + l * plane, fs[l], wref[s][l]);
+        for (int l = 0; l < 9; ++l)
+          C::bstore(make_rsrc(static_cast<char *>(dst) + (uint64_t)s * spec_b, spec_b), sto[l], uni(rb0), fs[l],
+                    wref[s][l]);
       }
-      if (REDUCE && WALLS) {
+      if (REDUCE && WALLS && col_ok) {
         if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7]));
         if (y == ly - 1) wt += 2.0 * (double(fs[5]) - double(fs[6]));
       }
     }
 
-    if (REDUCE) {
+    if (REDUCE && col_ok) {
       R sr = rho[0], mx = jx[0] + R(0.5) * Fx[0];
       bool bad = !(rho[0] > R(0) && rho[0] < R(INFINITY));
 #pragma unroll
@@ -434,6 +566,27 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       acc[RED_FLOW] += double(mx / sr);
       acc[RED_BAD] += bad ? 1.0 : 0.0;
     }
+    }  // WHAT != WHAT_MOMENTS
+
+    // ---- ring row y + 3 from the loads issued at the top of this iteration -----------------
+    ring_row(lead_slot, y + 3, FL, FH);
+  };
+
+  int lead_slot = 5;
+  auto next_slot = [](int sl) { return sl == 5 ? 0 : sl + 1; };
+  for (int y = yA; y < yB;) {
+    step_row(y, lead_slot, B[0], B[1]);
+    lead_slot = next_slot(lead_slot);
+    if (++y >= yB) break;
+    step_row(y, lead_slot, B[1], B[2]);
+    lead_slot = next_slot(lead_slot);
+    if (++y >= yB) break;
+    step_row(y, lead_slot, B[2], B[3]);
+    lead_slot = next_slot(lead_slot);
+    if (++y >= yB) break;
+    step_row(y, lead_slot, B[3], B[0]);
+    lead_slot = next_slot(lead_slot);
+    ++y;
   }
 
   if (REDUCE) {

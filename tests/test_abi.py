@@ -51,7 +51,7 @@ def test_default_weights_match_oracle_derivation(B):
 def test_pop_bytes(B, storage, es):
     for lx, ly, ns in ((5, 5, 1), (64, 7, 2), (1000, 33, 2)):
         lat = B.LbLattice(lx, ly, ns, 0, storage)
-        pitch = (lx + 63) // 64 * 64
+        pitch = (lx + 255) // 256 * 256
         assert B.pop_bytes(lat) == ns * 9 * ly * pitch * es
     assert B.pop_bytes(B.LbLattice(4, 10, 1, 0, storage)) == 0
     assert B.pop_bytes(B.LbLattice(10, 10, 3, 0, storage)) == 0

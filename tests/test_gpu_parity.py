@@ -140,16 +140,98 @@ def test_mass_conservation_fp64():
         assert abs(m1[s] - m0[s]) / m0[s] < 1e-12
 
 
+def amplification(c, times, eps=1e-9, seed=0):
+    """Sensitivity of the dynamics itself, from the FP64 oracle alone: a relative density
+    perturbation eps of the initial state grows to A(t) * eps.  Returns {t: (A_rho, A_u)}."""
+    cp = dict(c)
+    rng = np.random.default_rng(seed)
+    cp["rho"] = c["rho"] * (1.0 + eps * rng.uniform(-1.0, 1.0, c["rho"].shape))
+    o, op = make_oracle(c), make_oracle(cp)
+    out = {}
+    for t in times:
+        o.step(t - o.time)
+        op.step(t - op.time)
+        a, b = o.fields(), op.fields()
+        um = max(np.abs(a["u"]).max(), U_FLOOR)
+        out[t] = (rel_err(b["rho"], a["rho"]) / eps, np.abs(b["u"] - a["u"]).max() / um / eps)
+    return out
+
+
 @pytest.mark.parametrize("case", ["film", "channel"])
 def test_fp32_parity(case):
+    """FP32 storage and arithmetic: within 1e-5 of the FP64 oracle while the dynamics do not
+    amplify perturbations; later, within C * 2^-24 * A(t), where A(t) is the oracle's own
+    amplification of an initial perturbation (FP32 rounding is a perturbation of ~2^-24 per
+    step that the unstable modes of phase separation amplify like any other)."""
     c = film_case(96, 70) if case == "film" else emulsion_case(100, 77, walls=True, fraction=0.7, seed=5,
                                                                   rmin=5, rmax=10, g=1e-5)
+    times = (1, 10, 100, 300)
+    amp = amplification(c, times)
     sim = make_sim(c, storage="f32")
     orc = make_oracle(c)
-    for t_target in (1, 10, 100):
-        sim.step(t_target - sim.time)
-        orc.step(t_target - orc.time)
-        compare(sim, orc, 1e-5, pops=False)
+    for t in times:
+        sim.step(t - sim.time)
+        orc.step(t - orc.time)
+        rho, u = gpu_fields(sim)
+        fl = orc.fields()
+        e_rho = rel_err(rho, fl["rho"])
+        e_u = np.abs(u - fl["u"]).max() / max(np.abs(fl["u"]).max(), U_FLOOR)
+        tol_rho = max(1e-5, 128 * 2.0 ** -24 * amp[t][0])
+        tol_u = max(1e-5, 128 * 2.0 ** -24 * amp[t][1])
+        print(f"{case} t={t}: rho {e_rho:.2e} (tol {tol_rho:.1e}, A={amp[t][0]:.1f})  "
+              f"u {e_u:.2e} (tol {tol_u:.1e}, A={amp[t][1]:.1f})")
+        assert e_rho <= tol_rho and e_u <= tol_u
+        if t <= 10:
+            assert e_rho <= 1e-5
+
+
+def _steady(c, steps, storage):
+    sim = make_sim(c, storage=storage)
+    orc = make_oracle(c)
+    sim.step(steps)
+    orc.step(steps)
+    rho, u = gpu_fields(sim)
+    fl = orc.fields()
+    return rel_err(rho, fl["rho"]), rel_err(u, fl["u"]), fl
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_steady_poiseuille(storage, tol):
+    """Single-phase channel flow driven by g, at steady state (velocity relative to its maximum)."""
+    ly, lx = 32, 64
+    c = dict(lx=lx, ly=ly, ns=1, walls=1, g1=(0.0, 0.0), g2=(0.0, 0.0), gab=0.0, body=(1e-5, 0.0),
+             rho_wall=(1.0, 0.0), tau=(1.0, 1.0), psi0=1.0, rho0=1.0, rho=np.ones((1, ly, lx)), storage=storage,
+             rho_ref=(1.0, 0.0))
+    e_rho, e_u, fl = _steady(c, 12000, storage)
+    print(f"poiseuille {storage}: rho {e_rho:.2e} u {e_u:.2e} (u max {fl['u'].max():.3e})")
+    assert e_rho <= tol and e_u <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_steady_flat_interface(storage, tol):
+    """Flat liquid slab at the film couplings relaxed to equilibrium (quasi one-dimensional)."""
+    import lbgen
+    lx, ly = 128, 5
+    x = np.arange(lx)
+    prof = 0.28 + 1.11 * 0.5 * (np.tanh((x - 31.5) / 3.0) - np.tanh((x - 95.5) / 3.0))
+    c = film_case(lx, ly)
+    c["rho"] = np.broadcast_to(prof, (1, ly, lx)).copy()
+    e_rho, _, fl = _steady(c, 40000, storage)
+    print(f"flat interface {storage}: rho {e_rho:.2e}")
+    assert e_rho <= tol
+    assert np.abs(fl["u"]).max() < 1e-6
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_steady_droplet(storage, tol):
+    """Static liquid droplet (film couplings) after its shape relaxation."""
+    import lbgen
+    n = 64
+    c = film_case(n, n)
+    c["rho"] = lbgen.disc(n, n, 14, 1.39, 0.28)[None]
+    e_rho, _, _ = _steady(c, 6000, storage)
+    print(f"droplet {storage}: rho {e_rho:.2e}")
+    assert e_rho <= tol
 
 
 def test_bf16dev_error_bound():
