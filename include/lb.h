@@ -61,8 +61,8 @@ enum lb_status {
 /* Storage of the populations in HBM. */
 enum lb_storage {
   LB_F64 = 0,     /* FP64 populations, FP64 arithmetic */
-  LB_F32 = 1,     /* FP32 populations, FP32 arithmetic */
-  LB_BF16DEV = 2  /* BF16 deviations f_l - W_l rho_ref[s] from the rest equilibrium, FP32 arithmetic */
+  LB_F32 = 1,     /* FP32 deviations f_l - W_l rho_ref[s] (see lb_psi_params), FP32 arithmetic */
+  LB_BF16DEV = 2  /* BF16 deviations f_l - W_l rho_ref[s], FP32 arithmetic */
 };
 
 /* Output type of lb_moments. */
@@ -96,7 +96,10 @@ typedef struct {
 
 typedef struct {
   double psi0, rho0;   /* psi(rho) = psi0 (1 - exp(-rho / rho0)) */
-  double rho_ref[2];   /* LB_BF16DEV only: reference density per species for the stored deviations */
+  double rho_ref[2];   /* LB_F32 / LB_BF16DEV: populations are stored as deviations f_l - W_l rho_ref[s]
+                          from the rest state of this reference density per species, so their rounding
+                          is relative to the deviation, not to f_l (0: plain populations).  LB_F64 always
+                          stores plain populations. */
 } lb_psi_params;
 
 /* Fill *c with zero couplings and the default isotropic weights.  Pure host call. */

@@ -36,12 +36,13 @@ class Sim:
     Parameters follow the paper's statement of the problem: lattice (lx, ly, species,
     walls), couplings g1 = G_ss,1, g2 = G_ss,2, gab = G_AB, body force g, relaxation time
     tau, pseudopotential psi0 (1 - exp(-rho / rho0)); rho_init is the initial density
-    [n_species, ly, lx] (host array), started from rest equilibrium.
+    [n_species, ly, lx] (host array), started from rest equilibrium.  rho_ref: reference
+    density per species for the FP32/BF16 deviation storage (default: mean of rho_init).
     """
 
     def __init__(self, lx, ly, rho_init, n_species=1, walls=False, storage="f64", g1=(0.0, 0.0),
                  g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0), rho_wall=(0.0, 0.0), tau=(1.0, 1.0), psi0=1.0,
-                 rho0=1.0, rho_ref=(0.0, 0.0), w=None, p=None, t=None, cross_psi=False, device="cuda",
+                 rho0=1.0, rho_ref=None, w=None, p=None, t=None, cross_psi=False, device="cuda",
                  tile=None):
         import torch
         self._lib = B.load()
@@ -65,6 +66,9 @@ class Sim:
         cpl.cross_uses_psi = 1 if cross_psi else 0
         self.cpl = cpl
         self.tau = (ctypes.c_double * 2)(*_pair(tau))
+        rho = np.ascontiguousarray(np.broadcast_to(rho_init, (self.ns, self.ly, self.lx)), dtype=np.float64)
+        if rho_ref is None:  # deviations from the mean initial density of each species
+            rho_ref = tuple(float(rho[s].mean()) for s in range(self.ns)) + (0.0,) * (2 - self.ns)
         self.psi = B.LbPsiParams(float(psi0), float(rho0), (ctypes.c_double * 2)(*_pair(rho_ref)))
         nbytes = B.pop_bytes(self.lat)
         if nbytes == 0:
@@ -72,7 +76,6 @@ class Sim:
         self.pop_bytes = nbytes
         self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        rho = np.ascontiguousarray(np.broadcast_to(rho_init, (self.ns, self.ly, self.lx)), dtype=np.float64)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         rc = self._lib.lb_init(ctypes.byref(h), ctypes.byref(self.lat), ctypes.byref(cpl), self.tau,

@@ -239,6 +239,9 @@ int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const 
   c->psi = *psi;
   c->tau[0] = tau[0];
   c->tau[1] = lat->n_species == 2 ? tau[1] : tau[0];
+  if (lat->storage == LB_F64) {  // FP64 stores plain populations: checkpoint/restore stay bit-exact
+    c->psi.rho_ref[0] = c->psi.rho_ref[1] = 0.0;
+  }
   if (lat->n_species == 1) {  // single component: no cross term, second species unused
     c->cpl.g_ab = 0.0;
     c->cpl.g1[1] = c->cpl.g2[1] = 0.0;

@@ -57,15 +57,19 @@ __device__ inline Rsrc make_rsrc(const void *p, uint32_t bytes) {
 
 template <int MODE> struct Codec;
 
+// Every storage mode holds deviations d_l = f_l - W_l rho_ref from the rest equilibrium of a
+// per-species reference density.  load/store (layout kernels) convert to and from f; the
+// step works on deviations directly (bload/bstore), which costs nothing and keeps the
+// rounding of each stored value relative to |d_l| instead of |f_l|.
 template <> struct Codec<MODE_F64> {
   using S = double;
   using R = double;
-  __device__ static R load(const S *p, R) { return *p; }
-  __device__ static void store(S *p, R v, R) { *p = v; }
-  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff, R) {
+  __device__ static R load(const S *p, R wref) { return *p + wref; }
+  __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
+  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
-  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v, R) {
+  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
   }
   __device__ static R expo(R v) { return exp(v); }
@@ -75,37 +79,37 @@ template <> struct Codec<MODE_F64> {
 template <> struct Codec<MODE_F32> {
   using S = float;
   using R = float;
-  __device__ static R load(const S *p, R) { return *p; }
-  __device__ static void store(S *p, R v, R) { *p = v; }
-  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff, R) {
+  __device__ static R load(const S *p, R wref) { return *p + wref; }
+  __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
+  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
-  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v, R) {
+  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
   }
   __device__ static R expo(R v) { return __expf(v); }
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
 };
 
-// BF16 deviation from the rest equilibrium: stored value = bf16(f - W_l rho_ref).
+// BF16: stored value = bf16(d_l), arithmetic in FP32.
 template <> struct Codec<MODE_BF16> {
   using S = uint16_t;
   using R = float;
-  __device__ static R decode(uint32_t h, R wref) { return __uint_as_float(h << 16) + wref; }
-  __device__ static uint16_t encode(R v, R wref) {
-    const uint32_t b = __float_as_uint(v - wref);
+  __device__ static R decode(uint32_t h) { return __uint_as_float(h << 16); }
+  __device__ static uint16_t encode(R v) {
+    const uint32_t b = __float_as_uint(v);
     // round to nearest even; NaN stays NaN
     const uint32_t r = (b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) ? (b | 0x00400000u)
                                                                               : b + 0x7fffu + ((b >> 16) & 1u);
     return uint16_t(r >> 16);
   }
-  __device__ static R load(const S *p, R wref) { return decode(*p, wref); }
-  __device__ static void store(S *p, R v, R wref) { *p = encode(v, wref); }
-  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff, R wref) {
-    return decode(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0), wref);
+  __device__ static R load(const S *p, R wref) { return decode(*p) + wref; }
+  __device__ static void store(S *p, R v, R wref) { *p = encode(v - wref); }
+  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff) {
+    return decode(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
   }
-  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v, R wref) {
-    __builtin_amdgcn_raw_buffer_store_b16(encode(v, wref), r, voff, soff, 0);
+  __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
+    __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, voff, soff, 0);
   }
   __device__ static R expo(R v) { return __expf(v); }
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
@@ -153,7 +157,7 @@ __device__ inline LaneOffs lane_offsets(int x, int xm, int xp, uint32_t es, uint
 
 template <class C, int NS>
 __device__ inline void load_pull(const void *base, uint32_t spec_b, const LaneOffs &lo_, const RowOffs &r,
-                                 const typename C::R (&wref)[NS][9], typename C::R (&f)[NS][9]) {
+                                 typename C::R (&f)[NS][9]) {
   // source of each population: (lane offset, row offset)
   uint32_t vo[9], so[9];
   vo[0] = lo_.ld[0]; so[0] = r.o;
@@ -171,8 +175,8 @@ __device__ inline void load_pull(const void *base, uint32_t spec_b, const LaneOf
   for (int s = 0; s < NS; ++s) {
     const Rsrc rs = make_rsrc(static_cast<const char *>(base) + (uint64_t)s * spec_b, spec_b);
 #pragma unroll
-    for (int l = 0; l < 9; ++l)  // W_opp(l) = W_l, so the reference weight does not depend on reflection
-      f[s][l] = C::bload(rs, vo[l], uni(so[l]), wref[s][l]);
+    for (int l = 0; l < 9; ++l)  // W_opp(l) = W_l: a reflected deviation is still a deviation
+      f[s][l] = C::bload(rs, vo[l], uni(so[l]));
   }
 }
 
@@ -250,7 +254,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int tid = threadIdx.x;
 
   // Per-species constants in the arithmetic type.
-  R K1[NS], K2[NS], K4[NS], K5[NS], K8[NS], tau[NS], om[NS], wref[NS][9], psiw[NS], rhow[NS];
+  R K1[NS], K2[NS], K4[NS], K5[NS], K8[NS], tau[NS], om[NS], rref[NS], psiw[NS], rhow[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     K1[s] = R(a.K[s][0]);
@@ -262,8 +266,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     om[s] = R(a.omega[s]);
     psiw[s] = R(a.psi_w[s]);
     rhow[s] = R(a.rho_w[s]);
-#pragma unroll
-    for (int l = 0; l < 9; ++l) wref[s][l] = MODE == MODE_BF16 ? R(WD2Q9[l] * a.rho_ref[s]) : R(0);
+    rref[s] = R(a.rho_ref[s]);
   }
   const R T1 = R(a.T[0]), T2 = R(a.T[1]);
   const R gx = R(a.body[0]), gy = R(a.body[1]);
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
         V ps, rh;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          rh.v[s] = sum9(A[s]);
+          rh.v[s] = rref[s] + sum9(A[s]);
           ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
         }
         prow[tid + 2] = ps;
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
         V ps, rh;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          rh.v[s] = sum9(H[s]);
+          rh.v[s] = rref[s] + sum9(H[s]);
           ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
         }
         prow[hslot] = ps;
@@ -351,16 +354,16 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     constexpr int buf_of[5] = {0, 3, 1, 2, 3};
     {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 2, ly), ly, pitch_b);
-      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, wref, PH[0]);
-      load_pull<C, NS>(src, spec_b, pcc, pr, wref, B[buf_of[0]]);
+      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, PH[0]);
+      load_pull<C, NS>(src, spec_b, pcc, pr, B[buf_of[0]]);
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       if (k < 4) {
         const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 1 + k, ly), ly, pitch_b);
         if (halo)
-          load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, wref, PH[(k + 1) & 1]);
-        load_pull<C, NS>(src, spec_b, pcc, pr, wref, B[buf_of[k + 1]]);
+          load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, PH[(k + 1) & 1]);
+        load_pull<C, NS>(src, spec_b, pcc, pr, B[buf_of[k + 1]]);
       }
       ring_row(k, yA - 2 + k, B[buf_of[k]], PH[k & 1]);
     }
@@ -379,18 +382,19 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     const uint32_t rb0 = (uint32_t)y * pitch_b;
     {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rlead, ly), ly, pitch_b);
-      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, wref, FH);
-      load_pull<C, NS>(src, spec_b, pcc, pr, wref, FL);
+      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, FH);
+      load_pull<C, NS>(src, spec_b, pcc, pr, FL);
     }
 
     __syncthreads();
 
     // ---- update row y ---------------------------------------------------------------------
     // ring rows y-2 .. y+2 occupy slots lead_slot-5 .. lead_slot-1 (mod 6)
-    R rho[NS], jx[NS], jy[NS];
+    R drho[NS], rho[NS], jx[NS], jy[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      rho[s] = sum9(f[s]);
+      drho[s] = sum9(f[s]);
+      rho[s] = rref[s] + drho[s];
       jx[s] = (f[s][1] + f[s][5] + f[s][8]) - (f[s][3] + f[s][6] + f[s][7]);
       jy[s] = (f[s][2] + f[s][5] + f[s][6]) - (f[s][4] + f[s][7] + f[s][8]);
     }
@@ -505,39 +509,40 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       const R ir = C::rcp(rho[s]);
       const R ux = upx + tau[s] * Fx[s] * ir;
       const R uy = upy + tau[s] * Fy[s] * ir;
-      const R base = R(1) - R(1.5) * (ux * ux + uy * uy);
+      // Deviation form of f^eq_l = W_l rho (1 + 3 cu + 9/2 cu^2 - 3/2 u.u):
+      //   f^eq_l - W_l rho_ref = W_l (drho - 3/2 rho u.u) + W_l rho cu (3 + 9/2 cu)
+      const R m15 = R(-1.5) * (ux * ux + uy * uy);
       const R r9 = rho[s] * R(1.0 / 9.0), r36 = rho[s] * R(1.0 / 36.0);
+      const R b9 = drho[s] * R(1.0 / 9.0) + r9 * m15, b36 = drho[s] * R(1.0 / 36.0) + r36 * m15;
       const R o = om[s];
       R fs[9];
-      // feq_l = W_l rho (1 + 3 cu + 9/2 cu^2 - 3/2 u.u)
       {
         const R cu = ux;
-        fs[1] = f[s][1] + o * (r9 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][1]);
-        fs[3] = f[s][3] + o * (r9 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][3]);
+        fs[1] = f[s][1] + o * (b9 + r9 * (cu * (R(3) + R(4.5) * cu)) - f[s][1]);
+        fs[3] = f[s][3] + o * (b9 - r9 * (cu * (R(3) - R(4.5) * cu)) - f[s][3]);
       }
       {
         const R cu = uy;
-        fs[2] = f[s][2] + o * (r9 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][2]);
-        fs[4] = f[s][4] + o * (r9 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][4]);
+        fs[2] = f[s][2] + o * (b9 + r9 * (cu * (R(3) + R(4.5) * cu)) - f[s][2]);
+        fs[4] = f[s][4] + o * (b9 - r9 * (cu * (R(3) - R(4.5) * cu)) - f[s][4]);
       }
       {
         const R cu = ux + uy;
-        fs[5] = f[s][5] + o * (r36 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][5]);
-        fs[7] = f[s][7] + o * (r36 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][7]);
+        fs[5] = f[s][5] + o * (b36 + r36 * (cu * (R(3) + R(4.5) * cu)) - f[s][5]);
+        fs[7] = f[s][7] + o * (b36 - r36 * (cu * (R(3) - R(4.5) * cu)) - f[s][7]);
       }
       {
         const R cu = uy - ux;
-        fs[6] = f[s][6] + o * (r36 * (base + cu * (R(3) + R(4.5) * cu)) - f[s][6]);
-        fs[8] = f[s][8] + o * (r36 * (base - cu * (R(3) - R(4.5) * cu)) - f[s][8]);
+        fs[6] = f[s][6] + o * (b36 + r36 * (cu * (R(3) + R(4.5) * cu)) - f[s][6]);
+        fs[8] = f[s][8] + o * (b36 - r36 * (cu * (R(3) - R(4.5) * cu)) - f[s][8]);
       }
-      // rest population closes the mass balance exactly: f*_0 = rho - sum_{l>0} f*_l
-      fs[0] = rho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
+      // rest population closes the mass balance exactly: d*_0 = drho - sum_{l>0} d*_l
+      fs[0] = drho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
 
       if (STORE) {
 #pragma unroll
         for (int l = 0; l < 9; ++l)
-          C::bstore(make_rsrc(static_cast<char *>(dst) + (uint64_t)s * spec_b, spec_b), sto[l], uni(rb0), fs[l],
-                    wref[s][l]);
+          C::bstore(make_rsrc(static_cast<char *>(dst) + (uint64_t)s * spec_b, spec_b), sto[l], uni(rb0), fs[l]);
       }
       if (REDUCE && WALLS && col_ok) {
         if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7]));

