@@ -69,7 +69,8 @@ enum lb_storage {
 enum lb_dtype { LB_OUT_F64 = 0, LB_OUT_F32 = 1 };
 
 typedef struct {
-  int32_t lx, ly;      /* lattice size: lx, ly >= 5, ly <= 65535, lx * ly <= 2^27 */
+  int32_t lx, ly;      /* lattice size: lx, ly >= 5, ly <= 65535, lx * ly <= 2^27, and one population
+                          buffer (lb_pop_bytes) below 4 GiB */
   int32_t n_species;   /* 1 or 2 */
   int32_t walls;       /* 0: periodic in x and y; 1: channel, bounce-back walls below row 0 and above row ly-1 */
   int32_t storage;     /* enum lb_storage */

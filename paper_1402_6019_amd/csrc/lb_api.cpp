@@ -226,6 +226,8 @@ int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const 
   if (!rho_init || !pop_a || !pop_b) return fail(nullptr, LB_EINVAL, "null buffer");
   if (pop_a == pop_b) return fail(nullptr, LB_EINVAL, "pop_a and pop_b must differ");
   const size_t need = lb_pop_bytes(lat);
+  if (need >= ((size_t)1 << 32))  // the kernels address a buffer with 32-bit byte offsets
+    return fail(nullptr, LB_EINVAL, "lattice too large: one population buffer must stay below 4 GiB");
   if (pop_bytes < need) return fail(nullptr, LB_ENOMEM, "population buffers smaller than lb_pop_bytes()");
   const size_t nsite = (size_t)lat->lx * lat->ly;
   for (size_t i = 0; i < (size_t)lat->n_species * nsite; ++i)

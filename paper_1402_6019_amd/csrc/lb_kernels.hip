@@ -6,8 +6,9 @@
 //   body force  ->  velocity shift u_eq,s = u' + tau_s F_s / rho_s  ->  BGK collision
 //   ->  store of the post-collision populations (unshifted; the next step pulls them).
 //
-// Layout in HBM: populations as planes [species][l][y][pitch], x fastest (SoA), so every
-// load and store of a wavefront touches 64 consecutive elements of one row.
+// Layout in HBM: [species][y][l][pitch], x fastest: for each species and row, the nine
+// population rows follow each other, so every load and store of a wavefront touches 64
+// consecutive elements and one row of all planes is one contiguous run.
 //
 // Work decomposition: a workgroup owns a strip of tx columns (one thread per column) and a
 // segment of sy rows, and marches down its rows.  The force at row y needs psi at rows
@@ -188,15 +189,56 @@ template <bool WALLS>
 __device__ inline int lead_row(int r, int ly) { return WALLS ? min(max(r, 0), ly - 1) : r; }
 
 template <bool WALLS>
-__device__ inline RowOffs row_pull(int r, int ly, uint32_t pitch_b) {
+__device__ inline RowOffs row_pull(int r, int ly, uint32_t row_b) {
   RowOffs o;
   const int rw = WALLS ? r : wrapi(r, ly);
   o.lo = WALLS && rw == 0;
   o.hi = WALLS && rw == ly - 1;
-  o.o = (uint32_t)rw * pitch_b;
-  o.m = o.lo ? o.o : (uint32_t)wrapi(rw - 1, ly) * pitch_b;
-  o.p = o.hi ? o.o : (uint32_t)wrapi(rw + 1, ly) * pitch_b;
+  o.o = (uint32_t)rw * row_b;
+  o.m = o.lo ? o.o : (uint32_t)wrapi(rw - 1, ly) * row_b;
+  o.p = o.hi ? o.o : (uint32_t)wrapi(rw + 1, ly) * row_b;
   return o;
+}
+
+// One pulled population of a halo column: lane offsets (species, plane and column folded
+// in) for the direct and the reflected source, and masks for c_y = +1 / -1 (all ones or 0;
+// mask arithmetic instead of a three-way choice, which the compiler would otherwise turn
+// into a lookup table in scratch memory).
+struct HaloItem {
+  uint32_t direct, reflected;
+  uint32_t up, dn;
+};
+
+template <int NS>
+__device__ inline HaloItem halo_item(int l, int sp, int xh, int lx, uint32_t es, uint32_t plane_b,
+                                     uint32_t spec_b) {
+  int cx = 0, cy = 0, op = 0;
+  switch (l) {  // D2Q9 velocities and opposites
+    case 0: cx = 0; cy = 0; op = 0; break;
+    case 1: cx = 1; cy = 0; op = 3; break;
+    case 2: cx = 0; cy = 1; op = 4; break;
+    case 3: cx = -1; cy = 0; op = 1; break;
+    case 4: cx = 0; cy = -1; op = 2; break;
+    case 5: cx = 1; cy = 1; op = 7; break;
+    case 6: cx = -1; cy = 1; op = 8; break;
+    case 7: cx = -1; cy = -1; op = 5; break;
+    default: cx = 1; cy = -1; op = 6; break;
+  }
+  HaloItem h;
+  h.direct = (uint32_t)sp * spec_b + (uint32_t)l * plane_b + (uint32_t)wrapi(xh - cx, lx) * es;
+  h.reflected = (uint32_t)sp * spec_b + (uint32_t)op * plane_b + (uint32_t)xh * es;
+  h.up = cy == 1 ? 0xffffffffu : 0u;
+  h.dn = cy == -1 ? 0xffffffffu : 0u;
+  return h;
+}
+
+// Byte offset of a halo item in lead row r: source row r - c_y, or the item's reflected
+// source in row r when that row is a wall.
+__device__ inline uint32_t halo_offset(const HaloItem &h, const RowOffs &r) {
+  const uint32_t lo = r.lo ? 0xffffffffu : 0u, hi = r.hi ? 0xffffffffu : 0u;
+  const uint32_t bb = (h.up & lo) | (h.dn & hi);
+  const uint32_t row = r.o ^ ((r.m ^ r.o) & h.up) ^ ((r.p ^ r.o) & h.dn);
+  return (bb & (h.reflected + r.o)) | (~bb & (h.direct + row));
 }
 
 template <typename R>
@@ -245,8 +287,13 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int strip = logical / a.nseg;
   const int seg = logical - strip * a.nseg;
   const int lx = a.lx, ly = a.ly;
+  // Layout [species][y][l][pitch]: the nine planes of a species are interleaved row by row,
+  // so one row of all nine planes is a single contiguous run (fewer, longer DRAM streams
+  // than whole planes).  plane_b: byte stride between planes l and l+1 of one row; row_b:
+  // byte stride between rows; spec_b: byte stride between species.
   const uint32_t pitch_b = (uint32_t)a.pitch * sizeof(S);
-  const uint32_t plane_b = (uint32_t)a.plane * (uint32_t)sizeof(S);
+  const uint32_t plane_b = pitch_b;
+  const uint32_t row_b = 9u * pitch_b;
   const int x0 = strip * TX;
   const int w = min(TX, lx - x0);
   const int yA = seg * a.sy;
@@ -274,119 +321,166 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const void *const src = a.src;
   void *const dst = a.dst;
 
-  // Interior column of this thread (ring slot tid + 2) and, for threads 0..3, one halo
-  // column (ring slots 0, 1, w+2, w+3 = columns x0-2, x0-1, x0+w, x0+w+1).
+  // Interior column of this thread (ring slot tid + 2).
   const bool col_ok = tid < w;
   const int xc = x0 + (col_ok ? tid : 0);
   const uint32_t es = (uint32_t)sizeof(S);
-  const uint32_t spec_b = 9u * plane_b;
+  const uint32_t spec_b = 9u * (uint32_t)a.plane * (uint32_t)sizeof(S);
   const LaneOffs pcc = lane_offsets(xc, wrapi(xc - 1, lx), wrapi(xc + 1, lx), es, plane_b);
   // Store column: lanes past a ragged strip's end write into the row padding (the row
   // pitch is a multiple of the widest strip), which no kernel ever reads.
   uint32_t sto[9];
 #pragma unroll
   for (int l = 0; l < 9; ++l) sto[l] = (uint32_t)l * plane_b + (uint32_t)(x0 + tid) * es;
-  const bool halo = tid < 4;
-  const int hslot = tid < 2 ? tid : w + tid;
-  const int xh = wrapi(x0 - 2 + hslot, lx);
-  const int xhm = wrapi(xh - 1, lx), xhp = wrapi(xh + 1, lx);
+
+  // Halo columns x0-2, x0-1, x0+w, x0+w+1 (ring slots 0, 1, w+2, w+3).  Their 4 x NS x 9
+  // pulled populations per lead row ("halo items", item it: column it / (9 NS), species
+  // (it / 9) % NS, plane it % 9) are spread over the workgroup as single loads, two per
+  // thread (threads without a second item re-load item 0, so no load sits under a lane
+  // condition), staged in LDS and summed in plane order by one lane per (column, species)
+  // in every wave -- the same sum, in the same order, as for an interior column.
+  constexpr int NI = 36 * NS;
+  R *hstage = reinterpret_cast<R *>(psi_ring + (NS == 2 ? 12 : 6) * W4);  // [7][NI]
+  const int xhc0 = wrapi(x0 - 2, lx), xhc1 = wrapi(x0 - 1, lx), xhc2 = wrapi(x0 + w, lx),
+            xhc3 = wrapi(x0 + w + 1, lx);
+  HaloItem hitem[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    int it = tid + k * TX;
+    if (it >= NI) it = 0;
+    const int hc = it / (9 * NS), sp = (it / 9) % NS, l = it % 9;
+    const int xh = hc == 0 ? xhc0 : (hc == 1 ? xhc1 : (hc == 2 ? xhc2 : xhc3));
+    hitem[k] = halo_item<NS>(l, sp, xh, lx, es, plane_b, spec_b);
+  }
 
   double acc[RED_N];
 #pragma unroll
   for (int k = 0; k < RED_N; ++k) acc[k] = 0.0;
 
-  // Stage 1: psi_s and rho_s of lead row r into ring slot `slot` (interior and halo columns)
-  // from the pulled populations A (interior column) and H (halo column).
-  auto ring_row = [&](int slot, int r, const R (&A)[NS][9], const R (&H)[NS][9]) {
-    V *prow = psi_ring + slot * W4;
-    V *rrow = rho_ring + slot * W4;
+  // Stage 1, interior columns: psi_s and rho_s of lead row r into ring slot `slot` from the
+  // pulled populations A of this thread's column.
+  auto ring_row = [&](int slot, int r, const R (&A)[NS][9]) {
+    if (!col_ok) return;
+    V ps, rh;
     if (!row_fluid<WALLS>(r, ly)) {
-      V ps, rh;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         ps.v[s] = psiw[s];
         rh.v[s] = rhow[s];
       }
-      if (col_ok) {
-        prow[tid + 2] = ps;
-        if (NS == 2) rrow[tid + 2] = rh;
-      }
-      if (halo) {
-        prow[hslot] = ps;
-        if (NS == 2) rrow[hslot] = rh;
-      }
     } else {
-      if (col_ok) {
-        V ps, rh;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          rh.v[s] = rref[s] + sum9(A[s]);
-          ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
-        }
-        prow[tid + 2] = ps;
-        if (NS == 2) rrow[tid + 2] = rh;
+      for (int s = 0; s < NS; ++s) {
+        rh.v[s] = rref[s] + sum9(A[s]);
+        ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
       }
-      if (halo) {
-        V ps, rh;
+    }
+    psi_ring[slot * W4 + tid + 2] = ps;
+    if (NS == 2) rho_ring[slot * W4 + tid + 2] = rh;
+  };
+
+  // Stage 1, halo columns: load (two items per thread), stage into LDS buffer `buf`, and
+  // finish (after a barrier) into ring slot `slot`.
+  auto halo_load = [&](const RowOffs &r, R (&hv)[2]) {
+    const Rsrc rs = make_rsrc(src, (uint32_t)NS * spec_b);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          rh.v[s] = rref[s] + sum9(H[s]);
-          ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
-        }
-        prow[hslot] = ps;
-        if (NS == 2) rrow[hslot] = rh;
+    for (int k = 0; k < 2; ++k) hv[k] = C::bload(rs, halo_offset(hitem[k], r), 0u);
+  };
+  auto halo_stage = [&](int buf, const R (&hv)[2]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = tid + k * TX;
+      if (it < NI) hstage[buf * NI + it] = hv[k];
+    }
+  };
+  auto halo_finish = [&](int buf, int slot, int r) {
+    const int lane = tid & 63, wv = tid >> 6, nw = TX >> 6;
+    if (lane >= NS) return;
+    const int sp = lane;
+    const bool fluid = row_fluid<WALLS>(r, ly);
+    const R rr = sp == 0 ? rref[0] : rref[NS - 1];
+    for (int hc = wv; hc < 4; hc += nw) {
+      R rh, ps;
+      if (!fluid) {
+        rh = sp == 0 ? rhow[0] : rhow[NS - 1];
+        ps = sp == 0 ? psiw[0] : psiw[NS - 1];
+      } else {
+        const R *q = hstage + buf * NI + (hc * NS + sp) * 9;
+        R sum = q[0];
+#pragma unroll
+        for (int l = 1; l < 9; ++l) sum += q[l];
+        rh = rr + sum;
+        ps = psi0 * (R(1) - C::expo(rh * nirho0));
       }
+      const int hsl = hc < 2 ? hc : w + hc;
+      reinterpret_cast<R *>(psi_ring + slot * W4 + hsl)[sp] = ps;
+      if (NS == 2) reinterpret_cast<R *>(rho_ring + slot * W4 + hsl)[sp] = rh;
     }
   };
 
-  // Register FIFO of pulled populations.  The populations of lead row y+3, loaded in the
-  // iteration of output row y to compute its psi, are the stage-2 input of row y+3 three
-  // iterations later; four row buffers (the main loop is unrolled by four so their roles
-  // rotate statically) mean every population is loaded once per step, one iteration of
-  // arithmetic ahead of its first use.
-  R B[4][NS][9];
-  R FH[NS][9];  // halo column of the lead row (threads 0..3)
+  // Register FIFO of pulled populations, two rows of lookahead.  The populations of lead
+  // row y+4 are loaded in the iteration of output row y, turned into psi in the next
+  // iteration, and are the stage-2 input of row y+4 four iterations after loading; five
+  // row buffers (the main loop is unrolled by five so their roles rotate statically) mean
+  // every population is loaded once per step, a full iteration of arithmetic before its
+  // first use.
+  R B[5][NS][9];
+  R HV[2];  // halo items of the lead row in flight
 
-  // Prologue: ring rows yA-2 .. yA+2, loads one row ahead.  Rows yA, yA+1, yA+2 stay in
-  // B[1], B[2], B[3] for the first three output rows.
+  // Prologue: ring rows yA-2 .. yA+2 (slots 0..4).  Rows yA .. yA+2 stay in B[1..3]; the
+  // loads of row yA+3 go to B[4] once row yA-1 has been consumed from it.
   {
-    R PH[2][NS][9];
-    constexpr int buf_of[5] = {0, 3, 1, 2, 3};
-    {
-      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 2, ly), ly, pitch_b);
-      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, PH[0]);
-      load_pull<C, NS>(src, spec_b, pcc, pr, B[buf_of[0]]);
+    constexpr int bufp[5] = {0, 4, 1, 2, 3};
+    R HP[5][2];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 2 + k, ly), ly, row_b);
+      load_pull<C, NS>(src, spec_b, pcc, pr, B[bufp[k]]);
+      halo_load(pr, HP[k]);
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      if (k < 4) {
-        const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 1 + k, ly), ly, pitch_b);
-        if (halo)
-          load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, PH[(k + 1) & 1]);
-        load_pull<C, NS>(src, spec_b, pcc, pr, B[buf_of[k + 1]]);
+      ring_row(k, yA - 2 + k, B[bufp[k]]);
+      halo_stage(k, HP[k]);
+      if (k == 1) {
+        const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA + 3, ly), ly, row_b);
+        load_pull<C, NS>(src, spec_b, pcc, pr, B[4]);
+        halo_load(pr, HV);
       }
-      ring_row(k, yA - 2 + k, B[buf_of[k]], PH[k & 1]);
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 5; ++k) halo_finish(k, k, yA - 2 + k);
   }
 
-  // One output row y: issue the loads of lead row y+3 (halo batch first: it is the only one
-  // under a lane condition) -> barrier -> force + collision of row y from the ring and the
-  // FIFO, store -> ring row y+3.  Stores carry no condition either: lanes past a ragged
-  // strip's end write into the row padding.  The ring slot written last, (y+3) mod 6, is
-  // not among the rows y-2..y+2 that slower waves may still be reading.
-  auto step_row = [&](const int y_in, const int lead_slot_in, R (&FL)[NS][9], const R (&f)[NS][9]) {
-    // the row index is uniform; saying so keeps every row and plane offset in SGPRs
+  // One output row y (FIFO roles: FL <- lead row y+4, f = row y, FR = lead row y+3):
+  //   stage the halo items of lead row y+3 -> issue the loads of lead row y+4 -> barrier ->
+  //   ring row y+3 (interior and halo) -> force + collision of row y, store.
+  // Loads and stores carry no lane or row conditions (lanes past a ragged strip's end store
+  // into the row padding), so every wait covers exactly the batch it needs.  The ring slot
+  // written last, (y+3) mod 6, is not among the rows y-2..y+2 that slower waves may still
+  // read, and the halo staging buffers alternate between iterations.
+  auto step_row = [&](const int y_in, const int lead_slot_in, R (&FL)[NS][9], const R (&f)[NS][9],
+                      const R (&FR)[NS][9]) {
+    // the row index is uniform; saying so keeps every row offset in SGPRs
     const int y = (int)uni((uint32_t)y_in);
     const int lead_slot = (int)uni((uint32_t)lead_slot_in);
-    const int rlead = y + 3;
-    const uint32_t rb0 = (uint32_t)y * pitch_b;
+    const int hbuf = 5 + ((y + 3) & 1);
+    const uint32_t rb0 = (uint32_t)y * row_b;
+    halo_stage(hbuf, HV);
     {
-      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rlead, ly), ly, pitch_b);
-      if (halo) load_pull<C, NS>(src, spec_b, lane_offsets(xh, xhm, xhp, es, plane_b), pr, FH);
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(min(y + 4, yB + 1), ly), ly, row_b);
       load_pull<C, NS>(src, spec_b, pcc, pr, FL);
+      halo_load(pr, HV);
     }
 
     __syncthreads();
+
+    // ---- ring row y + 3 from the loads issued in the previous iteration ----------------------
+    // (slot (y+3) mod 6 is not among the rows y-2..y+2 read below; doing it first lets its
+    // LDS round trips overlap the update of row y)
+    ring_row(lead_slot, y + 3, FR);
+    halo_finish(hbuf, lead_slot, y + 3);
 
     // ---- update row y ---------------------------------------------------------------------
     // ring rows y-2 .. y+2 occupy slots lead_slot-5 .. lead_slot-1 (mod 6)
@@ -573,23 +667,24 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     }
     }  // WHAT != WHAT_MOMENTS
 
-    // ---- ring row y + 3 from the loads issued at the top of this iteration -----------------
-    ring_row(lead_slot, y + 3, FL, FH);
   };
 
   int lead_slot = 5;
   auto next_slot = [](int sl) { return sl == 5 ? 0 : sl + 1; };
   for (int y = yA; y < yB;) {
-    step_row(y, lead_slot, B[0], B[1]);
+    step_row(y, lead_slot, B[0], B[1], B[4]);
     lead_slot = next_slot(lead_slot);
     if (++y >= yB) break;
-    step_row(y, lead_slot, B[1], B[2]);
+    step_row(y, lead_slot, B[1], B[2], B[0]);
     lead_slot = next_slot(lead_slot);
     if (++y >= yB) break;
-    step_row(y, lead_slot, B[2], B[3]);
+    step_row(y, lead_slot, B[2], B[3], B[1]);
     lead_slot = next_slot(lead_slot);
     if (++y >= yB) break;
-    step_row(y, lead_slot, B[3], B[0]);
+    step_row(y, lead_slot, B[3], B[4], B[2]);
+    lead_slot = next_slot(lead_slot);
+    if (++y >= yB) break;
+    step_row(y, lead_slot, B[4], B[0], B[3]);
     lead_slot = next_slot(lead_slot);
     ++y;
   }
@@ -656,6 +751,11 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int
 // and its inverse g_l(z) = f_l(z + c_l) if z + c_l is fluid, else f_opp(l)(z).
 // ---------------------------------------------------------------------------------------
 
+// Element index of population l of species s at (x, y): layout [species][y][l][pitch].
+__device__ inline long long pop_index(int s, int l, int y, int x, long long plane, int pitch) {
+  return (long long)s * 9 * plane + ((long long)y * 9 + l) * pitch + x;
+}
+
 template <int MODE, bool WALLS>
 __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
   using C = Codec<MODE>;
@@ -678,7 +778,7 @@ __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
         zy = wrapi(zy, a.ly);
       }
       const double v = WD2Q9[l] * rho[s * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + (long long)(s * 9 + l) * a.plane + (long long)y * a.pitch + x, R(v),
+      C::store(out + pop_index(s, l, y, x, a.plane, a.pitch), R(v),
                R(WD2Q9[l] * a.rho_ref[s]));
     }
 }
@@ -706,7 +806,7 @@ __global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][l
         zy = wrapi(zy, a.ly);
       }
       const double v = f[(size_t)(s * 9 + lsrc) * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + (long long)(s * 9 + l) * a.plane + (long long)y * a.pitch + x, R(v),
+      C::store(out + pop_index(s, l, y, x, a.plane, a.pitch), R(v),
                R(WD2Q9[l] * a.rho_ref[s]));
     }
 }
@@ -733,7 +833,7 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const R v = C::load(in + (long long)(s * 9 + lsrc) * a.plane + (long long)zy * a.pitch + zx,
+      const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.plane, a.pitch),
                           R(WD2Q9[lsrc] * a.rho_ref[s]));
       f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] = double(v);
     }
@@ -745,7 +845,7 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
 
 size_t step_lds_bytes(int mode, int ns, int tx) {
   const size_t r = mode == MODE_F64 ? 8 : 4;
-  return 6 * (size_t)(tx + 4) * ns * r * (ns == 2 ? 2 : 1);
+  return 6 * (size_t)(tx + 4) * ns * r * (ns == 2 ? 2 : 1) + 7 * 36 * (size_t)ns * r;  // rings + halo staging
 }
 
 template <int MODE, int NS, bool WALLS>
