@@ -41,6 +41,7 @@ struct lb_ctx {
   int pitch = 0;
   long long plane = 0;
   int tx = 256, sy = 16;
+  int n_cu = 256;  // compute units of the device the context runs on
   int reduce_every = 0;
   int64_t t = 0;
   double *d_partials = nullptr;  // [partial_cap][RED_N], grown to the largest launch
@@ -186,10 +187,17 @@ int validate(const lb_lattice *lat, const lb_couplings *cpl, const double tau[2]
   return LB_OK;
 }
 
+// Default launch shape: the widest strip the lattice fills, and segments sized so that the
+// whole grid is resident at once (workgroups = resident workgroups per CU x CUs, at most):
+// the step is one pass over the lattice, and a second, partial wave of workgroups would
+// cost nearly as much as the first.
 void default_tile(lb_ctx *c) {
-  const int lx = c->lat.lx;
+  const int lx = c->lat.lx, ly = c->lat.ly;
   c->tx = lx >= 256 ? 256 : (lx >= 128 ? 128 : 64);
-  c->sy = std::min(16, c->lat.ly);
+  const int nstrip = (lx + c->tx - 1) / c->tx;
+  const int cap = step_blocks_per_cu(c->lat.storage, c->lat.n_species, c->lat.walls, c->tx) * c->n_cu;
+  const int nseg = std::max(1, cap / nstrip);
+  c->sy = std::min(ly, std::max(1, (ly + nseg - 1) / nseg));
 }
 
 }  // namespace
@@ -256,6 +264,12 @@ int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const 
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->pitch = row_pitch(lat->lx);
   c->plane = (long long)lat->ly * c->pitch;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      c->n_cu = ncu;
+  }
   default_tile(c);
 
   hipError_t e;

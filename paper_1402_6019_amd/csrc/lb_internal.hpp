@@ -64,5 +64,7 @@ hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
 
 size_t step_lds_bytes(int mode, int ns, int tx);
+// Workgroups of tx threads of the plain step kernel that one compute unit holds at once.
+int step_blocks_per_cu(int mode, int ns, int walls, int tx);
 
 }  // namespace lb355

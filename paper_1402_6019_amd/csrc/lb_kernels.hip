@@ -11,18 +11,23 @@
 // consecutive elements and one row of all planes is one contiguous run.
 //
 // Work decomposition: a workgroup owns a strip of tx columns (one thread per column) and a
-// segment of sy rows, and marches down its rows.  The force at row y needs psi at rows
-// y-2..y+2 and columns x-2..x+2, so the workgroup keeps a six-row ring of psi_s (and rho_s
-// for the A-B term) for its tx + 4 columns in LDS: each iteration computes the leading row
-// r = y + 2 of the ring (the pulled moments of tx + 4 sites), synchronises once, then
-// updates row y from the ring.  Interior columns are computed once per row; only the two
-// halo columns on each side and four extra rows per segment are recomputed by neighbours.
-// Six ring slots make one barrier per row sufficient: the slot written in iteration r+1 is
-// never among the five slots read in iteration r.
+// segment of sy rows, and marches through its rows, down for even segments and up for odd
+// ones.  The force at row y needs psi at rows y-2..y+2 and columns x-2..x+2, so the
+// workgroup keeps a six-row ring of psi_s (and rho_s for the A-B term) for its tx + 4
+// columns in LDS: each iteration computes the leading row of the ring (the pulled moments
+// of tx + 4 sites), synchronises once, then updates row y from the ring.  Interior columns
+// are computed once per row; only the two halo columns on each side and three rows beyond
+// each end of a segment are pulled again by the neighbours.  Six ring slots make one
+// barrier per row sufficient: the slot written in iteration r+1 is never among the five
+// slots read in iteration r.
 //
-// Workgroups are dispatched round-robin over the eight XCDs; xcd_remap() gives each XCD a
-// contiguous range of (strip, segment) tiles, segments fastest, so the halo rows shared by
-// consecutive segments are re-read from that XCD's own L2.
+// Those overlaps are read twice from L2 but once from memory when both readers run on the
+// same XCD at the same time.  Workgroups are dispatched round-robin over the eight XCDs;
+// xcd_remap() gives each XCD a contiguous range of tiles in band-major order (all strips
+// of a band of rows, then the next band), so horizontal neighbours share an XCD and reach
+// the same row together; and since neighbouring segments march in opposite directions,
+// both reach their common boundary rows at the same time (together at the start, or
+// together at the end of the march).
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -284,8 +289,9 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   __shared__ double red_lds[4][RED_N];
 
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int strip = logical / a.nseg;
-  const int seg = logical - strip * a.nseg;
+  const int nstrip = (int)gridDim.x / a.nseg;
+  const int seg = logical / nstrip;
+  const int strip = logical - seg * nstrip;
   const int lx = a.lx, ly = a.ly;
   // Layout [species][y][l][pitch]: the nine planes of a species are interleaved row by row,
   // so one row of all nine planes is a single contiguous run (fewer, longer DRAM streams
@@ -298,6 +304,11 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int w = min(TX, lx - x0);
   const int yA = seg * a.sy;
   const int yB = min(yA + a.sy, ly);
+  // march direction and first output row: rows y0, y0 + dir, ..., through the segment
+  const int dir = (seg & 1) ? -1 : 1;
+  const int y0 = dir > 0 ? yA : yB - 1;
+  // last lead row the march needs (two beyond the segment's far end)
+  const int ylast = dir > 0 ? yB + 1 : yA - 2;
   const int tid = threadIdx.x;
 
   // Per-species constants in the arithmetic type.
@@ -418,42 +429,43 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     }
   };
 
-  // Register FIFO of pulled populations, two rows of lookahead.  The populations of lead
-  // row y+4 are loaded in the iteration of output row y, turned into psi in the next
-  // iteration, and are the stage-2 input of row y+4 four iterations after loading; five
-  // row buffers (the main loop is unrolled by five so their roles rotate statically) mean
-  // every population is loaded once per step, a full iteration of arithmetic before its
-  // first use.
+  // Register FIFO of pulled populations, two rows of lookahead.  Rows are named in march
+  // order below (y + 4 means y + 4 dir).  The populations of lead row y+4 are loaded in the
+  // iteration of output row y, turned into psi in the next iteration, and are the stage-2
+  // input of row y+4 four iterations after loading; five row buffers (the main loop is
+  // unrolled by five so their roles rotate statically) mean every population is loaded once
+  // per step, a full iteration of arithmetic before its first use.
   R B[5][NS][9];
   R HV[2];  // halo items of the lead row in flight
 
-  // Prologue: ring rows yA-2 .. yA+2 (slots 0..4).  Rows yA .. yA+2 stay in B[1..3]; the
-  // loads of row yA+3 go to B[4] once row yA-1 has been consumed from it.
+  // Prologue: ring rows y0-2 .. y0+2 (slots 0..4).  Rows y0 .. y0+2 stay in B[1..3]; the
+  // loads of row y0+3 go to B[4] once row y0-1 has been consumed from it.
   {
     constexpr int bufp[5] = {0, 4, 1, 2, 3};
     R HP[5][2];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA - 2 + k, ly), ly, row_b);
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(y0 + dir * (k - 2), ly), ly, row_b);
       load_pull<C, NS>(src, spec_b, pcc, pr, B[bufp[k]]);
       halo_load(pr, HP[k]);
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      ring_row(k, yA - 2 + k, B[bufp[k]]);
+      ring_row(k, y0 + dir * (k - 2), B[bufp[k]]);
       halo_stage(k, HP[k]);
       if (k == 1) {
-        const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(yA + 3, ly), ly, row_b);
+        const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(y0 + 3 * dir, ly), ly, row_b);
         load_pull<C, NS>(src, spec_b, pcc, pr, B[4]);
         halo_load(pr, HV);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 5; ++k) halo_finish(k, k, yA - 2 + k);
+    for (int k = 0; k < 5; ++k) halo_finish(k, k, y0 + dir * (k - 2));
   }
 
-  // One output row y (FIFO roles: FL <- lead row y+4, f = row y, FR = lead row y+3):
+  // One output row y (march order; FIFO roles: FL <- lead row y+4, f = row y, FR = lead
+  // row y+3):
   //   stage the halo items of lead row y+3 -> issue the loads of lead row y+4 -> barrier ->
   //   ring row y+3 (interior and halo) -> force + collision of row y, store.
   // Loads and stores carry no lane or row conditions (lanes past a ragged strip's end store
@@ -469,7 +481,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     const uint32_t rb0 = (uint32_t)y * row_b;
     halo_stage(hbuf, HV);
     {
-      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(min(y + 4, yB + 1), ly), ly, row_b);
+      const int r4 = dir > 0 ? min(y + 4, ylast) : max(y - 4, ylast);
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r4, ly), ly, row_b);
       load_pull<C, NS>(src, spec_b, pcc, pr, FL);
       halo_load(pr, HV);
     }
@@ -479,11 +492,12 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     // ---- ring row y + 3 from the loads issued in the previous iteration ----------------------
     // (slot (y+3) mod 6 is not among the rows y-2..y+2 read below; doing it first lets its
     // LDS round trips overlap the update of row y)
-    ring_row(lead_slot, y + 3, FR);
-    halo_finish(hbuf, lead_slot, y + 3);
+    ring_row(lead_slot, y + 3 * dir, FR);
+    halo_finish(hbuf, lead_slot, y + 3 * dir);
 
     // ---- update row y ---------------------------------------------------------------------
-    // ring rows y-2 .. y+2 occupy slots lead_slot-5 .. lead_slot-1 (mod 6)
+    // the ring holds rows y + dir (m - 2), m = 0..4, in slots lead_slot + 1 + m (mod 6): the
+    // row at physical offset d is in slot lead_slot + 3 + dir d
     R drho[NS], rho[NS], jx[NS], jy[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -493,11 +507,11 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       jy[s] = (f[s][2] + f[s][5] + f[s][6]) - (f[s][4] + f[s][7] + f[s][8]);
     }
 
-    // ring rows y-2 .. y+2
+    // ring rows y-2 .. y+2 (physical order)
     const V *rows[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      int sl = lead_slot + 1 + k;
+      int sl = lead_slot + 3 + dir * (k - 2);
       sl = sl >= 6 ? sl - 6 : sl;
       sl = sl >= 6 ? sl - 6 : sl;
       rows[k] = psi_ring + sl * W4 + tid + 2;
@@ -535,7 +549,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const V *base = a.cross_psi ? psi_ring : rho_ring;
-        int sl = lead_slot + 2 + k;
+        int sl = lead_slot + 3 + dir * (k - 1);
         sl = sl >= 6 ? sl - 6 : sl;
         sl = sl >= 6 ? sl - 6 : sl;
         xr[k] = base + sl * W4 + tid + 2;
@@ -671,22 +685,23 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 
   int lead_slot = 5;
   auto next_slot = [](int sl) { return sl == 5 ? 0 : sl + 1; };
-  for (int y = yA; y < yB;) {
-    step_row(y, lead_slot, B[0], B[1], B[4]);
+  const int nrow = yB - yA;
+  for (int i = 0; i < nrow;) {
+    step_row(y0 + dir * i, lead_slot, B[0], B[1], B[4]);
     lead_slot = next_slot(lead_slot);
-    if (++y >= yB) break;
-    step_row(y, lead_slot, B[1], B[2], B[0]);
+    if (++i >= nrow) break;
+    step_row(y0 + dir * i, lead_slot, B[1], B[2], B[0]);
     lead_slot = next_slot(lead_slot);
-    if (++y >= yB) break;
-    step_row(y, lead_slot, B[2], B[3], B[1]);
+    if (++i >= nrow) break;
+    step_row(y0 + dir * i, lead_slot, B[2], B[3], B[1]);
     lead_slot = next_slot(lead_slot);
-    if (++y >= yB) break;
-    step_row(y, lead_slot, B[3], B[4], B[2]);
+    if (++i >= nrow) break;
+    step_row(y0 + dir * i, lead_slot, B[3], B[4], B[2]);
     lead_slot = next_slot(lead_slot);
-    if (++y >= yB) break;
-    step_row(y, lead_slot, B[4], B[0], B[3]);
+    if (++i >= nrow) break;
+    step_row(y0 + dir * i, lead_slot, B[4], B[0], B[3]);
     lead_slot = next_slot(lead_slot);
-    ++y;
+    ++i;
   }
 
   if (REDUCE) {
@@ -871,6 +886,30 @@ template <int MODE>
 static hipError_t launch_step_m(int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
   if (ns == 1) return walls ? launch_step_t<MODE, 1, true>(what, tx, nb, a, st) : launch_step_t<MODE, 1, false>(what, tx, nb, a, st);
   return walls ? launch_step_t<MODE, 2, true>(what, tx, nb, a, st) : launch_step_t<MODE, 2, false>(what, tx, nb, a, st);
+}
+
+template <int MODE, int NS, bool WALLS>
+static int blocks_per_cu_t(int tx) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<MODE, NS, WALLS, WHAT_STEP>, tx,
+                                                   step_lds_bytes(MODE, NS, tx)) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int MODE>
+static int blocks_per_cu_m(int ns, int walls, int tx) {
+  if (ns == 1) return walls ? blocks_per_cu_t<MODE, 1, true>(tx) : blocks_per_cu_t<MODE, 1, false>(tx);
+  return walls ? blocks_per_cu_t<MODE, 2, true>(tx) : blocks_per_cu_t<MODE, 2, false>(tx);
+}
+
+int step_blocks_per_cu(int mode, int ns, int walls, int tx) {
+  switch (mode) {
+    case MODE_F64: return blocks_per_cu_m<MODE_F64>(ns, walls, tx);
+    case MODE_F32: return blocks_per_cu_m<MODE_F32>(ns, walls, tx);
+    case MODE_BF16: return blocks_per_cu_m<MODE_BF16>(ns, walls, tx);
+  }
+  return 1;
 }
 
 hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st) {

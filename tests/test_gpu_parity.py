@@ -103,11 +103,15 @@ def test_channel_observables_fp64():
     assert wt == pytest.approx(ref_t, rel=1e-9, abs=1e-16)
 
 
-def test_tile_shape_invariance_bitwise():
-    """Every launch shape gives bitwise identical FP64 populations (halo / ring race check)."""
-    c = emulsion_case(130, 45, walls=True, fraction=0.7, seed=3, rmin=5, rmax=9, g=1e-5)
+@pytest.mark.parametrize("walls,storage", [(True, "f64"), (False, "f64"), (False, "f32"), (True, "bf16dev")])
+def test_tile_shape_invariance_bitwise(walls, storage):
+    """Every launch shape (strip width, segment height, march direction of odd segments,
+    ragged strips and segments) gives bitwise identical populations: a halo, ring or
+    direction mistake shows up as a difference."""
+    c = emulsion_case(130, 45, walls=walls, fraction=0.7, seed=3, rmin=5, rmax=9, g=1e-5 if walls else 0.0)
+    c["storage"] = storage
     ref = None
-    for tile in ((64, 1), (64, 7), (128, 3), (256, 16), (256, 45)):
+    for tile in (None, (64, 1), (64, 2), (64, 7), (128, 3), (256, 4), (256, 16), (256, 45)):
         sim = make_sim(c, tile=tile)
         sim.step(12)
         f = sim.checkpoint().cpu().numpy()
