@@ -67,12 +67,16 @@ template <int MODE> struct Codec;
 // per-species reference density.  load/store (layout kernels) convert to and from f; the
 // step works on deviations directly (bload/bstore), which costs nothing and keeps the
 // rounding of each stored value relative to |d_l| instead of |f_l|.
+// L is the type a pulled population is held in between its load and its use (the register
+// FIFO of the step); dec() turns it into the arithmetic type.
 template <> struct Codec<MODE_F64> {
   using S = double;
   using R = double;
+  using L = double;
+  __device__ static R dec(L v) { return v; }
   __device__ static R load(const S *p, R wref) { return *p + wref; }
   __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
-  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff) {
+  __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
@@ -85,9 +89,11 @@ template <> struct Codec<MODE_F64> {
 template <> struct Codec<MODE_F32> {
   using S = float;
   using R = float;
+  using L = float;
+  __device__ static R dec(L v) { return v; }
   __device__ static R load(const S *p, R wref) { return *p + wref; }
   __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
-  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff) {
+  __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
@@ -98,9 +104,12 @@ template <> struct Codec<MODE_F32> {
 };
 
 // BF16: stored value = bf16(d_l), arithmetic in FP32.
+// BF16: the FIFO keeps the raw 16-bit values (two to a register), decoded where used.
 template <> struct Codec<MODE_BF16> {
   using S = uint16_t;
   using R = float;
+  using L = uint16_t;
+  __device__ static R dec(L v) { return decode(v); }
   __device__ static R decode(uint32_t h) { return __uint_as_float(h << 16); }
   __device__ static uint16_t encode(R v) {
     const uint32_t b = __float_as_uint(v);
@@ -111,8 +120,8 @@ template <> struct Codec<MODE_BF16> {
   }
   __device__ static R load(const S *p, R wref) { return decode(*p) + wref; }
   __device__ static void store(S *p, R v, R wref) { *p = encode(v - wref); }
-  __device__ static R bload(Rsrc r, uint32_t voff, uint32_t soff) {
-    return decode(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
   }
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
     __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, voff, soff, 0);
@@ -137,46 +146,36 @@ __device__ inline int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a -
 
 // Where the nine populations pulled into one site come from:
 //   f_l(x, y) = f*_l(x - c_l, y - c_l), or f*_opp(l)(x, y) when (x - c_l, y - c_l) is a wall.
-// A load address is  species base (buffer descriptor) + row offset (SGPR) + lane offset
-// (VGPR).  The lane offset folds in the plane, l * plane_bytes + column bytes of x - c_lx,
-// and is fixed for the whole kernel; only the three row offsets change from row to row.
+// A load address is  species base (buffer descriptor) + row and plane offset (SGPR) + column
+// offset (VGPR).  Only the column bytes of x, x - 1 and x + 1 live in VGPRs, fixed for the
+// whole kernel; the plane and the source row go into the uniform offset.
 struct RowOffs {
   uint32_t m, o, p;  // byte offsets of rows y-1, y, y+1 (or y where reflected)
   bool lo, hi;       // row y-1 / y+1 is a wall
 };
 
-struct LaneOffs {
-  uint32_t ld[9];  // l * plane_bytes + bytes of column x - c_lx
-  uint32_t bb[4];  // (5..8) * plane_bytes + bytes of column x: reflected sources
+struct LaneCols {
+  uint32_t c, m, p;  // bytes of columns x, x - 1, x + 1 (periodic wrap folded in)
 };
 
-__device__ inline LaneOffs lane_offsets(int x, int xm, int xp, uint32_t es, uint32_t plane_b) {
-  LaneOffs o;
-  const uint32_t xb = (uint32_t)x * es, xmb = (uint32_t)xm * es, xpb = (uint32_t)xp * es;
-  const uint32_t colb[9] = {xb, xmb, xb, xpb, xb, xmb, xpb, xpb, xmb};  // column of x - c_lx
-#pragma unroll
-  for (int l = 0; l < 9; ++l) o.ld[l] = (uint32_t)l * plane_b + colb[l];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) o.bb[k] = (uint32_t)(5 + k) * plane_b + xb;
-  return o;
-}
-
 template <class C, int NS>
-__device__ inline void load_pull(const void *base, uint32_t spec_b, const LaneOffs &lo_, const RowOffs &r,
-                                 typename C::R (&f)[NS][9]) {
-  // source of each population: (lane offset, row offset)
+__device__ inline void load_pull(const void *base, uint32_t spec_b, uint32_t plane_b, const LaneCols &col,
+                                 const RowOffs &r, typename C::L (&f)[NS][9]) {
+  // source of each population: (column offset, row + plane offset)
+  const uint32_t P1 = plane_b, P2 = 2 * plane_b, P3 = 3 * plane_b, P4 = 4 * plane_b, P5 = 5 * plane_b,
+                 P6 = 6 * plane_b, P7 = 7 * plane_b, P8 = 8 * plane_b;
   uint32_t vo[9], so[9];
-  vo[0] = lo_.ld[0]; so[0] = r.o;
-  vo[1] = lo_.ld[1]; so[1] = r.o;
-  vo[3] = lo_.ld[3]; so[3] = r.o;
+  vo[0] = col.c; so[0] = r.o;
+  vo[1] = col.m; so[1] = r.o + P1;
+  vo[3] = col.p; so[3] = r.o + P3;
   // c_y = +1 populations come from the row below, or bounce back off the wall below
-  vo[2] = r.lo ? lo_.ld[4] : lo_.ld[2]; so[2] = r.lo ? r.o : r.m;  // reflected: plane 4 at x
-  vo[5] = r.lo ? lo_.bb[2] : lo_.ld[5]; so[5] = r.lo ? r.o : r.m;  // plane 7 at x
-  vo[6] = r.lo ? lo_.bb[3] : lo_.ld[6]; so[6] = r.lo ? r.o : r.m;  // plane 8 at x
+  vo[2] = col.c;                  so[2] = r.lo ? r.o + P4 : r.m + P2;  // reflected: plane 4 at x
+  vo[5] = r.lo ? col.c : col.m;   so[5] = r.lo ? r.o + P7 : r.m + P5;  // plane 7 at x
+  vo[6] = r.lo ? col.c : col.p;   so[6] = r.lo ? r.o + P8 : r.m + P6;  // plane 8 at x
   // c_y = -1 populations come from the row above, or bounce back off the wall above
-  vo[4] = r.hi ? lo_.ld[2] : lo_.ld[4]; so[4] = r.hi ? r.o : r.p;  // plane 2 at x
-  vo[7] = r.hi ? lo_.bb[0] : lo_.ld[7]; so[7] = r.hi ? r.o : r.p;  // plane 5 at x
-  vo[8] = r.hi ? lo_.bb[1] : lo_.ld[8]; so[8] = r.hi ? r.o : r.p;  // plane 6 at x
+  vo[4] = col.c;                  so[4] = r.hi ? r.o + P2 : r.p + P4;  // plane 2 at x
+  vo[7] = r.hi ? col.c : col.p;   so[7] = r.hi ? r.o + P5 : r.p + P7;  // plane 5 at x
+  vo[8] = r.hi ? col.c : col.m;   so[8] = r.hi ? r.o + P6 : r.p + P8;  // plane 6 at x
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const Rsrc rs = make_rsrc(static_cast<const char *>(base) + (uint64_t)s * spec_b, spec_b);
@@ -274,10 +273,11 @@ __device__ inline T wave_sum(T v) {
 // so the memory latency of both load batches overlaps the arithmetic of steps 1 and 5.
 
 template <int MODE, int NS, bool WALLS, int WHAT>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step_kernel(StepArgs a) {
   using C = Codec<MODE>;
   using R = typename C::R;
   using S = typename C::S;
+  using L = typename C::L;
   using V = Vec<R, NS>;
   constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_REDUCE);
   constexpr bool REDUCE = (WHAT == WHAT_STEP_REDUCE || WHAT == WHAT_OBSERVE);
@@ -337,12 +337,10 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int xc = x0 + (col_ok ? tid : 0);
   const uint32_t es = (uint32_t)sizeof(S);
   const uint32_t spec_b = 9u * (uint32_t)a.plane * (uint32_t)sizeof(S);
-  const LaneOffs pcc = lane_offsets(xc, wrapi(xc - 1, lx), wrapi(xc + 1, lx), es, plane_b);
+  const LaneCols pcc = {(uint32_t)xc * es, (uint32_t)wrapi(xc - 1, lx) * es, (uint32_t)wrapi(xc + 1, lx) * es};
   // Store column: lanes past a ragged strip's end write into the row padding (the row
   // pitch is a multiple of the widest strip), which no kernel ever reads.
-  uint32_t sto[9];
-#pragma unroll
-  for (int l = 0; l < 9; ++l) sto[l] = (uint32_t)l * plane_b + (uint32_t)(x0 + tid) * es;
+  const uint32_t sto = (uint32_t)(x0 + tid) * es;
 
   // Halo columns x0-2, x0-1, x0+w, x0+w+1 (ring slots 0, 1, w+2, w+3).  Their 4 x NS x 9
   // pulled populations per lead row ("halo items", item it: column it / (9 NS), species
@@ -370,7 +368,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 
   // Stage 1, interior columns: psi_s and rho_s of lead row r into ring slot `slot` from the
   // pulled populations A of this thread's column.
-  auto ring_row = [&](int slot, int r, const R (&A)[NS][9]) {
+  auto ring_row = [&](int slot, int r, const L (&A)[NS][9]) {
     if (!col_ok) return;
     V ps, rh;
     if (!row_fluid<WALLS>(r, ly)) {
@@ -382,7 +380,10 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     } else {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        rh.v[s] = rref[s] + sum9(A[s]);
+        R a9[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) a9[l] = C::dec(A[s][l]);
+        rh.v[s] = rref[s] + sum9(a9);
         ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
       }
     }
@@ -392,16 +393,16 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 
   // Stage 1, halo columns: load (two items per thread), stage into LDS buffer `buf`, and
   // finish (after a barrier) into ring slot `slot`.
-  auto halo_load = [&](const RowOffs &r, R (&hv)[2]) {
+  auto halo_load = [&](const RowOffs &r, L (&hv)[2]) {
     const Rsrc rs = make_rsrc(src, (uint32_t)NS * spec_b);
 #pragma unroll
     for (int k = 0; k < 2; ++k) hv[k] = C::bload(rs, halo_offset(hitem[k], r), 0u);
   };
-  auto halo_stage = [&](int buf, const R (&hv)[2]) {
+  auto halo_stage = [&](int buf, const L (&hv)[2]) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int it = tid + k * TX;
-      if (it < NI) hstage[buf * NI + it] = hv[k];
+      if (it < NI) hstage[buf * NI + it] = C::dec(hv[k]);
     }
   };
   auto halo_finish = [&](int buf, int slot, int r) {
@@ -435,18 +436,18 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   // input of row y+4 four iterations after loading; five row buffers (the main loop is
   // unrolled by five so their roles rotate statically) mean every population is loaded once
   // per step, a full iteration of arithmetic before its first use.
-  R B[5][NS][9];
-  R HV[2];  // halo items of the lead row in flight
+  L B[5][NS][9];
+  L HV[2];  // halo items of the lead row in flight
 
   // Prologue: ring rows y0-2 .. y0+2 (slots 0..4).  Rows y0 .. y0+2 stay in B[1..3]; the
   // loads of row y0+3 go to B[4] once row y0-1 has been consumed from it.
   {
     constexpr int bufp[5] = {0, 4, 1, 2, 3};
-    R HP[5][2];
+    L HP[5][2];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(y0 + dir * (k - 2), ly), ly, row_b);
-      load_pull<C, NS>(src, spec_b, pcc, pr, B[bufp[k]]);
+      load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, B[bufp[k]]);
       halo_load(pr, HP[k]);
     }
 #pragma unroll
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       halo_stage(k, HP[k]);
       if (k == 1) {
         const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(y0 + 3 * dir, ly), ly, row_b);
-        load_pull<C, NS>(src, spec_b, pcc, pr, B[4]);
+        load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, B[4]);
         halo_load(pr, HV);
       }
     }
@@ -472,8 +473,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   // into the row padding), so every wait covers exactly the batch it needs.  The ring slot
   // written last, (y+3) mod 6, is not among the rows y-2..y+2 that slower waves may still
   // read, and the halo staging buffers alternate between iterations.
-  auto step_row = [&](const int y_in, const int lead_slot_in, R (&FL)[NS][9], const R (&f)[NS][9],
-                      const R (&FR)[NS][9]) {
+  auto step_row = [&](const int y_in, const int lead_slot_in, L (&FL)[NS][9], const L (&fraw)[NS][9],
+                      const L (&FR)[NS][9]) {
     // the row index is uniform; saying so keeps every row offset in SGPRs
     const int y = (int)uni((uint32_t)y_in);
     const int lead_slot = (int)uni((uint32_t)lead_slot_in);
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     {
       const int r4 = dir > 0 ? min(y + 4, ylast) : max(y - 4, ylast);
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r4, ly), ly, row_b);
-      load_pull<C, NS>(src, spec_b, pcc, pr, FL);
+      load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, FL);
       halo_load(pr, HV);
     }
 
@@ -498,6 +499,11 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     // ---- update row y ---------------------------------------------------------------------
     // the ring holds rows y + dir (m - 2), m = 0..4, in slots lead_slot + 1 + m (mod 6): the
     // row at physical offset d is in slot lead_slot + 3 + dir d
+    R f[NS][9];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int l = 0; l < 9; ++l) f[s][l] = C::dec(fraw[s][l]);
     R drho[NS], rho[NS], jx[NS], jy[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -650,7 +656,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
       if (STORE) {
 #pragma unroll
         for (int l = 0; l < 9; ++l)
-          C::bstore(make_rsrc(static_cast<char *>(dst) + (uint64_t)s * spec_b, spec_b), sto[l], uni(rb0), fs[l]);
+          C::bstore(make_rsrc(static_cast<char *>(dst) + (uint64_t)s * spec_b, spec_b), sto,
+                    uni(rb0 + (uint32_t)l * plane_b), fs[l]);
       }
       if (REDUCE && WALLS && col_ok) {
         if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7]));
