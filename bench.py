@@ -90,21 +90,62 @@ def copy_reference(nbytes, steps):
             "kernel": "torch copy_ (float32, contiguous)"}
 
 
-def field_errors(rho, kw, nsteps, orc_fields):
-    """Relative error of rho and u of each GPU storage mode against the oracle after nsteps."""
+def rel_errors(r, u, ref):
+    """Max-norm errors of rho and u relative to the max-norm of the oracle's fields."""
     import numpy as np
+    return {"rho": float(np.abs(r - ref["rho"]).max() / np.abs(ref["rho"]).max()),
+            "u": float(np.abs(u - ref["u"]).max() / np.abs(ref["u"]).max())}
+
+
+def emulsion_errors(rho, kw, ref_by_t):
+    """rho and u of each GPU storage mode against the oracle at the checkpoint times (the
+    emulsion coarsens, so a rounding difference grows with time like any perturbation)."""
     from paper_1402_6019_amd import Sim
     out = {}
     for storage in ("f64", "f32", "bf16dev"):
         sim = Sim(LX, LY, rho, storage=storage, **kw)
-        sim.step(nsteps)
-        r, u = sim.moments()
-        r = r.cpu().numpy()
-        u = u.cpu().numpy()
+        out[storage] = {}
+        for t in sorted(ref_by_t):
+            sim.step(t - sim.time)
+            r, u = sim.moments()
+            out[storage][str(t)] = rel_errors(r.cpu().numpy(), u.cpu().numpy(), ref_by_t[t])
         sim.close()
-        e_r = float(np.abs(r - orc_fields["rho"]).max() / np.abs(orc_fields["rho"]).max())
-        e_u = float(np.abs(u - orc_fields["u"]).max() / np.abs(orc_fields["u"]).max())
-        out[storage] = {"rho_rel_err": e_r, "u_rel_err": e_u}
+    return out
+
+
+def channel_errors(steps=300, window=200):
+    """Confined emulsion in a 256 x 128 channel (walls, wetting, body force 1e-5): rho, u after
+    `steps` steps and the wall stress averaged over the last `window` steps, each GPU storage
+    mode against the oracle."""
+    import numpy as np
+    import lbgen
+    from oracle import Oracle, Params
+    from paper_1402_6019_amd import Sim
+    lx, ly = 256, 128
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.85, seed=4, walls=True, rmin=6, rmax=14)
+    kw = dict(n_species=2, walls=True, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+              body=(1e-5, 0.0), rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0)
+    P = Params(lx=lx, ly=ly, ns=2, walls=1, g1=kw["g1"], g2=kw["g2"], gab=kw["gab"], body=kw["body"],
+               rho_wall=kw["rho_wall"], tau=kw["tau"], psi0=kw["psi0"], rho0=kw["rho0"])
+    orc = Oracle(P, rho_init=rho)
+    orc.step(steps - window)
+    recs = orc.step(window, record=True)
+    ref = orc.fields()
+    ref_w = np.array([recs[:, 4].mean(), recs[:, 5].mean()])
+    out = {"workload": f"confined emulsion {lx}x{ly}, walls + wetting, g = 1e-5, fraction 0.85, seed 4",
+           "steps": steps, "stress_window": window}
+    for storage in ("f64", "f32", "bf16dev"):
+        sim = Sim(lx, ly, rho, storage=storage, rho_ref=(float(rho[0].mean()), float(rho[1].mean())), **kw)
+        sim.step(steps - window)
+        sim.set_reduce_every(1)
+        sim.wall_stress(reset=True)
+        sim.step(window)
+        w = np.array(sim.wall_stress(reset=True))
+        r, u = sim.moments()
+        e = rel_errors(r.cpu().numpy(), u.cpu().numpy(), ref)
+        e["wall_stress"] = float(np.abs(w - ref_w).max() / np.abs(ref_w).max())
+        out[storage] = e
+        sim.close()
     return out
 
 
@@ -115,28 +156,32 @@ def cpu_baseline(rho, kw, budget_s=15.0):
     P = Params(lx=LX, ly=LY, ns=2, walls=0, g1=kw["g1"], g2=kw["g2"], gab=kw["gab"], body=kw["body"],
                tau=kw["tau"], psi0=kw["psi0"], rho0=kw["rho0"])
     orc = Oracle(P, rho_init=rho)
+    refs = {}
     t0 = time.perf_counter()
-    orc.step(2)
-    per = (time.perf_counter() - t0) / 2
+    orc.step(10)
+    per = (time.perf_counter() - t0) / 10
+    refs[10] = orc.fields()
+    orc.step(90)
+    refs[100] = orc.fields()
     n = max(2, int(budget_s / per))
     t0 = time.perf_counter()
     orc.step(n)
     dt = time.perf_counter() - t0
-    steps_total = n + 2
-    fields = orc.fields()
+    refs[100 + n] = orc.fields()
     return {
         "value": LX * LY * n / dt / 1e6,
         "unit": "MLUPS",
         "cores": oracle.get_threads(),
         "kind": "oracle",
-        "sample": f"{n} steps of the same 1024x1024 two-component lattice from the same initial state "
-                  f"({dt:.1f} s, FP64, OpenMP over rows)",
-    }, steps_total, fields
+        "sample": f"{n} steps (steps 100..{100 + n}) of the same 1024x1024 two-component lattice from the "
+                  f"same initial state ({dt:.1f} s, FP64, OpenMP over rows)",
+    }, refs
 
 
-def traffic_from_profile(kernel_hash, storage, steps_unit_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source; otherwise None."""
+def traffic_from_profile(kernel_hash, storage, tile):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a copy of known size) from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source and at the launch shape timed here; otherwise None."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic_emulsion1024.json")
     if not os.path.exists(path):
         return None
@@ -144,7 +189,10 @@ def traffic_from_profile(kernel_hash, storage, steps_unit_bytes):
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_hash or storage not in d.get("storage", {}):
         return None
-    return d["storage"][storage].get("hbm_bytes_per_launch")
+    rec = d["storage"][storage]
+    if list(rec.get("tile", [])) != list(tile):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -177,7 +225,7 @@ def main():
     copy = copy_reference(head["algo_bytes_per_launch"] // 2, min(args.steps, 500))
     roof = {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": head["gbs"] / HBM_PEAK_GBS,
-            "traffic": traffic_from_profile(khash, "f32", head["algo_bytes_per_launch"]),
+            "traffic": traffic_from_profile(khash, "f32", head["tile"]),
             "kernel": "step_kernel<F32, 2 species, periodic>", "bytes_per_lu": 144,
             "copy_ceiling_gbs": copy["gbs"], "frac_of_copy": head["gbs"] / copy["gbs"],
             "note": "footprint 2 x 75.5 MB fits in the 256 MB Infinity Cache"}
@@ -202,10 +250,11 @@ def main():
         "fp64": {"mlups": res["f64"]["mlups"], "ms_per_step": res["f64"]["ms_per_step"],
                  "roofline": {"bound": "hbm", "achieved": res["f64"]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": res["f64"]["gbs"] / HBM_PEAK_GBS, "bytes_per_lu": 288,
-                              "traffic": traffic_from_profile(khash, "f64", res["f64"]["algo_bytes_per_launch"])}},
+                              "traffic": traffic_from_profile(khash, "f64", res["f64"]["tile"])}},
         "bf16dev": {"mlups": res["bf16dev"]["mlups"], "ms_per_step": res["bf16dev"]["ms_per_step"],
                     "roofline": {"bound": "hbm", "achieved": res["bf16dev"]["gbs"], "peak": HBM_PEAK_GBS,
-                                 "unit": "GB/s", "frac": res["bf16dev"]["gbs"] / HBM_PEAK_GBS, "bytes_per_lu": 72}},
+                                 "unit": "GB/s", "frac": res["bf16dev"]["gbs"] / HBM_PEAK_GBS, "bytes_per_lu": 72,
+                                 "traffic": traffic_from_profile(khash, "bf16dev", res["bf16dev"]["tile"])}},
         "speedup_vs_fp64": {"f32": res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"],
                             "bf16dev": res["f64"]["ms_per_step"] / res["bf16dev"]["ms_per_step"]},
         "tiles": {k: v["tile"] for k, v in res.items()},
@@ -213,9 +262,10 @@ def main():
         "kernel_source_hash": khash,
     }
     if not args.no_cpu:
-        base, nsteps, fields = cpu_baseline(rho, kw)
+        base, refs = cpu_baseline(rho, kw)
         out["cpu_baseline"] = base
-        out["error_vs_oracle"] = {"steps": nsteps, **field_errors(rho, kw, nsteps, fields)}
+        out["error_vs_oracle"] = {"emulsion_1024_by_step": emulsion_errors(rho, kw, refs),
+                                  "channel_256x128": channel_errors()}
     print(json.dumps(out), flush=True)
 
 
