@@ -165,11 +165,88 @@ int64_t lb_time(const lb_ctx *ctx);
 int lb_set_tile(lb_ctx *ctx, int32_t tx, int32_t sy);
 int lb_get_tile(const lb_ctx *ctx, int32_t *tx, int32_t *sy);
 
+/* Replay plain steps from captured HIP graphs: with steps > 0 (even) and no reductions
+   (lb_set_reduce_every k = 0), lb_step runs whole groups of `steps` launches as one graph
+   launch on the context's stream and the remainder one by one.  Graphs are captured on first
+   use on a private stream and rebuilt after lb_set_tile / lb_autotune.  steps = 0 turns
+   graphs off.  Host call; results are bitwise those of individual launches. */
+int lb_set_graph(lb_ctx *ctx, int32_t steps);
+
+/* Autotuner: time trial_steps launches of each candidate launch shape (tx in {64, 128, 256},
+   sy from 1 to 64, and the current shape) with HIP events on the context's stream, keep the
+   fastest and return it in *tx, *sy and its time per step in milliseconds in *ms (any
+   output may be NULL).  Trial launches read the current state and write the other
+   population buffer, so the state is unchanged.  Synchronises. */
+int lb_autotune(lb_ctx *ctx, int32_t trial_steps, int32_t *tx, int32_t *sy, double *ms);
+
 /* Message of the last failure on ctx (ctx = NULL: last failure of lb_init in this thread). */
 const char *lb_last_error(const lb_ctx *ctx);
 
 /* Release the context's own buffers (not the caller's). */
 void lb_destroy(lb_ctx *ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * Batches: n independent lattices (e.g. channels of uneven size with their own couplings,
+ * relaxation times and body forces) advanced together by one persistent kernel launch per
+ * time step.  Each instance evolves exactly as it would in its own lb_init context (same
+ * step, bitwise the same per-site arithmetic).  All instances share storage, n_species and
+ * walls; sizes, couplings, tau and psi parameters are per instance.
+ * Ownership and errors as for lb_ctx; lb_batch_last_error(NULL) reports lb_batch_init.
+ * ------------------------------------------------------------------------------------- */
+typedef struct lb_batch lb_batch;
+
+/* Bytes of ONE population buffer holding all n instances (each instance's lb_pop_bytes,
+   rounded up to 256 bytes).  0 for invalid input.  Pure host call. */
+size_t lb_batch_pop_bytes(int32_t n, const lb_lattice *lats);
+
+/* Create a batch.  lats, cpls, psis: host arrays of n; tau: host [n][2]; rho_init: host
+   array of n host pointers, instance i [n_species][ly_i][lx_i].  Validation per instance as
+   in lb_init.  pop_a, pop_b: device buffers of pop_bytes >= lb_batch_pop_bytes.
+   Synchronises the stream. */
+int lb_batch_init(lb_batch **out, int32_t n, const lb_lattice *lats, const lb_couplings *cpls, const double *tau,
+                  const lb_psi_params *psis, const double *const *rho_init, void *pop_a, void *pop_b,
+                  size_t pop_bytes, void *hip_stream);
+
+/* Advance every instance by n >= 0 steps: one launch per step over the tiles of all
+   instances (plus one reduction launch on reduced steps).  Asynchronous. */
+int lb_batch_step(lb_batch *b, int64_t n);
+
+/* As lb_set_reduce_every, for every instance. */
+int lb_batch_set_reduce_every(lb_batch *b, int32_t k);
+
+/* As lb_set_graph: graphs of `steps` batch launches. */
+int lb_batch_set_graph(lb_batch *b, int32_t steps);
+
+/* Tile shape of all instances (tx in {64, 128, 256}, sy >= 1) and the persistent grid:
+   grid workgroups take the tiles in rounds (grid = 0: one workgroup per tile).  Rebuilds the
+   tile table.  Synchronises. */
+int lb_batch_set_tile(lb_batch *b, int32_t tx, int32_t sy, int32_t grid);
+int lb_batch_get_tile(const lb_batch *b, int32_t *tx, int32_t *sy, int32_t *grid);
+
+/* Autotuner over tx, sy in {2, ..., 32} and grid in {resident workgroups, one per tile}, as
+   lb_autotune; out[3] = (tx, sy, grid) and *ms (either may be NULL).  Synchronises. */
+int lb_batch_autotune(lb_batch *b, int32_t trial_steps, int32_t out[3], double *ms);
+
+/* Moments of instance i, as lb_moments (device outputs [n_species][ly_i][lx_i] and
+   [2][ly_i][lx_i]).  Asynchronous. */
+int lb_batch_moments(lb_batch *b, int32_t i, void *rho, void *u, int32_t dtype);
+
+/* FP64 totals of every instance (host out[n][5]: mass A, mass B, momentum x, momentum y,
+   flow rate), as lb_totals.  Synchronises. */
+int lb_batch_totals(lb_batch *b, double *out);
+
+/* Time-averaged wall stress of every instance (host out[n][2]), as lb_wall_stress.
+   Channel batches only.  Synchronises. */
+int lb_batch_wall_stress(lb_batch *b, double *out, int32_t reset);
+
+/* Checkpoint / restore instance i in the canonical FP64 layout, as lb_checkpoint /
+   lb_restore. */
+int lb_batch_checkpoint(lb_batch *b, int32_t i, void *dst_f64);
+int lb_batch_restore(lb_batch *b, int32_t i, const void *src_f64);
+
+int64_t lb_batch_time(const lb_batch *b);
+const char *lb_batch_last_error(const lb_batch *b);
+void lb_batch_destroy(lb_batch *b);
 
 #ifdef __cplusplus
 }

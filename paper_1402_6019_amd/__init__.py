@@ -14,7 +14,7 @@ from ._binding import LB_BF16DEV, LB_F32, LB_F64, LbError
 
 STORAGE = {"f64": LB_F64, "f32": LB_F32, "bf16dev": LB_BF16DEV}
 
-__all__ = ["Sim", "LbError", "STORAGE", "default_weights"]
+__all__ = ["Sim", "Batch", "LbError", "STORAGE", "default_weights"]
 
 
 def default_weights():
@@ -28,6 +28,34 @@ def _pair(v):
         return (float(v), float(v))
     v = tuple(float(x) for x in v)
     return v if len(v) == 2 else (v[0], v[0])
+
+
+def _couplings(g1=(0.0, 0.0), g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0), rho_wall=(0.0, 0.0), w=None, p=None, t=None,
+               cross_psi=False):
+    cpl = B.default_couplings()
+    cpl.g1[:] = _pair(g1)
+    cpl.g2[:] = _pair(g2)
+    cpl.g_ab = float(gab)
+    if w is not None:
+        cpl.w[:] = [float(v) for v in w]
+    if p is not None:
+        cpl.p[:] = [float(v) for v in p]
+    if t is not None:
+        cpl.t[:] = [float(v) for v in t]
+    cpl.body_force[:] = _pair(body) if len(body) == 2 else body
+    cpl.rho_wall[:] = _pair(rho_wall)
+    cpl.cross_uses_psi = 1 if cross_psi else 0
+    return cpl
+
+
+def _density(rho_init, ns, ly, lx):
+    return np.ascontiguousarray(np.broadcast_to(rho_init, (ns, ly, lx)), dtype=np.float64)
+
+
+def _psi_params(psi0, rho0, rho_ref, rho):
+    if rho_ref is None:  # deviations from the mean initial density of each species
+        rho_ref = tuple(float(r.mean()) for r in rho) + (0.0,) * (2 - rho.shape[0])
+    return B.LbPsiParams(float(psi0), float(rho0), (ctypes.c_double * 2)(*_pair(rho_ref)))
 
 
 class Sim:
@@ -51,25 +79,11 @@ class Sim:
         self.lx, self.ly, self.ns = int(lx), int(ly), int(n_species)
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         self.lat = B.LbLattice(self.lx, self.ly, self.ns, 1 if walls else 0, self.storage)
-        cpl = B.default_couplings()
-        cpl.g1[:] = _pair(g1)
-        cpl.g2[:] = _pair(g2)
-        cpl.g_ab = float(gab)
-        if w is not None:
-            cpl.w[:] = [float(v) for v in w]
-        if p is not None:
-            cpl.p[:] = [float(v) for v in p]
-        if t is not None:
-            cpl.t[:] = [float(v) for v in t]
-        cpl.body_force[:] = _pair(body) if len(body) == 2 else body
-        cpl.rho_wall[:] = _pair(rho_wall)
-        cpl.cross_uses_psi = 1 if cross_psi else 0
+        cpl = _couplings(g1, g2, gab, body, rho_wall, w, p, t, cross_psi)
         self.cpl = cpl
         self.tau = (ctypes.c_double * 2)(*_pair(tau))
-        rho = np.ascontiguousarray(np.broadcast_to(rho_init, (self.ns, self.ly, self.lx)), dtype=np.float64)
-        if rho_ref is None:  # deviations from the mean initial density of each species
-            rho_ref = tuple(float(rho[s].mean()) for s in range(self.ns)) + (0.0,) * (2 - self.ns)
-        self.psi = B.LbPsiParams(float(psi0), float(rho0), (ctypes.c_double * 2)(*_pair(rho_ref)))
+        rho = _density(rho_init, self.ns, self.ly, self.lx)
+        self.psi = _psi_params(psi0, rho0, rho_ref, rho)
         nbytes = B.pop_bytes(self.lat)
         if nbytes == 0:
             raise LbError(B.LB_EINVAL, "invalid lattice")
@@ -122,6 +136,16 @@ class Sim:
         self._chk(self._lib.lb_get_tile(self._h, ctypes.byref(tx), ctypes.byref(sy)))
         return tx.value, sy.value
 
+    def set_graph(self, steps):
+        """Replay plain steps in captured HIP graphs of `steps` launches (0: off)."""
+        self._chk(self._lib.lb_set_graph(self._h, int(steps)))
+
+    def autotune(self, trial_steps=20):
+        """Pick the fastest launch shape by timing; returns ((tx, sy), ms per step)."""
+        tx, sy, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._chk(self._lib.lb_autotune(self._h, int(trial_steps), ctypes.byref(tx), ctypes.byref(sy), ctypes.byref(ms)))
+        return (tx.value, sy.value), ms.value
+
     def moments(self, dtype=None):
         """(rho [ns, ly, lx], u [2, ly, lx]) device tensors of the current state."""
         torch = self.torch
@@ -157,3 +181,134 @@ class Sim:
             raise ValueError("populations must have shape (n_species, 9, ly, lx)")
         self._keep = f  # keep alive until the asynchronous restore kernel has read it
         self._chk(self._lib.lb_restore(self._h, ctypes.c_void_p(f.data_ptr())))
+
+
+class Batch:
+    """Many independent lattices stepped together by one persistent launch per time step.
+
+    instances: list of dicts with the keyword arguments of Sim (lx, ly, rho_init, and any of
+    g1, g2, gab, body, rho_wall, tau, psi0, rho0, rho_ref, w, p, t, cross_psi); storage,
+    n_species and walls are common to all instances.
+    """
+
+    def __init__(self, instances, n_species=2, walls=True, storage="f32", device="cuda"):
+        import torch
+        self._lib = B.load()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.n = len(instances)
+        self.ns = int(n_species)
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        n = self.n
+        self.lats = (B.LbLattice * n)()
+        self.cpls = (B.LbCouplings * n)()
+        self.psis = (B.LbPsiParams * n)()
+        self.taus = (ctypes.c_double * (2 * n))()
+        self._rho = []
+        self.shapes = []
+        for i, inst in enumerate(instances):
+            lx, ly = int(inst["lx"]), int(inst["ly"])
+            self.shapes.append((lx, ly))
+            self.lats[i] = B.LbLattice(lx, ly, self.ns, 1 if walls else 0, self.storage)
+            self.cpls[i] = _couplings(inst.get("g1", (0.0, 0.0)), inst.get("g2", (0.0, 0.0)), inst.get("gab", 0.0),
+                                      inst.get("body", (0.0, 0.0)), inst.get("rho_wall", (0.0, 0.0)), inst.get("w"),
+                                      inst.get("p"), inst.get("t"), inst.get("cross_psi", False))
+            tau = _pair(inst.get("tau", (1.0, 1.0)))
+            self.taus[2 * i], self.taus[2 * i + 1] = tau
+            rho = _density(inst["rho_init"], self.ns, ly, lx)
+            self._rho.append(rho)
+            self.psis[i] = _psi_params(inst.get("psi0", 1.0), inst.get("rho0", 1.0), inst.get("rho_ref"), rho)
+        nbytes = self._lib.lb_batch_pop_bytes(n, self.lats)
+        if nbytes == 0:
+            raise LbError(B.LB_EINVAL, "invalid lattice in batch")
+        self.pop_bytes = nbytes
+        self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                                        for r in self._rho])
+        h = ctypes.c_void_p()
+        rc = self._lib.lb_batch_init(ctypes.byref(h), n, self.lats, self.cpls, self.taus, self.psis, ptrs,
+                                     ctypes.c_void_p(self.pop_a.data_ptr()), ctypes.c_void_p(self.pop_b.data_ptr()),
+                                     nbytes, ctypes.c_void_p(self.stream.cuda_stream))
+        B.check_batch(rc, None)
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lb_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        return B.check_batch(rc, self._h)
+
+    @property
+    def time(self):
+        return self._lib.lb_batch_time(self._h)
+
+    def step(self, n=1):
+        self._chk(self._lib.lb_batch_step(self._h, int(n)))
+
+    def set_reduce_every(self, k):
+        self._chk(self._lib.lb_batch_set_reduce_every(self._h, int(k)))
+
+    def set_graph(self, steps):
+        self._chk(self._lib.lb_batch_set_graph(self._h, int(steps)))
+
+    def set_tile(self, tx, sy, grid=0):
+        self._chk(self._lib.lb_batch_set_tile(self._h, int(tx), int(sy), int(grid)))
+
+    def get_tile(self):
+        tx, sy, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._chk(self._lib.lb_batch_get_tile(self._h, ctypes.byref(tx), ctypes.byref(sy), ctypes.byref(g)))
+        return tx.value, sy.value, g.value
+
+    def autotune(self, trial_steps=10):
+        out = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double()
+        self._chk(self._lib.lb_batch_autotune(self._h, int(trial_steps), out, ctypes.byref(ms)))
+        return tuple(out), ms.value
+
+    def moments(self, i, dtype=None):
+        torch = self.torch
+        dtype = dtype or torch.float64
+        lx, ly = self.shapes[i]
+        rho = torch.empty((self.ns, ly, lx), dtype=dtype, device=self.device)
+        u = torch.empty((2, ly, lx), dtype=dtype, device=self.device)
+        code = B.LB_OUT_F32 if dtype == torch.float32 else B.LB_OUT_F64
+        self._chk(self._lib.lb_batch_moments(self._h, int(i), ctypes.c_void_p(rho.data_ptr()),
+                                             ctypes.c_void_p(u.data_ptr()), code))
+        return rho, u
+
+    def totals(self):
+        """[n, 5] FP64: mass A, mass B, momentum x, momentum y, flow rate."""
+        out = np.zeros((self.n, 5))
+        self._chk(self._lib.lb_batch_totals(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def wall_stress(self, reset=False):
+        out = np.zeros((self.n, 2))
+        self._chk(self._lib.lb_batch_wall_stress(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 1 if reset else 0))
+        return out
+
+    def checkpoint(self, i):
+        lx, ly = self.shapes[i]
+        f = self.torch.empty((self.ns, 9, ly, lx), dtype=self.torch.float64, device=self.device)
+        self._chk(self._lib.lb_batch_checkpoint(self._h, int(i), ctypes.c_void_p(f.data_ptr())))
+        return f
+
+    def restore(self, i, f):
+        lx, ly = self.shapes[i]
+        f = self.torch.as_tensor(f, dtype=self.torch.float64, device=self.device).contiguous()
+        if tuple(f.shape) != (self.ns, 9, ly, lx):
+            raise ValueError("populations must have shape (n_species, 9, ly, lx)")
+        self._keep = f
+        self._chk(self._lib.lb_batch_restore(self._h, int(i), ctypes.c_void_p(f.data_ptr())))

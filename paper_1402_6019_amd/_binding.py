@@ -60,8 +60,28 @@ SIGNATURES = {
     "lb_time": (_i64, [_vp]),
     "lb_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
     "lb_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "lb_set_graph": (ctypes.c_int, [_vp, _i32]),
+    "lb_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]),
     "lb_last_error": (ctypes.c_char_p, [_vp]),
     "lb_destroy": (None, [_vp]),
+    # batches
+    "lb_batch_pop_bytes": (_sz, [_i32, ctypes.POINTER(LbLattice)]),
+    "lb_batch_init": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(LbLattice), ctypes.POINTER(LbCouplings),
+                                     _dp, ctypes.POINTER(LbPsiParams), ctypes.POINTER(_dp), _vp, _vp, _sz, _vp]),
+    "lb_batch_step": (ctypes.c_int, [_vp, _i64]),
+    "lb_batch_set_reduce_every": (ctypes.c_int, [_vp, _i32]),
+    "lb_batch_set_graph": (ctypes.c_int, [_vp, _i32]),
+    "lb_batch_set_tile": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
+    "lb_batch_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "lb_batch_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), _dp]),
+    "lb_batch_moments": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32]),
+    "lb_batch_totals": (ctypes.c_int, [_vp, _dp]),
+    "lb_batch_wall_stress": (ctypes.c_int, [_vp, _dp, _i32]),
+    "lb_batch_checkpoint": (ctypes.c_int, [_vp, _i32, _vp]),
+    "lb_batch_restore": (ctypes.c_int, [_vp, _i32, _vp]),
+    "lb_batch_time": (_i64, [_vp]),
+    "lb_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "lb_batch_destroy": (None, [_vp]),
 }
 
 
@@ -88,6 +108,13 @@ def load():
 def check(rc, ctx=None):
     if rc != LB_OK:
         msg = load().lb_last_error(ctx)
+        raise LbError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def check_batch(rc, b=None):
+    if rc != LB_OK:
+        msg = load().lb_batch_last_error(b)
         raise LbError(rc, msg.decode() if msg else "")
     return rc
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblb355.so")
-SOURCES = ["lb_kernels.hip", "lb_api.cpp"]
+SOURCES = ["lb_kernels.hip", "lb_api.cpp", "lb_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -23,6 +23,9 @@ FLAGS = [
     "-shared",
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: the kernels write their fused multiply-adds explicitly, so
+    # every kernel and launch shape rounds identically
+    "-ffp-contract=off",
     "-Wall",
     "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"),

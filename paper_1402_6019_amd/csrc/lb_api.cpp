@@ -12,20 +12,17 @@
 #include <string>
 
 #include "../../include/lb.h"
+#include "lb_host.hpp"
 #include "lb_internal.hpp"
 #include "lb_tables.hpp"
 
 using namespace lb355;
+using namespace lb355::host;
 
 namespace {
 
 thread_local std::string g_init_error;
 
-constexpr int kPitchAlign = 256;  // elements: a multiple of the widest strip (see the step kernel's stores)
-constexpr int kMaxBlocks = 1 << 20;
-
-size_t elem_size(int storage) { return storage == LB_F64 ? 8 : (storage == LB_F32 ? 4 : 2); }
-int row_pitch(int lx) { return (lx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
 
 }  // namespace
 
@@ -52,6 +49,7 @@ struct lb_ctx {
   hipEvent_t ev = nullptr;
   bool check_pending = false;
   bool unstable = false;
+  GraphCache graph;  // graph.steps > 0: plain steps are replayed from captured graphs
   std::string err;
 };
 
@@ -86,27 +84,19 @@ int ensure_partials(lb_ctx *c, int nb) {
 }
 
 void fill_step_args(const lb_ctx *c, StepArgs &a) {
-  std::memset(&a, 0, sizeof(a));
-  a.plane = c->plane;
-  a.lx = c->lat.lx;
-  a.ly = c->lat.ly;
-  a.pitch = c->pitch;
-  a.sy = c->sy;
-  a.cross_psi = c->cpl.cross_uses_psi;
-  for (int s = 0; s < 2; ++s) {
-    for (int q = 0; q < 5; ++q) a.K[s][q] = c->cpl.g1[s] * c->cpl.w[q] + c->cpl.g2[s] * c->cpl.p[q];
-    a.tau[s] = c->tau[s];
-    a.omega[s] = 1.0 / c->tau[s];
-    a.rho_w[s] = c->cpl.rho_wall[s];
-    a.psi_w[s] = c->psi.psi0 * (1.0 - std::exp(-c->cpl.rho_wall[s] / c->psi.rho0));
-    a.rho_ref[s] = c->psi.rho_ref[s];
-  }
-  a.T[0] = c->cpl.g_ab * c->cpl.t[0];
-  a.T[1] = c->cpl.g_ab * c->cpl.t[1];
-  a.body[0] = c->cpl.body_force[0];
-  a.body[1] = c->cpl.body_force[1];
-  a.psi0 = c->psi.psi0;
-  a.irho0 = 1.0 / c->psi.rho0;
+  a = make_step_args(c->lat, c->cpl, c->psi, c->tau, c->pitch, c->plane, c->sy);
+}
+
+// One plain step launch (no reductions) from buffer `from` to the other one, on stream st.
+hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st) {
+  int nseg = 0;
+  const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
+  StepArgs a;
+  fill_step_args(c, a);
+  a.nseg = nseg;
+  a.src = c->pop[from];
+  a.dst = c->pop[from ^ 1];
+  return launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
 }
 
 // One launch of the fused kernel on the current buffer.
@@ -152,40 +142,6 @@ int poll_health(lb_ctx *c, bool wait) {
   return LB_OK;
 }
 
-int validate(const lb_lattice *lat, const lb_couplings *cpl, const double tau[2], const lb_psi_params *psi,
-             std::string &msg) {
-  if (!lat || !cpl || !tau || !psi) { msg = "null argument"; return LB_EINVAL; }
-  if (lat->lx < 5 || lat->ly < 5) { msg = "lx and ly must be >= 5"; return LB_EINVAL; }
-  if (lat->ly > 65535 || (long long)lat->lx * lat->ly > (1LL << 31) / 16) {
-    msg = "lattice too large (ly <= 65535, lx * ly <= 2^27)";
-    return LB_EINVAL;
-  }
-  if (lat->n_species != 1 && lat->n_species != 2) { msg = "n_species must be 1 or 2"; return LB_EINVAL; }
-  if (lat->walls != 0 && lat->walls != 1) { msg = "walls must be 0 or 1"; return LB_EINVAL; }
-  if (lat->storage < LB_F64 || lat->storage > LB_BF16DEV) { msg = "unknown storage"; return LB_EINVAL; }
-  for (int s = 0; s < lat->n_species; ++s) {
-    if (!(tau[s] > 0.5) || !std::isfinite(tau[s])) { msg = "tau must be finite and > 1/2"; return LB_EINVAL; }
-    if (!std::isfinite(cpl->g1[s]) || !std::isfinite(cpl->g2[s]) || !std::isfinite(cpl->rho_wall[s]) ||
-        !std::isfinite(psi->rho_ref[s])) {
-      msg = "non-finite coupling";
-      return LB_EINVAL;
-    }
-    if (lat->walls && !(cpl->rho_wall[s] >= 0.0)) { msg = "rho_wall must be >= 0"; return LB_EINVAL; }
-  }
-  if (!std::isfinite(cpl->g_ab) || !std::isfinite(cpl->body_force[0]) || !std::isfinite(cpl->body_force[1])) {
-    msg = "non-finite coupling";
-    return LB_EINVAL;
-  }
-  for (int q = 0; q < 5; ++q)
-    if (!std::isfinite(cpl->w[q]) || !std::isfinite(cpl->p[q])) { msg = "non-finite weight"; return LB_EINVAL; }
-  if (!std::isfinite(cpl->t[0]) || !std::isfinite(cpl->t[1])) { msg = "non-finite weight"; return LB_EINVAL; }
-  if (!(psi->psi0 > 0.0) || !(psi->rho0 > 0.0) || !std::isfinite(psi->psi0) || !std::isfinite(psi->rho0)) {
-    msg = "psi0 and rho0 must be finite and > 0";
-    return LB_EINVAL;
-  }
-  if (cpl->cross_uses_psi != 0 && cpl->cross_uses_psi != 1) { msg = "cross_uses_psi must be 0 or 1"; return LB_EINVAL; }
-  return LB_OK;
-}
 
 // Default launch shape: the widest strip the lattice fills, and segments sized so that the
 // whole grid is resident at once (workgroups = resident workgroups per CU x CUs, at most):
@@ -249,27 +205,14 @@ int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const 
   c->psi = *psi;
   c->tau[0] = tau[0];
   c->tau[1] = lat->n_species == 2 ? tau[1] : tau[0];
-  if (lat->storage == LB_F64) {  // FP64 stores plain populations: checkpoint/restore stay bit-exact
-    c->psi.rho_ref[0] = c->psi.rho_ref[1] = 0.0;
-  }
-  if (lat->n_species == 1) {  // single component: no cross term, second species unused
-    c->cpl.g_ab = 0.0;
-    c->cpl.g1[1] = c->cpl.g2[1] = 0.0;
-    c->cpl.rho_wall[1] = 0.0;
-    c->psi.rho_ref[1] = 0.0;
-  }
+  normalise(c->lat, c->cpl, c->psi, c->tau);
   c->pop[0] = pop_a;
   c->pop[1] = pop_b;
   c->pop_bytes = pop_bytes;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->pitch = row_pitch(lat->lx);
   c->plane = (long long)lat->ly * c->pitch;
-  {
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
-      c->n_cu = ncu;
-  }
+  c->n_cu = device_cu_count();
   default_tile(c);
 
   hipError_t e;
@@ -316,6 +259,19 @@ int lb_step(lb_ctx *c, int64_t n) {
   int rc = poll_health(c, false);
   if (rc) return rc;
   bool reduced = false;
+  // Without reductions, whole graphs of graph.steps launches (an even number: the state
+  // returns to the same buffer) are replayed; the rest is launched one by one.
+  if (c->graph.steps > 0 && c->reduce_every == 0) {
+    while (n >= c->graph.steps) {
+      hipGraphExec_t g = nullptr;
+      const int from = c->cur;
+      hipError_t e = c->graph.get(from, [&](int k, hipStream_t st) { return launch_plain_step(c, from ^ (k & 1), st); }, &g);
+      if (e == hipSuccess) e = hipGraphLaunch(g, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "step graph");
+      c->t += c->graph.steps;
+      n -= c->graph.steps;
+    }
+  }
   for (int64_t k = 0; k < n; ++k) {
     const bool red = c->reduce_every > 0 && (c->t % c->reduce_every) == 0;
     rc = run_step_kernel(c, red ? WHAT_STEP_REDUCE : WHAT_STEP, nullptr, nullptr, 0);
@@ -444,6 +400,56 @@ int lb_set_tile(lb_ctx *c, int32_t tx, int32_t sy) {
   if (grid_blocks(c, tx, sy, nullptr) > kMaxBlocks) return fail(c, LB_EINVAL, "too many workgroups");
   c->tx = tx;
   c->sy = std::min<int32_t>(sy, c->lat.ly);
+  c->graph.clear();  // captured launches carry the old shape
+  return LB_OK;
+}
+
+int lb_set_graph(lb_ctx *c, int32_t steps) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (steps < 0 || (steps & 1)) return fail(c, LB_EINVAL, "graph steps must be even and >= 0");
+  c->graph.clear();
+  c->graph.steps = steps;
+  return LB_OK;
+}
+
+int lb_autotune(lb_ctx *c, int32_t trial_steps, int32_t *tx_out, int32_t *sy_out, double *ms_out) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (trial_steps < 1) return fail(c, LB_EINVAL, "trial_steps must be >= 1");
+  int rc = poll_health(c, true);
+  if (rc) return rc;
+  // Every trial launch reads the current state and writes the other buffer, which holds
+  // nothing needed: the state is the same before and after tuning.
+  const int tx0 = c->tx, sy0 = c->sy;
+  int best_tx = tx0, best_sy = sy0;
+  double best = -1.0;
+  const int txs[3] = {64, 128, 256};
+  const int sys[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
+  auto trial = [&](int tx, int sy) -> int {
+    if (sy > c->lat.ly || grid_blocks(c, tx, sy, nullptr) > kMaxBlocks) return LB_OK;
+    c->tx = tx;
+    c->sy = sy;
+    const double ms = time_launches(c->stream, 2, trial_steps, [&]() { return launch_plain_step(c, c->cur, c->stream); });
+    if (ms < 0.0) return hip_fail(c, hipGetLastError(), "autotune trial");
+    if (best < 0.0 || ms < best) {
+      best = ms;
+      best_tx = tx;
+      best_sy = sy;
+    }
+    return LB_OK;
+  };
+  rc = trial(tx0, sy0);  // the default shape competes too
+  for (int tx : txs) {
+    if (tx > 64 && tx / 2 >= c->lat.lx) continue;  // wider than the lattice needs
+    for (int sy : sys)
+      if (!rc && !(tx == tx0 && sy == sy0)) rc = trial(tx, sy);
+  }
+  c->tx = rc ? tx0 : best_tx;
+  c->sy = rc ? sy0 : best_sy;
+  c->graph.clear();
+  if (rc) return rc;
+  if (tx_out) *tx_out = c->tx;
+  if (sy_out) *sy_out = c->sy;
+  if (ms_out) *ms_out = best;
   return LB_OK;
 }
 
@@ -465,6 +471,7 @@ void lb_destroy(lb_ctx *c) {
   if (c->d_acc) (void)hipFree(c->d_acc);
   if (c->h_acc) (void)hipHostFree(c->h_acc);
   if (c->ev) (void)hipEventDestroy(c->ev);
+  c->graph.destroy();
   delete c;
 }
 

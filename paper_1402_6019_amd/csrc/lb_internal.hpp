@@ -40,7 +40,34 @@ struct StepArgs {
   double tau[2], omega[2];
   double psi0, irho0;
   double rho_w[2], psi_w[2];  // wall ghost rows (channel)
-  double rho_ref[2];          // BF16 deviation reference
+  double rho_ref[2];          // FP32 / BF16 deviation reference
+  long long offset;           // batch: byte offset of this instance in each population buffer
+};
+
+// Batched launches: one tile of one instance.
+struct TileDesc {
+  int inst;   // instance index (into BatchArgs::inst)
+  int strip;  // strip of blockDim.x columns
+  int seg;    // segment of StepArgs::sy rows
+  int part;   // row of reduction partials this tile writes
+};
+
+// Kernel arguments of the batched step: tiles [tile0, tile0 + ntiles) of the table.
+struct BatchArgs {
+  const StepArgs *inst;  // [n] per-instance arguments (device)
+  const TileDesc *tiles; // tile table (device)
+  int tile0, ntiles;
+  const char *src;       // population buffers holding every instance at StepArgs::offset
+  char *dst;
+  double *partials;      // [tiles][RED_N]
+  void *out_rho, *out_u; // WHAT_MOMENTS (the launch then covers one instance)
+  int out_f32;
+};
+
+// Second reduction pass of one batch instance: partial rows [p0, p0 + n).
+struct ReduceJob {
+  int p0, n;
+  double inv_lx;
 };
 
 // Arguments of the layout kernels (init / checkpoint / restore).
@@ -62,6 +89,11 @@ hipError_t launch_checkpoint(int mode, int walls, const LayoutArgs &a, hipStream
 hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t st);
 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+
+hipError_t launch_batch_step(int mode, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
+                             hipStream_t st);
+hipError_t launch_batch_reduce(const double *partials, const ReduceJob *jobs, int njobs, double *totals, double *acc,
+                               int accumulate, hipStream_t st);
 
 size_t step_lds_bytes(int mode, int ns, int tx);
 // Workgroups of tx threads of the plain step kernel that one compute unit holds at once.

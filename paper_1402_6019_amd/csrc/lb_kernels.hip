@@ -245,6 +245,12 @@ __device__ inline uint32_t halo_offset(const HaloItem &h, const RowOffs &r) {
   return (bb & (h.reflected + r.o)) | (~bb & (h.direct + row));
 }
 
+// Fused multiply-add where the arithmetic asks for one.  Device code is compiled without
+// floating-point contraction, so every rounding is fixed by the source: every kernel and
+// every unrolled copy of the row update computes bitwise the same result.
+__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <typename R>
 __device__ inline R sum9(const R f[9]) {
   R r = f[0];
@@ -272,8 +278,13 @@ __device__ inline T wave_sum(T v) {
 //   5. force + collision of row y from the ring and the stage-2 registers, store
 // so the memory latency of both load batches overlaps the arithmetic of steps 1 and 5.
 
+// One tile: strip `strip` (tx = blockDim.x columns) and segment `seg` (a.sy rows) of the
+// lattice described by a, read from src and written to dst.  part: this tile's row of
+// reduction partials; out_*: moments output (WHAT_MOMENTS).
 template <int MODE, int NS, bool WALLS, int WHAT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step_kernel(StepArgs a) {
+__device__ __forceinline__ void run_tile(const StepArgs &a, const void *const src, void *const dst, const int strip,
+                                         const int seg, double *const part, void *const out_rho,
+                                         void *const out_u, const int out_f32) {
   using C = Codec<MODE>;
   using R = typename C::R;
   using S = typename C::S;
@@ -288,10 +299,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   V *rho_ring = psi_ring + 6 * W4;                   // [6][W4] (two species only)
   __shared__ double red_lds[4][RED_N];
 
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int nstrip = (int)gridDim.x / a.nseg;
-  const int seg = logical / nstrip;
-  const int strip = logical - seg * nstrip;
   const int lx = a.lx, ly = a.ly;
   // Layout [species][y][l][pitch]: the nine planes of a species are interleaved row by row,
   // so one row of all nine planes is a single contiguous run (fewer, longer DRAM streams
@@ -329,8 +336,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   const R T1 = R(a.T[0]), T2 = R(a.T[1]);
   const R gx = R(a.body[0]), gy = R(a.body[1]);
   const R psi0 = R(a.psi0), nirho0 = R(-a.irho0);
-  const void *const src = a.src;
-  void *const dst = a.dst;
 
   // Interior column of this thread (ring slot tid + 2).
   const bool col_ok = tid < w;
@@ -542,12 +547,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
       const R da = qa.v[s] - qA.v[s], db = qb.v[s] - qB.v[s];
       const R dc = qc.v[s] - qC.v[s], dd = qd.v[s] - qD.v[s];
       const R ea = d8a.v[s] - d8A.v[s], eb = d8b.v[s] - d8B.v[s];
-      const R sx = K1[s] * dE + K2[s] * (dd1 + dd2) + K4[s] * d4x + K5[s] * (R(2) * (da + db) + (dc + dd)) +
-                   K8[s] * (ea + eb);
-      const R sy = K1[s] * dN + K2[s] * (dd1 - dd2) + K4[s] * d4y + K5[s] * ((da - db) + R(2) * (dc - dd)) +
-                   K8[s] * (ea - eb);
-      Fx[s] = -pc.v[s] * sx + rho[s] * gx;
-      Fy[s] = -pc.v[s] * sy + rho[s] * gy;
+      const R sx = fmadd(K1[s], dE, fmadd(K2[s], dd1 + dd2, fmadd(K4[s], d4x,
+                   fmadd(K5[s], R(2) * (da + db) + (dc + dd), K8[s] * (ea + eb)))));
+      const R sy = fmadd(K1[s], dN, fmadd(K2[s], dd1 - dd2, fmadd(K4[s], d4y,
+                   fmadd(K5[s], (da - db) + R(2) * (dc - dd), K8[s] * (ea - eb)))));
+      Fx[s] = fmadd(-pc.v[s], sx, rho[s] * gx);
+      Fy[s] = fmadd(-pc.v[s], sy, rho[s] * gy);
     }
     if (NS == 2) {
       // A-B repulsion over the first belt between the densities (or psi) of both species.
@@ -569,10 +574,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
       for (int s = 0; s < NS; ++s) {
         const int o = 1 - s;
         const R t1 = xne.v[o] - xsw.v[o], t2 = xse.v[o] - xnw.v[o];
-        const R cx = T1 * (xe.v[o] - xw.v[o]) + T2 * (t1 + t2);
-        const R cy = T1 * (xn.v[o] - xs.v[o]) + T2 * (t1 - t2);
-        Fx[s] -= c0.v[s] * cx;
-        Fy[s] -= c0.v[s] * cy;
+        const R cx = fmadd(T1, xe.v[o] - xw.v[o], T2 * (t1 + t2));
+        const R cy = fmadd(T1, xn.v[o] - xs.v[o], T2 * (t1 - t2));
+        Fx[s] = fmadd(-c0.v[s], cx, Fx[s]);
+        Fy[s] = fmadd(-c0.v[s], cy, Fy[s]);
       }
     }
 
@@ -580,9 +585,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
     R nux = jx[0] * om[0], nuy = jy[0] * om[0], den = rho[0] * om[0];
 #pragma unroll
     for (int s = 1; s < NS; ++s) {
-      nux += jx[s] * om[s];
-      nuy += jy[s] * om[s];
-      den += rho[s] * om[s];
+      nux = fmadd(jx[s], om[s], nux);
+      nuy = fmadd(jy[s], om[s], nuy);
+      den = fmadd(rho[s], om[s], den);
     }
     const R iden = C::rcp(den);
     const R upx = nux * iden, upy = nuy * iden;
@@ -597,21 +602,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
       }
       const size_t site = (size_t)y * lx + xc;
       const size_t nsite = (size_t)lx * ly;
-      if (a.out_rho) {
+      if (out_rho) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          if (a.out_f32) static_cast<float *>(a.out_rho)[s * nsite + site] = float(rho[s]);
-          else static_cast<double *>(a.out_rho)[s * nsite + site] = double(rho[s]);
+          if (out_f32) static_cast<float *>(out_rho)[s * nsite + site] = float(rho[s]);
+          else static_cast<double *>(out_rho)[s * nsite + site] = double(rho[s]);
         }
       }
-      if (a.out_u) {
+      if (out_u) {
         const R ux = mx / sr, uy = my / sr;
-        if (a.out_f32) {
-          static_cast<float *>(a.out_u)[site] = float(ux);
-          static_cast<float *>(a.out_u)[nsite + site] = float(uy);
+        if (out_f32) {
+          static_cast<float *>(out_u)[site] = float(ux);
+          static_cast<float *>(out_u)[nsite + site] = float(uy);
         } else {
-          static_cast<double *>(a.out_u)[site] = double(ux);
-          static_cast<double *>(a.out_u)[nsite + site] = double(uy);
+          static_cast<double *>(out_u)[site] = double(ux);
+          static_cast<double *>(out_u)[nsite + site] = double(uy);
         }
       }
     }
@@ -621,35 +626,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const R ir = C::rcp(rho[s]);
-      const R ux = upx + tau[s] * Fx[s] * ir;
-      const R uy = upy + tau[s] * Fy[s] * ir;
+      const R ux = fmadd(tau[s] * Fx[s], ir, upx);
+      const R uy = fmadd(tau[s] * Fy[s], ir, upy);
       // Deviation form of f^eq_l = W_l rho (1 + 3 cu + 9/2 cu^2 - 3/2 u.u):
       //   f^eq_l - W_l rho_ref = W_l (drho - 3/2 rho u.u) + W_l rho cu (3 + 9/2 cu)
-      const R m15 = R(-1.5) * (ux * ux + uy * uy);
+      const R m15 = R(-1.5) * fmadd(ux, ux, uy * uy);
       const R r9 = rho[s] * R(1.0 / 9.0), r36 = rho[s] * R(1.0 / 36.0);
-      const R b9 = drho[s] * R(1.0 / 9.0) + r9 * m15, b36 = drho[s] * R(1.0 / 36.0) + r36 * m15;
+      const R b9 = fmadd(r9, m15, drho[s] * R(1.0 / 9.0)), b36 = fmadd(r36, m15, drho[s] * R(1.0 / 36.0));
       const R o = om[s];
+      // relaxation of one population towards W_l (drho - 3/2 rho u.u) + W_l rho cu (3 + 9/2 cu),
+      // cu = c_l . u (r = W_l rho, b = the velocity-independent part); opposite links take -cu
+      auto relax = [o](R fl, R b, R r, R cu) { return fmadd(o, fmadd(r, cu * fmadd(R(4.5), cu, R(3)), b) - fl, fl); };
       R fs[9];
-      {
-        const R cu = ux;
-        fs[1] = f[s][1] + o * (b9 + r9 * (cu * (R(3) + R(4.5) * cu)) - f[s][1]);
-        fs[3] = f[s][3] + o * (b9 - r9 * (cu * (R(3) - R(4.5) * cu)) - f[s][3]);
-      }
-      {
-        const R cu = uy;
-        fs[2] = f[s][2] + o * (b9 + r9 * (cu * (R(3) + R(4.5) * cu)) - f[s][2]);
-        fs[4] = f[s][4] + o * (b9 - r9 * (cu * (R(3) - R(4.5) * cu)) - f[s][4]);
-      }
-      {
-        const R cu = ux + uy;
-        fs[5] = f[s][5] + o * (b36 + r36 * (cu * (R(3) + R(4.5) * cu)) - f[s][5]);
-        fs[7] = f[s][7] + o * (b36 - r36 * (cu * (R(3) - R(4.5) * cu)) - f[s][7]);
-      }
-      {
-        const R cu = uy - ux;
-        fs[6] = f[s][6] + o * (b36 + r36 * (cu * (R(3) + R(4.5) * cu)) - f[s][6]);
-        fs[8] = f[s][8] + o * (b36 - r36 * (cu * (R(3) - R(4.5) * cu)) - f[s][8]);
-      }
+      fs[1] = relax(f[s][1], b9, r9, ux);
+      fs[3] = relax(f[s][3], b9, r9, -ux);
+      fs[2] = relax(f[s][2], b9, r9, uy);
+      fs[4] = relax(f[s][4], b9, r9, -uy);
+      fs[5] = relax(f[s][5], b36, r36, ux + uy);
+      fs[7] = relax(f[s][7], b36, r36, -(ux + uy));
+      fs[6] = relax(f[s][6], b36, r36, uy - ux);
+      fs[8] = relax(f[s][8], b36, r36, -(uy - ux));
       // rest population closes the mass balance exactly: d*_0 = drho - sum_{l>0} d*_l
       fs[0] = drho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
 
@@ -723,14 +719,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
       double v = 0.0;
       const int nw = (TX + 63) >> 6;
       for (int i = 0; i < nw; ++i) v += red_lds[i][tid];
-      a.partials[(size_t)blockIdx.x * RED_N + tid] = v;
+      part[tid] = v;
     }
   }
 }
 
+// One lattice: one workgroup per tile, tiles in band-major order spread over the XCDs.
+template <int MODE, int NS, bool WALLS, int WHAT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step_kernel(StepArgs a) {
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int nstrip = (int)gridDim.x / a.nseg;
+  const int seg = logical / nstrip;
+  const int strip = logical - seg * nstrip;
+  run_tile<MODE, NS, WALLS, WHAT>(a, a.src, a.dst, strip, seg, a.partials + (size_t)blockIdx.x * RED_N, a.out_rho,
+                                  a.out_u, a.out_f32);
+}
+
+// Many independent lattices in one persistent launch.  The host lists every tile of every
+// instance (band-major within an instance); the workgroups of the grid take the tiles in
+// rounds of gridDim.x, each round spread over the XCDs like the single-lattice grid, and
+// read the instance's sizes, couplings and buffer offsets from b.inst.  Tiles of one round
+// that neighbour each other share their overlap rows and columns through L2.
+template <int MODE, int NS, bool WALLS, int WHAT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void batch_step_kernel(BatchArgs b) {
+  const int G = (int)gridDim.x;
+  const int mine = xcd_remap(blockIdx.x, G);
+  for (int base = 0; base < b.ntiles; base += G) {
+    const int t = base + mine;
+    if (t >= b.ntiles) break;  // later rounds are shorter still
+    if (base > 0) __syncthreads();  // the previous tile's last ring and staging reads are done
+    const int ti = (int)__builtin_amdgcn_readfirstlane((uint32_t)(b.tile0 + t));
+    const TileDesc td = b.tiles[ti];
+    const StepArgs &a = b.inst[td.inst];
+    run_tile<MODE, NS, WALLS, WHAT>(a, b.src + a.offset, b.dst + a.offset, td.strip, td.seg,
+                                    b.partials + (size_t)td.part * RED_N, b.out_rho, b.out_u, b.out_f32);
+  }
+}
+
 // Second reduction pass: fixed-order sum of the per-workgroup partials (deterministic).
-__global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int nblocks, double *totals, double *acc,
-                                                     int accumulate, double inv_lx) {
+__device__ __forceinline__ void reduce_block(const double *partials, int nblocks, double *totals, double *acc,
+                                             int accumulate, double inv_lx) {
   __shared__ double sm[256][RED_N];
   const int tid = threadIdx.x;
   double v[RED_N];
@@ -764,6 +792,19 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int
       acc[3] += t[RED_BAD];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int nblocks, double *totals, double *acc,
+                                                     int accumulate, double inv_lx) {
+  reduce_block(partials, nblocks, totals, acc, accumulate, inv_lx);
+}
+
+// One workgroup per instance of a batch: its tiles' partials are a contiguous range.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const double *partials, const ReduceJob *jobs,
+                                                           double *totals, double *acc, int accumulate) {
+  const ReduceJob j = jobs[blockIdx.x];
+  reduce_block(partials + (size_t)j.p0 * RED_N, j.n, totals + (size_t)blockIdx.x * RED_N,
+               acc + (size_t)blockIdx.x * 4, accumulate, j.inv_lx);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -893,6 +934,50 @@ template <int MODE>
 static hipError_t launch_step_m(int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
   if (ns == 1) return walls ? launch_step_t<MODE, 1, true>(what, tx, nb, a, st) : launch_step_t<MODE, 1, false>(what, tx, nb, a, st);
   return walls ? launch_step_t<MODE, 2, true>(what, tx, nb, a, st) : launch_step_t<MODE, 2, false>(what, tx, nb, a, st);
+}
+
+template <int MODE, int NS, bool WALLS>
+static hipError_t launch_batch_t(int what, int tx, int grid, const BatchArgs &b, hipStream_t st) {
+  const size_t lds = step_lds_bytes(MODE, NS, tx);
+  switch (what) {
+    case WHAT_STEP:
+      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    case WHAT_STEP_REDUCE:
+      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    case WHAT_MOMENTS:
+      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_MOMENTS>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    case WHAT_OBSERVE:
+      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_OBSERVE>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_batch_m(int ns, int walls, int what, int tx, int grid, const BatchArgs &b, hipStream_t st) {
+  if (ns == 1) return walls ? launch_batch_t<MODE, 1, true>(what, tx, grid, b, st) : launch_batch_t<MODE, 1, false>(what, tx, grid, b, st);
+  return walls ? launch_batch_t<MODE, 2, true>(what, tx, grid, b, st) : launch_batch_t<MODE, 2, false>(what, tx, grid, b, st);
+}
+
+hipError_t launch_batch_step(int mode, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
+                             hipStream_t st) {
+  switch (mode) {
+    case MODE_F64: return launch_batch_m<MODE_F64>(ns, walls, what, tx, grid, b, st);
+    case MODE_F32: return launch_batch_m<MODE_F32>(ns, walls, what, tx, grid, b, st);
+    case MODE_BF16: return launch_batch_m<MODE_BF16>(ns, walls, what, tx, grid, b, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_reduce(const double *partials, const ReduceJob *jobs, int njobs, double *totals, double *acc,
+                               int accumulate, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(njobs), dim3(256), 0, st, partials, jobs, totals, acc, accumulate);
+  return hipGetLastError();
 }
 
 template <int MODE, int NS, bool WALLS>

@@ -110,6 +110,7 @@ def test_tile_shape_invariance_bitwise(walls, storage):
     direction mistake shows up as a difference."""
     c = emulsion_case(130, 45, walls=walls, fraction=0.7, seed=3, rmin=5, rmax=9, g=1e-5 if walls else 0.0)
     c["storage"] = storage
+    c["tau"] = (0.9, 1.2)  # tau != 1, so that every multiply of the collision rounds
     ref = None
     for tile in (None, (64, 1), (64, 2), (64, 7), (128, 3), (256, 4), (256, 16), (256, 45)):
         sim = make_sim(c, tile=tile)
