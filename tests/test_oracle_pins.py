@@ -517,3 +517,92 @@ def test_two_component_lamella():
     pb = dg.bulk_pressure_2c(rho[0, 0], rho[1, 0], P)
     assert pa == pytest.approx(pn.mean(), rel=1e-8)
     assert pb == pytest.approx(pn.mean(), rel=1e-8)
+
+
+# ----------------------------------------------------------------------------------------
+# P16: the oracle's complex-step gradient of the time-averaged loss
+#   L = lw0 <(W_bot + W_top)/2> + lw1 <Q>   (wall stress and flow rate, emulsion section)
+# ----------------------------------------------------------------------------------------
+
+def test_gradient_uniform_state_under_body_force_closed_form():
+    """Uniform fluid at rest, periodic, body force g: every step adds exactly rho g to the
+    momentum (u_eq = u' + tau F / rho and omega tau = 1), so u_x(t) = (t + 1/2) g and
+    <Q> over t = 0..T-1 is ly g T / 2: dL/dg = lw1 ly T / 2, and the uniform state feels no
+    pseudopotential force, so dL/dG1 = dL/dG2 = 0."""
+    from oracle import cs_grad
+    lx, ly, T, g = 6, 7, 9, 3e-5
+    P = Params(lx=lx, ly=ly, ns=1, g1=(-5.0, 0.0), g2=(4.0, 0.0), body=(g, 0.0))
+    o = Oracle(P, rho_init=np.full((1, ly, lx), 0.9))
+    f0 = o.get_f()
+    lw = (0.0, 1.0)
+    L, dg = cs_grad(P, f0, T, lw, 3)
+    assert L == pytest.approx(ly * g * T / 2, rel=1e-12)
+    assert dg == pytest.approx(ly * T / 2, rel=1e-12)
+    for param in (0, 1):
+        assert abs(cs_grad(P, f0, T, lw, param)[1]) < 1e-15
+
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_gradient_one_step_sinusoid_closed_form(m):
+    """One step from rest on psi = alpha + beta sin(kx): Q(0) = (1/2 lx) sum F_x / rho with
+    F_x = -psi 2 beta cos(kx) sum_a k_a sin(k a); dQ/dG1 and dQ/dG2 are the same sums with
+    the shell weights w (attractive belt) or p (both belts) in place of K."""
+    from oracle import cs_grad
+    lx, ly = 24, 5
+    P = Params(lx=lx, ly=ly, ns=1, **FILM)
+    kap = 2 * np.pi * m / lx
+    x = np.arange(lx)
+    alpha, beta = 0.6, 0.1
+    psi = alpha + beta * np.sin(kap * x)
+    rho = _state_for_psi(np.broadcast_to(psi, (ly, lx)), P)
+    o = Oracle(P, rho_init=rho[None])
+    f0 = o.get_f()
+
+    def dfx(W):  # x-force per unit coupling for shell weights W(q), q = 1, 2, 4, 5, 8
+        k1 = W[0] + 2 * W[1] + 2 * W[3]
+        k2 = W[2] + 2 * W[3] + 2 * W[4]
+        return -psi * 2 * beta * np.cos(kap * x) * (k1 * np.sin(kap) + 2 * k2 * np.sin(2 * kap))
+
+    r = rho[0]
+    fx = P.g1[0] * dfx(P.w) + P.g2[0] * dfx(P.p)
+    L, d1 = cs_grad(P, f0, 1, (0.0, 1.0), 0)
+    _, d2 = cs_grad(P, f0, 1, (0.0, 1.0), 1)
+    assert L == pytest.approx(ly / (2 * lx) * np.sum(fx / r), rel=1e-11, abs=1e-16)
+    assert d1 == pytest.approx(ly / (2 * lx) * np.sum(dfx(P.w) / r), rel=1e-11, abs=1e-16)
+    assert d2 == pytest.approx(ly / (2 * lx) * np.sum(dfx(P.p) / r), rel=1e-11, abs=1e-16)
+
+
+@pytest.mark.parametrize("param", [0, 1, 2, 3])
+def test_gradient_complex_step_matches_central_differences(param):
+    """Complex step against central differences of the oracle's own loss on a small
+    two-component channel (walls, wetting, body force), every parameter."""
+    from oracle import cs_grad
+    import dataclasses
+    lx, ly, T = 20, 14, 25
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.6, seed=7, walls=True, rmin=3, rmax=5)
+    P = Params(lx=lx, ly=ly, ns=2, walls=1, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+               body=(1e-4, 0.0), rho_wall=lbgen.EMULSION_POOR, rho0=lbgen.EMULSION_RHO0)
+    f0 = Oracle(P, rho_init=rho).get_f()
+    lw = (1.0, 0.3)
+    L, d = cs_grad(P, f0, T, lw, param)
+
+    def loss(Pp):
+        o = Oracle(Pp, rho_init=rho)
+        o.set_f(f0)
+        rec = o.step(T, record=True)
+        return lw[0] * np.mean(0.5 * (rec[:, 4] + rec[:, 5])) + lw[1] * np.mean(rec[:, 6])
+
+    def shifted(e):
+        if param == 0:
+            return dataclasses.replace(P, g1=tuple(v + e for v in P.g1))
+        if param == 1:
+            return dataclasses.replace(P, g2=tuple(v + e for v in P.g2))
+        if param == 2:
+            return dataclasses.replace(P, gab=P.gab + e)
+        return dataclasses.replace(P, body=(P.body[0] + e, P.body[1]))
+
+    base = [sum(P.g1) / 2, sum(P.g2) / 2, P.gab, P.body[0]][param]
+    h = 1e-4 * abs(base)
+    fd = (loss(shifted(h)) - loss(shifted(-h))) / (2 * h)
+    assert L == pytest.approx(loss(P), rel=1e-12)
+    assert d == pytest.approx(fd, rel=1e-5)
