@@ -179,6 +179,28 @@ int lb_set_graph(lb_ctx *ctx, int32_t steps);
    population buffer, so the state is unchanged.  Synchronises. */
 int lb_autotune(lb_ctx *ctx, int32_t trial_steps, int32_t *tx, int32_t *sy, double *ms);
 
+/* Replace the couplings (G_ss,1, G_ss,2, G_AB, weights, body force, wall densities) of a
+   running simulation; validated as in lb_init.  Takes effect at the next step.  Host call. */
+int lb_set_couplings(lb_ctx *ctx, const lb_couplings *cpl);
+
+/*
+ * Adjoint (reverse-time) gradient of the time-averaged wall stress and flow rate (emulsion
+ * section: Poiseuille flow of a confined emulsion) over the next T >= 1 steps:
+ *   L = lw[0] * (1/T) sum_t (W_bot(t) + W_top(t)) / 2  +  lw[1] * (1/T) sum_t Q(t),
+ * W_bot/W_top as in lb_wall_stress for step t, Q(t) = (1/lx) sum_x u_x (u as in lb_moments),
+ * t running over the T steps from the current state, which is held fixed.  Outputs (host):
+ * *loss = L and grad[7] = dL/d(G_AA,1, G_BB,1, G_AA,2, G_BB,2, G_AB, g_x, g_y).
+ * The forward pass keeps an FP64 checkpoint of the populations every `every` steps
+ * (every <= 0: ceil(sqrt(T))); the reverse sweep recomputes each segment's states from its
+ * checkpoint and runs the hand-written reverse step (FP64 for LB_F64 contexts, FP32
+ * otherwise).  workspace: device buffer of lb_adjoint_workspace_bytes(ctx, T, every) bytes,
+ * owned by the caller.  On return the context holds the state after T steps, bit for bit as
+ * lb_step(ctx, T) would leave it, and lb_time has advanced by T; the running wall-stress
+ * average is reset.  Synchronises. */
+size_t lb_adjoint_workspace_bytes(const lb_ctx *ctx, int64_t T, int32_t every);
+int lb_adjoint(lb_ctx *ctx, int64_t T, int32_t every, const double loss_weights[2], double *loss, double grad[7],
+               void *workspace, size_t workspace_bytes);
+
 /* Message of the last failure on ctx (ctx = NULL: last failure of lb_init in this thread). */
 const char *lb_last_error(const lb_ctx *ctx);
 

@@ -81,6 +81,7 @@ class Sim:
         self.lat = B.LbLattice(self.lx, self.ly, self.ns, 1 if walls else 0, self.storage)
         cpl = _couplings(g1, g2, gab, body, rho_wall, w, p, t, cross_psi)
         self.cpl = cpl
+        self._ckw = dict(g1=g1, g2=g2, gab=gab, body=body, rho_wall=rho_wall, w=w, p=p, t=t, cross_psi=cross_psi)
         self.tau = (ctypes.c_double * 2)(*_pair(tau))
         rho = _density(rho_init, self.ns, self.ly, self.lx)
         self.psi = _psi_params(psi0, rho0, rho_ref, rho)
@@ -135,6 +136,31 @@ class Sim:
         tx, sy = ctypes.c_int32(), ctypes.c_int32()
         self._chk(self._lib.lb_get_tile(self._h, ctypes.byref(tx), ctypes.byref(sy)))
         return tx.value, sy.value
+
+    def set_couplings(self, **kw):
+        """Replace couplings (any of g1, g2, gab, body, rho_wall, w, p, t, cross_psi); the
+        others keep their current values."""
+        self._ckw.update(kw)
+        cpl = _couplings(**self._ckw)
+        self._chk(self._lib.lb_set_couplings(self._h, ctypes.byref(cpl)))
+        self.cpl = cpl
+
+    def adjoint(self, T, loss_weights=(1.0, 0.0), every=0):
+        """Loss L = lw0 <(W_bot + W_top)/2> + lw1 <Q> over the next T steps and its gradient
+        dL/d(G_AA,1, G_BB,1, G_AA,2, G_BB,2, G_AB, g_x, g_y) by the hand-written adjoint with
+        checkpoints every `every` steps (0: sqrt(T)).  Advances the state by T steps."""
+        torch = self.torch
+        nbytes = self._lib.lb_adjoint_workspace_bytes(self._h, int(T), int(every))
+        if nbytes == 0:
+            raise LbError(B.LB_EINVAL, "invalid adjoint request")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        lw = (ctypes.c_double * 2)(*[float(v) for v in loss_weights])
+        loss = ctypes.c_double()
+        grad = (ctypes.c_double * 7)()
+        self._chk(self._lib.lb_adjoint(self._h, int(T), int(every), lw, ctypes.byref(loss), grad,
+                                       ctypes.c_void_p(ws.data_ptr()), nbytes))
+        del ws
+        return loss.value, np.array(grad[:])
 
     def set_graph(self, steps):
         """Replay plain steps in captured HIP graphs of `steps` launches (0: off)."""

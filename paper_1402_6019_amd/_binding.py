@@ -61,6 +61,9 @@ SIGNATURES = {
     "lb_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
     "lb_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "lb_set_graph": (ctypes.c_int, [_vp, _i32]),
+    "lb_set_couplings": (ctypes.c_int, [_vp, ctypes.POINTER(LbCouplings)]),
+    "lb_adjoint_workspace_bytes": (_sz, [_vp, _i64, _i32]),
+    "lb_adjoint": (ctypes.c_int, [_vp, _i64, _i32, _dp, _dp, _dp, _vp, _sz]),
     "lb_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]),
     "lb_last_error": (ctypes.c_char_p, [_vp]),
     "lb_destroy": (None, [_vp]),

@@ -1,0 +1,389 @@
+// Hand-written adjoint (reverse-time) step of the two-belt pseudopotential lattice
+// Boltzmann map, for gradients of the time-averaged wall stress and flow rate with respect
+// to the couplings G_ss,1, G_ss,2, G_AB and the body force g.
+//
+// Forward map of one step (state x = pre-collision populations f(t), canonical layout):
+//   rho_s = sum_l x_l,  j_s = sum_l c_l x_l,  psi_s = psi0 (1 - exp(-rho_s / rho0))
+//   F_s   = -psi_s sum_h K_s(q) c (psi_s(x+c) - psi_s(x-c))              (eq. (FORCE))
+//           -G_AB r_s sum_{h in belt 1} t(q) c (r_sbar(x+c) - r_sbar(x-c)) (r = rho or psi)
+//           +rho_s g
+//   u'    = sum_s omega_s j_s / sum_s omega_s rho_s,   u_s = u' + tau_s F_s / rho_s
+//   y_l   = (1 - omega_s) x_l + omega_s f^eq_l(rho_s, u_s)                 (eq. (LB))
+//   x'_l(x) = y_l(x - c_l), or y_opp(l)(x) when x - c_l is a wall row      (streaming)
+// Loss of one step (weights cW = lw0 / T, cQ = lw1 / T):
+//   cW (W_bot + W_top) / 2,  W_bot = (1/lx) sum_x sum_s sum_{c_ly = -1} 2 c_lx y_l(x, 0)
+//   cQ Q,  Q = (1/lx) sum_x u_x,  u = (sum_s j_s + F_s / 2) / sum_s rho_s
+//
+// Reverse step, given lambda' = dL/dx(t+1):
+//   a_l(x)   = lambda'_l(x + c_l), or lambda'_opp(l)(x) when x + c_l is a wall row (the
+//              transpose of streaming), plus the wall-stress source on the wall rows;
+//   then the chain rule through the collision, the velocity shift and u' per site gives
+//   the local part of lambda(t), the force adjoint Fbar_s and the parameter sensitivities
+//   Fbar_s . dF_s/dtheta; finally the force's dependence on the neighbours' psi (and rho)
+//   is a gather with the same stencil:
+//     psibar_s(y) += sum_h K_s(q) c . (A_s(y+c) - A_s(y-c)),   A_s = psi_s Fbar_s
+//     rbar_sbar(y) += G_AB sum_{h in belt 1} t(q) c . (B_s(y+c) - B_s(y-c)),  B_s = r_s Fbar_s
+//   and rhobar = psi'(rho) psibar enters every lambda_l(t).
+// All three kernels work on canonical-layout arrays [..][y][x], one thread per site.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lb_internal.hpp"
+#include "lb_tables.hpp"
+
+namespace lb355 {
+
+namespace {
+
+__device__ inline int wrapx(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+template <typename R>
+struct AdjView {
+  const AdjArgs &a;
+  int lx, ly;
+  size_t n;  // sites
+  __device__ AdjView(const AdjArgs &aa) : a(aa), lx(aa.lx), ly(aa.ly), n((size_t)aa.lx * aa.ly) {}
+  __device__ R *fields() const { return static_cast<R *>(a.fields); }
+  // field k (0 rho, 1 psi, 2 jx, 3 jy) of species s at site i
+  __device__ R fld(int k, int s, size_t i) const { return fields()[((size_t)k * 2 + s) * n + i]; }
+  __device__ R &fldw(int k, int s, size_t i) const { return fields()[((size_t)k * 2 + s) * n + i]; }
+};
+
+template <bool WALLS>
+__device__ inline bool site_of(int x, int y, int lx, int ly, size_t &i) {
+  if (WALLS && (y < 0 || y >= ly)) return false;
+  const int xi = wrapx(x, lx);
+  const int yi = WALLS ? y : wrapx(y, ly);
+  i = (size_t)yi * lx + xi;
+  return true;
+}
+
+template <typename T>
+__device__ inline T block_sum(T v, T *sm) {
+  // wave reduction, then across the waves of the block (sm: one slot per wave)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm[wv] = v;
+  __syncthreads();
+  T r = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sm[k];
+  return r;
+}
+
+}  // namespace
+
+// Moments and pseudopotential of the forward state x(t).
+template <typename R, int NS>
+__global__ __launch_bounds__(256) void adj_fields_kernel(AdjArgs a) {
+  AdjView<R> v(a);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= v.lx) return;
+  const size_t i = (size_t)y * v.lx + x;
+  for (int s = 0; s < NS; ++s) {
+    R r = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const R f = R(a.x[((size_t)s * Q + l) * v.n + i]);
+      r += f;
+      jx += R(CXS[l]) * f;
+      jy += R(CYS[l]) * f;
+    }
+    v.fldw(0, s, i) = r;
+    v.fldw(1, s, i) = R(a.psi0) * (R(1) - exp(-r * R(a.irho0)));
+    v.fldw(2, s, i) = jx;
+    v.fldw(3, s, i) = jy;
+  }
+}
+
+// Local part of the reverse step: force recompute, transposed streaming, the collision's
+// and velocity shift's adjoints; writes lampart, Fbar and per-block partial sums.
+template <typename R, int NS, bool WALLS>
+__global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
+  AdjView<R> v(a);
+  __shared__ double sm[4];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  const bool live = x < v.lx;
+  const int xs = live ? x : 0;
+  const size_t i = (size_t)y * v.lx + xs;
+  const R *lam_next = static_cast<const R *>(a.lam_next);
+  R *lampart = static_cast<R *>(a.lampart);
+  R *fbar = static_cast<R *>(a.fbar);
+
+  auto psi_at = [&](int s, int dx, int dy) -> R {
+    size_t j;
+    return site_of<WALLS>(xs + dx, y + dy, v.lx, v.ly, j) ? v.fld(1, s, j) : R(a.psi_w[s]);
+  };
+  auto rho_at = [&](int s, int dx, int dy) -> R {
+    size_t j;
+    return site_of<WALLS>(xs + dx, y + dy, v.lx, v.ly, j) ? v.fld(0, s, j) : R(a.rho_w[s]);
+  };
+
+  R rho[2], jx[2], jy[2], psi[2], Fx[2], Fy[2];
+  R s1x[2], s1y[2], s2x[2], s2y[2], xx[2], xy[2], self[2];
+  for (int s = 0; s < NS; ++s) {
+    rho[s] = v.fld(0, s, i);
+    psi[s] = v.fld(1, s, i);
+    jx[s] = v.fld(2, s, i);
+    jy[s] = v.fld(3, s, i);
+    // two-belt sums with the attractive (w) and repulsive (p) shell weights
+    R ax = 0, ay = 0, bx = 0, by = 0;
+#pragma unroll
+    for (int h = 0; h < NHALF; ++h) {
+      const R d = psi_at(s, HX[h], HY[h]) - psi_at(s, -HX[h], -HY[h]);
+      const R wq = R(a.w[HQ[h]]), pq = R(a.p[HQ[h]]);
+      ax += wq * R(HX[h]) * d;
+      ay += wq * R(HY[h]) * d;
+      bx += pq * R(HX[h]) * d;
+      by += pq * R(HY[h]) * d;
+    }
+    s1x[s] = ax; s1y[s] = ay; s2x[s] = bx; s2y[s] = by;
+    Fx[s] = -psi[s] * (R(a.g1[s]) * ax + R(a.g2[s]) * bx);
+    Fy[s] = -psi[s] * (R(a.g1[s]) * ay + R(a.g2[s]) * by);
+    xx[s] = 0; xy[s] = 0; self[s] = 0;
+  }
+  if (NS == 2) {
+    for (int s = 0; s < 2; ++s) {
+      const int o = 1 - s;
+      R cx = 0, cy = 0;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const R d = a.cross_psi ? psi_at(o, HX[h], HY[h]) - psi_at(o, -HX[h], -HY[h])
+                                : rho_at(o, HX[h], HY[h]) - rho_at(o, -HX[h], -HY[h]);
+        const R tq = R(a.t[HQ[h]]);
+        cx += tq * R(HX[h]) * d;
+        cy += tq * R(HY[h]) * d;
+      }
+      xx[s] = cx;
+      xy[s] = cy;
+      self[s] = a.cross_psi ? psi[s] : rho[s];
+      Fx[s] -= R(a.gab) * self[s] * cx;
+      Fy[s] -= R(a.gab) * self[s] * cy;
+    }
+  }
+  for (int s = 0; s < NS; ++s) {
+    Fx[s] += rho[s] * R(a.body[0]);
+    Fy[s] += rho[s] * R(a.body[1]);
+  }
+
+  // common velocity and the shifted equilibrium velocities
+  R nx = 0, ny = 0, den = 0, rtot = 0, mx = 0, my = 0;
+  for (int s = 0; s < NS; ++s) {
+    const R om = R(a.omega[s]);
+    nx += om * jx[s];
+    ny += om * jy[s];
+    den += om * rho[s];
+    rtot += rho[s];
+    mx += jx[s] + R(0.5) * Fx[s];
+    my += jy[s] + R(0.5) * Fy[s];
+  }
+  const R upx = nx / den, upy = ny / den;
+  const R urx = mx / rtot;  // reported (half-force) velocity, x component
+
+  // adjoint sources of this step's loss
+  const R cW = R(a.cW), cQ = R(a.cQ);
+  double loss_w = 0.0;
+  const double loss_q = live ? double(cQ * urx) / v.lx : 0.0;
+
+  R ubx = 0, uby = 0;  // adjoint of u'
+  R rbar[2], jbx[2], jby[2], fbx[2], fby[2];
+  R lp[2][Q];
+  for (int s = 0; s < NS; ++s) {
+    const R om = R(a.omega[s]), tau = R(a.tau[s]);
+    const R ux = upx + tau * Fx[s] / rho[s], uy = upy + tau * Fy[s] / rho[s];
+    const R uu = ux * ux + uy * uy;
+    R rb = 0, bx = 0, by = 0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      // transposed streaming: the population leaving x along c_l arrives at x + c_l, or
+      // bounces back into opp(l) at x when x + c_l is a wall row
+      size_t j;
+      R al;
+      if (site_of<WALLS>(xs + CXS[l], y + CYS[l], v.lx, v.ly, j)) al = lam_next[((size_t)s * Q + l) * v.n + j];
+      else al = lam_next[((size_t)s * Q + OPPS[l]) * v.n + i];
+      const R cu = R(CXS[l]) * ux + R(CYS[l]) * uy;
+      const R wl = R(WD2Q9[l]);
+      const R feq = wl * rho[s] * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+      if (WALLS && ((y == 0 && CYS[l] == -1) || (y == v.ly - 1 && CYS[l] == 1))) {
+        // wall stress: d/dy_l of cW (1/2)(1/lx) 2 c_lx y_l
+        al += cW * R(CXS[l]) / R(v.lx);
+        const R yl = (R(1) - om) * R(a.x[((size_t)s * Q + l) * v.n + i]) + om * feq;  // post-collision
+        if (live) loss_w += double(cW * R(CXS[l]) * yl) / v.lx;
+      }
+      lp[s][l] = (R(1) - om) * al;
+      rb += om * al * feq / rho[s];
+      const R k = om * al * wl * rho[s];
+      bx += k * (R(3) * R(CXS[l]) + R(9) * cu * R(CXS[l]) - R(3) * ux);
+      by += k * (R(3) * R(CYS[l]) + R(9) * cu * R(CYS[l]) - R(3) * uy);
+    }
+    // u_s = u' + tau F_s / rho_s
+    ubx += bx;
+    uby += by;
+    fbx[s] = tau * bx / rho[s];
+    fby[s] = tau * by / rho[s];
+    rb -= tau * (Fx[s] * bx + Fy[s] * by) / (rho[s] * rho[s]);
+    rbar[s] = rb;
+  }
+  for (int s = 0; s < NS; ++s) {
+    const R om = R(a.omega[s]);
+    // u' = sum omega j / sum omega rho
+    jbx[s] = om * ubx / den;
+    jby[s] = om * uby / den;
+    rbar[s] -= om * (upx * ubx + upy * uby) / den;
+    // flow rate: Q = (1/lx) sum (sum_s j_s + F_s / 2)_x / sum_s rho_s
+    jbx[s] += cQ / (R(v.lx) * rtot);
+    fbx[s] += cQ / (R(2) * R(v.lx) * rtot);
+    rbar[s] -= cQ * urx / (R(v.lx) * rtot);
+  }
+  // force: F_s = -psi_s S_s - G_AB self_s X_s + rho_s g
+  double dg1[2] = {0, 0}, dg2[2] = {0, 0}, dgab = 0, dgx = 0, dgy = 0;
+  R psib[2] = {0, 0};
+  for (int s = 0; s < NS; ++s) {
+    const R Sx = R(a.g1[s]) * s1x[s] + R(a.g2[s]) * s2x[s], Sy = R(a.g1[s]) * s1y[s] + R(a.g2[s]) * s2y[s];
+    psib[s] -= fbx[s] * Sx + fby[s] * Sy;
+    rbar[s] += fbx[s] * R(a.body[0]) + fby[s] * R(a.body[1]);
+    if (NS == 2) {
+      const R cb = -R(a.gab) * (fbx[s] * xx[s] + fby[s] * xy[s]);
+      if (a.cross_psi) psib[s] += cb;
+      else rbar[s] += cb;
+    }
+    if (live) {
+      dg1[s] = double(-psi[s] * (fbx[s] * s1x[s] + fby[s] * s1y[s]));
+      dg2[s] = double(-psi[s] * (fbx[s] * s2x[s] + fby[s] * s2y[s]));
+      dgab += double(-self[s] * (fbx[s] * xx[s] + fby[s] * xy[s]));
+      dgx += double(fbx[s] * rho[s]);
+      dgy += double(fby[s] * rho[s]);
+    }
+    // psi'(rho) = (psi0 / rho0) exp(-rho / rho0)
+    rbar[s] += psib[s] * R(a.psi0) * R(a.irho0) * exp(-rho[s] * R(a.irho0));
+  }
+  if (live) {
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int l = 0; l < Q; ++l)
+        lampart[((size_t)s * Q + l) * v.n + i] = lp[s][l] + rbar[s] + R(CXS[l]) * jbx[s] + R(CYS[l]) * jby[s];
+      fbar[((size_t)s * 2 + 0) * v.n + i] = fbx[s];
+      fbar[((size_t)s * 2 + 1) * v.n + i] = fby[s];
+    }
+  }
+  // per-block partial sums (fixed order: waves, then blocks in the second pass)
+  double vals[ADJ_N] = {dg1[0], dg1[1], dg2[0], dg2[1], dgab, dgx, dgy, loss_w, loss_q};
+  const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+  for (int k = 0; k < ADJ_N; ++k) {
+    const double t = block_sum(vals[k], sm);
+    if (threadIdx.x == 0) a.partials[blk * ADJ_N + k] = t;
+  }
+}
+
+// Nonlocal part: the force's dependence on the neighbours' psi (and rho), gathered with the
+// forward stencil; completes lambda(t).
+template <typename R, int NS, bool WALLS>
+__global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
+  AdjView<R> v(a);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= v.lx) return;
+  const size_t i = (size_t)y * v.lx + x;
+  const R *fbar = static_cast<const R *>(a.fbar);
+  const R *lampart = static_cast<const R *>(a.lampart);
+  R *lam = static_cast<R *>(a.lam);
+  // A_s = psi_s Fbar_s and B_s = r_s Fbar_s at a neighbour (zero on wall rows)
+  auto AB = [&](int k, int s, int dx, int dy, R &bx, R &by) {
+    size_t j;
+    if (!site_of<WALLS>(x + dx, y + dy, v.lx, v.ly, j)) {
+      bx = by = 0;
+      return;
+    }
+    const R f = v.fld(k, s, j);
+    bx = f * fbar[((size_t)s * 2 + 0) * v.n + j];
+    by = f * fbar[((size_t)s * 2 + 1) * v.n + j];
+  };
+  R psib[2] = {0, 0}, rbar[2] = {0, 0};
+  for (int s = 0; s < NS; ++s) {
+    R Kq[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Kq[q] = R(a.K[s][q]);
+    R acc = 0;
+#pragma unroll
+    for (int h = 0; h < NHALF; ++h) {
+      R px, py, mx, my;
+      AB(1, s, HX[h], HY[h], px, py);
+      AB(1, s, -HX[h], -HY[h], mx, my);
+      acc += Kq[HQ[h]] * (R(HX[h]) * (px - mx) + R(HY[h]) * (py - my));
+    }
+    psib[s] += acc;
+  }
+  if (NS == 2) {
+    for (int s = 0; s < 2; ++s) {  // species s's force depends on species o = 1 - s's field
+      const int o = 1 - s;
+      const int k = a.cross_psi ? 1 : 0;
+      R acc = 0;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        R px, py, mx, my;
+        AB(k, s, HX[h], HY[h], px, py);
+        AB(k, s, -HX[h], -HY[h], mx, my);
+        acc += R(a.t[HQ[h]]) * (R(HX[h]) * (px - mx) + R(HY[h]) * (py - my));
+      }
+      // B_s uses species s's own r (r_s Fbar_s); it lands on the other species' field
+      if (a.cross_psi) psib[o] += R(a.gab) * acc;
+      else rbar[o] += R(a.gab) * acc;
+    }
+  }
+  for (int s = 0; s < NS; ++s) {
+    const R r = v.fld(0, s, i);
+    const R rb = rbar[s] + psib[s] * R(a.psi0) * R(a.irho0) * exp(-r * R(a.irho0));
+#pragma unroll
+    for (int l = 0; l < Q; ++l) lam[((size_t)s * Q + l) * v.n + i] = lampart[((size_t)s * Q + l) * v.n + i] + rb;
+  }
+}
+
+// acc[k] += sum over blocks of partials[block][k], in block order (deterministic).
+__global__ __launch_bounds__(256) void adj_reduce_kernel(const double *partials, int nblocks, double *acc) {
+  __shared__ double sm[4];
+  for (int k = 0; k < ADJ_N; ++k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partials[(size_t)b * ADJ_N + k];
+    const double t = block_sum(v, sm);
+    if (threadIdx.x == 0) acc[k] += t;
+  }
+}
+
+__global__ void zero_kernel(uint32_t *p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+int adj_blocks(int lx, int ly) { return ((lx + 255) / 256) * ly; }
+
+template <typename R, int NS, bool WALLS>
+static hipError_t adj_step_t(const AdjArgs &a, double *acc, hipStream_t st) {
+  const dim3 grid((a.lx + 255) / 256, a.ly), block(256);
+  hipLaunchKernelGGL((adj_fields_kernel<R, NS>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), grid, block, 0, st, a);
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(256), 0, st, a.partials, (int)(grid.x * grid.y), acc);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t adj_step_r(int ns, int walls, const AdjArgs &a, double *acc, hipStream_t st) {
+  if (ns == 1) return walls ? adj_step_t<R, 1, true>(a, acc, st) : adj_step_t<R, 1, false>(a, acc, st);
+  return walls ? adj_step_t<R, 2, true>(a, acc, st) : adj_step_t<R, 2, false>(a, acc, st);
+}
+
+hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, double *acc, hipStream_t st) {
+  return fp64 ? adj_step_r<double>(ns, walls, a, acc, st) : adj_step_r<float>(ns, walls, a, acc, st);
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, static_cast<uint32_t *>(p), n);
+  return hipGetLastError();
+}
+
+}  // namespace lb355

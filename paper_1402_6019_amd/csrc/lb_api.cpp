@@ -404,6 +404,18 @@ int lb_set_tile(lb_ctx *c, int32_t tx, int32_t sy) {
   return LB_OK;
 }
 
+int lb_set_couplings(lb_ctx *c, const lb_couplings *cpl) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!cpl) return fail(c, LB_EINVAL, "null couplings");
+  std::string msg;
+  int rc = validate(&c->lat, cpl, c->tau, &c->psi, msg);
+  if (rc) return fail(c, rc, msg);
+  c->cpl = *cpl;
+  normalise(c->lat, c->cpl, c->psi, c->tau);
+  c->graph.clear();  // captured launches carry the old couplings
+  return LB_OK;
+}
+
 int lb_set_graph(lb_ctx *c, int32_t steps) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (steps < 0 || (steps & 1)) return fail(c, LB_EINVAL, "graph steps must be even and >= 0");
@@ -458,6 +470,156 @@ int lb_get_tile(const lb_ctx *c, int32_t *tx, int32_t *sy) {
   *tx = c->tx;
   *sy = c->sy;
   return LB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Adjoint: gradient of L = lw0 <(W_bot + W_top)/2> + lw1 <Q> over T steps.
+// ---------------------------------------------------------------------------------------
+
+namespace {
+
+struct AdjLayout {
+  int every = 1, ncp = 1;
+  size_t s64 = 0, lamb = 0, nsite = 0;
+  size_t ckpt = 0, seg = 0, fin = 0, lam0 = 0, lam1 = 0, lampart = 0, fields = 0, fbar = 0, partials = 0, acc = 0;
+  size_t total = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+AdjLayout adjoint_layout(const lb_ctx *c, int64_t T, int32_t every) {
+  AdjLayout L;
+  L.every = every > 0 ? every : std::max<int>(1, (int)std::ceil(std::sqrt((double)T)));
+  L.every = (int)std::min<int64_t>(L.every, std::max<int64_t>(T, 1));
+  L.ncp = (int)((T + L.every - 1) / L.every);
+  L.nsite = (size_t)c->lat.lx * c->lat.ly;
+  const size_t rs = c->lat.storage == LB_F64 ? 8 : 4;
+  const int ns = c->lat.n_species;
+  L.s64 = align256((size_t)ns * 9 * L.nsite * 8);
+  L.lamb = align256((size_t)ns * 9 * L.nsite * rs);
+  size_t o = 0;
+  L.ckpt = o; o += (size_t)L.ncp * L.s64;
+  L.seg = o; o += (size_t)L.every * L.s64;
+  L.fin = o; o += align256(lb_pop_bytes(&c->lat));
+  L.lam0 = o; o += L.lamb;
+  L.lam1 = o; o += L.lamb;
+  L.lampart = o; o += L.lamb;
+  L.fields = o; o += align256(8 * L.nsite * rs);
+  L.fbar = o; o += align256(4 * L.nsite * rs);
+  L.partials = o; o += align256((size_t)adj_blocks(c->lat.lx, c->lat.ly) * ADJ_N * 8);
+  L.acc = o; o += align256(ADJ_N * 8);
+  L.total = o;
+  return L;
+}
+
+AdjArgs adjoint_args(const lb_ctx *c, double lw0, double lw1, int64_t T) {
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.lx = c->lat.lx;
+  a.ly = c->lat.ly;
+  a.cross_psi = c->cpl.cross_uses_psi;
+  for (int s = 0; s < 2; ++s) {
+    for (int q = 0; q < 5; ++q) a.K[s][q] = c->cpl.g1[s] * c->cpl.w[q] + c->cpl.g2[s] * c->cpl.p[q];
+    a.g1[s] = c->cpl.g1[s];
+    a.g2[s] = c->cpl.g2[s];
+    a.body[s] = c->cpl.body_force[s];
+    a.tau[s] = c->tau[s];
+    a.omega[s] = 1.0 / c->tau[s];
+    a.rho_w[s] = c->cpl.rho_wall[s];
+    a.psi_w[s] = c->psi.psi0 * (1.0 - std::exp(-c->cpl.rho_wall[s] / c->psi.rho0));
+  }
+  for (int q = 0; q < 5; ++q) {
+    a.w[q] = c->cpl.w[q];
+    a.p[q] = c->cpl.p[q];
+  }
+  a.t[0] = c->cpl.t[0];
+  a.t[1] = c->cpl.t[1];
+  a.gab = c->cpl.g_ab;
+  a.psi0 = c->psi.psi0;
+  a.irho0 = 1.0 / c->psi.rho0;
+  a.cW = lw0 / (double)T;
+  a.cQ = lw1 / (double)T;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_adjoint_workspace_bytes(const lb_ctx *c, int64_t T, int32_t every) {
+  if (!c || T < 1) return 0;
+  return adjoint_layout(c, T, every).total;
+}
+
+int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, const double loss_weights[2], double *loss, double grad[7],
+               void *workspace, size_t workspace_bytes) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (T < 1) return fail(c, LB_EINVAL, "T must be >= 1");
+  if (!loss_weights || !grad) return fail(c, LB_EINVAL, "null argument");
+  if (!workspace) return fail(c, LB_EINVAL, "null workspace");
+  const AdjLayout L = adjoint_layout(c, T, every);
+  if (workspace_bytes < L.total) return fail(c, LB_ENOMEM, "workspace smaller than lb_adjoint_workspace_bytes()");
+  int rc = poll_health(c, true);
+  if (rc) return rc;
+  char *ws = static_cast<char *>(workspace);
+  const int64_t t0 = c->t;
+  const int keep_reduce = c->reduce_every;
+  c->reduce_every = 0;
+  auto done = [&](int code) {
+    c->reduce_every = keep_reduce;
+    return code;
+  };
+  // forward pass with a checkpoint every L.every steps
+  for (int k = 0; k < L.ncp; ++k) {
+    if ((rc = lb_checkpoint(c, ws + L.ckpt + (size_t)k * L.s64))) return done(rc);
+    if ((rc = lb_step(c, std::min<int64_t>(L.every, T - (int64_t)k * L.every)))) return done(rc);
+  }
+  // the final state, bit for bit (the context continues from it)
+  const int cur_final = c->cur;
+  const size_t popb = lb_pop_bytes(&c->lat);
+  hipError_t e = hipMemcpyAsync(ws + L.fin, c->pop[cur_final], popb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = launch_zero(ws + L.lam1, L.lamb, c->stream);
+  if (e == hipSuccess) e = launch_zero(ws + L.acc, ADJ_N * 8, c->stream);
+  if (e != hipSuccess) return done(hip_fail(c, e, "adjoint setup"));
+  // reverse sweep, one checkpoint segment at a time
+  AdjArgs a = adjoint_args(c, loss_weights[0], loss_weights[1], T);
+  a.lampart = ws + L.lampart;
+  a.fields = ws + L.fields;
+  a.fbar = ws + L.fbar;
+  a.partials = reinterpret_cast<double *>(ws + L.partials);
+  double *acc = reinterpret_cast<double *>(ws + L.acc);
+  char *lam_next = ws + L.lam1, *lam_cur = ws + L.lam0;
+  const int fp64 = c->lat.storage == LB_F64;
+  for (int k = L.ncp - 1; k >= 0; --k) {
+    const int len = (int)std::min<int64_t>(L.every, T - (int64_t)k * L.every);
+    if ((rc = lb_restore(c, ws + L.ckpt + (size_t)k * L.s64))) return done(rc);
+    for (int j = 0; j < len; ++j) {  // recompute the segment's states
+      if ((rc = lb_checkpoint(c, ws + L.seg + (size_t)j * L.s64))) return done(rc);
+      if (j + 1 < len && (rc = lb_step(c, 1))) return done(rc);
+    }
+    for (int j = len - 1; j >= 0; --j) {
+      a.x = reinterpret_cast<const double *>(ws + L.seg + (size_t)j * L.s64);
+      a.lam_next = lam_next;
+      a.lam = lam_cur;
+      e = launch_adjoint_step(fp64, c->lat.n_species, c->lat.walls, a, acc, c->stream);
+      if (e != hipSuccess) return done(hip_fail(c, e, "adjoint step"));
+      std::swap(lam_next, lam_cur);
+    }
+  }
+  // back to the state after T steps
+  e = hipMemcpyAsync(c->pop[cur_final], ws + L.fin, popb, hipMemcpyDeviceToDevice, c->stream);
+  double h[ADJ_N];
+  if (e == hipSuccess) e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return done(hip_fail(c, e, "adjoint readback"));
+  c->cur = cur_final;
+  c->t = t0 + T;
+  for (int k = 0; k < 7; ++k) grad[k] = h[k];
+  if (loss) *loss = h[ADJ_LW] + h[ADJ_LQ];
+  if (!std::isfinite(h[ADJ_LW] + h[ADJ_LQ])) return done(fail(c, LB_EUNSTABLE, "non-finite loss"));
+  return done(LB_OK);
 }
 
 const char *lb_last_error(const lb_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }

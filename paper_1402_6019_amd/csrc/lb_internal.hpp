@@ -79,6 +79,34 @@ struct LayoutArgs {
   double rho_ref[2];
 };
 
+// Reverse step of the adjoint (lb_adjoint.hip).  Arrays are canonical [..][y][x]; R is
+// double for FP64 contexts and float otherwise.
+struct AdjArgs {
+  const double *x;       // forward pre-collision state f(t) [s][l][y][x], FP64
+  const void *lam_next;  // lambda(t+1) [s][l][y][x] (R)
+  void *lam;             // lambda(t) (R, written)
+  void *lampart;         // local part of lambda(t) (R, scratch)
+  void *fields;          // [4][2][y][x] (R): rho, psi, jx, jy of f(t)
+  void *fbar;            // [2][2][y][x] (R): force adjoint
+  double *partials;      // [blocks][ADJ_N]
+  int lx, ly;
+  int cross_psi, pad_;
+  double K[2][5];        // G_ss,1 w(q) + G_ss,2 p(q)
+  double w[5], p[5], t[2];
+  double g1[2], g2[2], gab;
+  double body[2], tau[2], omega[2];
+  double psi0, irho0;
+  double rho_w[2], psi_w[2];
+  double cW, cQ;         // per-step loss weights
+};
+
+// Per-block partial sums of the adjoint: parameter sensitivities and the loss.
+enum AdjSlot { ADJ_G1A = 0, ADJ_G1B, ADJ_G2A, ADJ_G2B, ADJ_GAB, ADJ_GX, ADJ_GY, ADJ_LW, ADJ_LQ, ADJ_N };
+
+int adj_blocks(int lx, int ly);
+hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, double *acc, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
 // Host-side launchers (lb_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nblocks, const StepArgs &a,
                        hipStream_t st);

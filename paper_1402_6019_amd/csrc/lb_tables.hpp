@@ -26,4 +26,12 @@ constexpr double W_ATTR[NSHELL] = {4.0 / 45.0, 1.0 / 30.0, 1.0 / 360.0, 0.0, 0.0
 constexpr double P_REP[NSHELL] = {4.0 / 63.0, 4.0 / 135.0, 1.0 / 180.0, 2.0 / 945.0, 1.0 / 15120.0};
 constexpr double T_CROSS[2] = {1.0 / 9.0, 1.0 / 36.0};
 
+// One link of each +-c pair of the two belts ("half-links"), with its shell index: the force
+// sum over 24 links is a sum over these 12 of K(q) c (psi(x + c) - psi(x - c)).  The first
+// four form the first belt (|c|^2 = 1, 2) used by the A-B repulsion.
+constexpr int NHALF = 12;
+constexpr int HX[NHALF] = {1, 0, 1, 1, 2, 0, 2, 1, 1, 2, 2, 2};
+constexpr int HY[NHALF] = {0, 1, 1, -1, 0, 2, 1, 2, -2, -1, 2, -2};
+constexpr int HQ[NHALF] = {0, 0, 1, 1, 2, 2, 3, 3, 3, 3, 4, 4};
+
 }  // namespace lb355

@@ -1,0 +1,173 @@
+"""The hand-written adjoint: gradients of the time-averaged wall stress and flow rate with
+respect to G_ss,1, G_ss,2, G_AB and g, against the oracle's complex-step gradient (FP64)
+and against central finite differences of the GPU forward (FP64 and FP32)."""
+
+import numpy as np
+import pytest
+
+import lbgen
+from cases import emulsion_case, film_case, make_oracle, make_sim, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+def channel(lx=40, ly=24, storage="f64", seed=11, g=2e-5):
+    c = emulsion_case(lx, ly, walls=True, fraction=0.7, seed=seed, rmin=4, rmax=7, g=g)
+    c["storage"] = storage
+    return c
+
+
+def oracle_grads(c, T, lw):
+    from oracle import cs_grad
+    P = oracle_params(c)
+    f0 = make_oracle(c).get_f()
+    out = [cs_grad(P, f0, T, lw, k) for k in range(4)]
+    return out[0][0], np.array([d for _, d in out])
+
+
+def to4(g7):
+    """(G1 of both species, G2 of both species, G_AB, g_x) from the per-species gradient."""
+    return np.array([g7[0] + g7[1], g7[2] + g7[3], g7[4], g7[5]])
+
+
+@pytest.mark.parametrize("every", [8, 0])
+def test_adjoint_fp64_matches_oracle_complex_step_channel(every):
+    c = channel()
+    T, lw = 60, (1.0, 0.3)
+    sim = make_sim(c)
+    loss, g7 = sim.adjoint(T, lw, every=every)
+    L_o, d_o = oracle_grads(c, T, lw)
+    print(f"every={every}: loss {loss:.12e} vs {L_o:.12e}; grad {to4(g7)} vs {d_o}", flush=True)
+    assert loss == pytest.approx(L_o, rel=1e-10)
+    np.testing.assert_allclose(to4(g7), d_o, rtol=1e-8, atol=1e-12 * np.abs(d_o).max())
+    sim.close()
+
+
+def test_adjoint_fp64_single_component_periodic():
+    """One component, periodic, body force (no walls: the loss is the flow rate only)."""
+    from oracle import cs_grad
+    n = 32
+    c = film_case(n, n)
+    c["rho"] = lbgen.disc(n, n, 8, 1.39, 0.28)[None]
+    c["body"] = (3e-5, 0.0)
+    T, lw = 40, (0.0, 1.0)
+    sim = make_sim(c)
+    loss, g7 = sim.adjoint(T, lw)
+    P = oracle_params(c)
+    f0 = make_oracle(c).get_f()
+    ref = [cs_grad(P, f0, T, lw, k) for k in (0, 1, 3)]
+    assert loss == pytest.approx(ref[0][0], rel=1e-10)
+    got = [g7[0], g7[2], g7[5]]
+    for k in range(3):
+        assert got[k] == pytest.approx(ref[k][1], rel=1e-8, abs=1e-14)
+    sim.close()
+
+
+def forward_loss(c, T, lw):
+    """L from the forward path's own FP64 reductions: the flow rate Q(t) of every state
+    (lb_totals) and the wall stress averaged over T reduced steps (lb_wall_stress)."""
+    sim = make_sim(c)
+    sim.set_reduce_every(1)
+    sim.wall_stress(reset=True)
+    q = 0.0
+    for _ in range(T):
+        q += sim.totals()[2]
+        sim.step(1)
+    wb, wt = sim.wall_stress(reset=True)
+    sim.close()
+    return lw[0] * 0.5 * (wb + wt) + lw[1] * q / T
+
+
+def fd_grads(c, T, lw, h_rel=1e-4):
+    """Central differences (relative step h_rel) of the GPU FP64 forward loss."""
+    def loss(g1, g2, gab, gx):
+        return forward_loss(dict(c, g1=g1, g2=g2, gab=gab, body=(gx, 0.0), storage="f64"), T, lw)
+
+    base = dict(g1=tuple(c["g1"]), g2=tuple(c["g2"]), gab=c["gab"], gx=c["body"][0])
+    out = []
+    for k, name in enumerate(("g1", "g2", "gab", "gx")):
+        if name in ("g1", "g2"):
+            h = h_rel * abs(np.mean(base[name]))
+            p = dict(base, **{name: tuple(v + h for v in base[name])})
+            m = dict(base, **{name: tuple(v - h for v in base[name])})
+        else:
+            h = h_rel * abs(base[name])
+            p = dict(base, **{name: base[name] + h})
+            m = dict(base, **{name: base[name] - h})
+        out.append((loss(**p) - loss(**m)) / (2 * h))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-4), ("f32", 1e-4)])
+def test_adjoint_against_central_differences(storage, tol):
+    """Within 1e-4 of central differences with a relative step of 1e-4.  The differences'
+    own truncation error is of order 1e-5 here (the exact check is the complex-step one)."""
+    c = channel(64, 32, storage=storage, seed=12)
+    T, lw = 200, (1.0, 0.5)
+    sim = make_sim(c)
+    loss, g7 = sim.adjoint(T, lw)
+    L_fwd = forward_loss(dict(c, storage="f64"), T, lw)
+    fd = fd_grads(c, T, lw)
+    err = np.abs(to4(g7) - fd) / np.abs(fd)
+    print(f"{storage}: loss {loss:.10e} (forward reductions {L_fwd:.10e}); adjoint {to4(g7)} fd {fd} "
+          f"rel err {err}", flush=True)
+    assert loss == pytest.approx(L_fwd, rel=1e-10 if storage == "f64" else 1e-4)
+    assert err.max() < tol
+    sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_leaves_the_state_of_plain_stepping(storage):
+    c = channel(50, 20, storage=storage, seed=13)
+    a, b = make_sim(c), make_sim(c)
+    a.adjoint(37, (1.0, 1.0), every=5)
+    b.step(37)
+    assert a.time == b.time == 37
+    assert np.array_equal(a.checkpoint().cpu().numpy(), b.checkpoint().cpu().numpy())
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.checkpoint().cpu().numpy(), b.checkpoint().cpu().numpy())
+    a.close()
+    b.close()
+
+
+def test_autograd_function_shared_coupling():
+    """theta = (G1, G2, G_AB, g) with G1, G2 shared by both species, through torch autograd."""
+    import torch
+    from paper_1402_6019_amd.adjoint import channel_loss
+    c = channel(40, 24, seed=14)
+    c["g1"] = (-9.0, -9.0)
+    c["g2"] = (8.1, 8.1)
+    sim = make_sim(c)
+    f0 = sim.checkpoint().clone()
+    T, lw = 50, (1.0, 0.3)
+    th = torch.tensor([-9.0, 8.1, c["gab"], c["body"][0]], dtype=torch.float64, requires_grad=True)
+    theta6 = torch.stack([th[0], th[0], th[1], th[1], th[2], th[3]])
+    L = channel_loss(theta6, sim, f0, T, lw)
+    (g,) = torch.autograd.grad(L, th)
+    L_o, d_o = oracle_grads(c, T, lw)
+    assert float(L.detach()) == pytest.approx(L_o, rel=1e-10)
+    np.testing.assert_allclose(g.numpy(), d_o, rtol=1e-8, atol=1e-12 * np.abs(d_o).max())
+    # a second evaluation from the same initial state gives the same value
+    L2 = channel_loss(theta6.detach(), sim, f0, T, lw)
+    assert float(L2) == float(L.detach())
+    sim.close()
+
+
+def test_adjoint_full_size_channel_against_oracle_short_horizon():
+    """The 512 x 256 confined emulsion channel at its real size: FP64 adjoint against the
+    oracle's complex-step gradient over a short horizon (the oracle runs in complex
+    arithmetic on the CPU)."""
+    lx, ly = 512, 256
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.8, seed=5, walls=True)
+    c = dict(lx=lx, ly=ly, ns=2, walls=1, g1=(-9.0, -9.0), g2=(8.1, 8.1), gab=lbgen.EMULSION_GAB, body=(1e-6, 0.0),
+             rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0, rho=rho,
+             storage="f64", rho_ref=(0.0, 0.0))
+    T, lw = 12, (1.0, 1.0)
+    sim = make_sim(c)
+    loss, g7 = sim.adjoint(T, lw)
+    L_o, d_o = oracle_grads(c, T, lw)
+    print(f"512x256: loss {loss:.12e} vs {L_o:.12e}; grad {to4(g7)} vs {d_o}", flush=True)
+    assert loss == pytest.approx(L_o, rel=1e-10)
+    np.testing.assert_allclose(to4(g7), d_o, rtol=1e-7, atol=1e-12 * np.abs(d_o).max())
+    sim.close()
