@@ -134,6 +134,82 @@ def batched_sweep(steps, n=64):
             "footprint_mb": 144 * sites / 1e6}
 
 
+def adjoint_channel(T=4000, prerelax=2000, check_fd=True):
+    """Gradient of L = <(W_bot + W_top)/2> + <Q> over T steps with respect to (G1, G2, G_AB,
+    g_x) on a 512 x 256 confined emulsion channel (G1, G2 shared by both species), after an
+    FP64 pre-relaxation that is not differentiated: FP32 forward and reverse sweep with
+    sqrt(T) FP64 checkpoints.  Checked against central differences (relative step 1e-4) of
+    the FP64 forward path's own reductions."""
+    import numpy as np
+    import torch
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    lx, ly = 512, 256
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.8, seed=5, walls=True)
+    base = dict(n_species=2, walls=True, g1=(-9.0, -9.0), g2=(8.1, 8.1), gab=lbgen.EMULSION_GAB, body=(1e-6, 0.0),
+                rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0)
+    pre = Sim(lx, ly, rho, storage="f64", **base)
+    pre.step(prerelax)
+    f0 = pre.checkpoint().clone()
+    pre.close()
+    lw = (1.0, 1.0)
+    sim = Sim(lx, ly, rho, storage="f32", **base)
+    sim.restore(f0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, g7 = sim.adjoint(T, lw, fp64_reverse=True)
+    t_adj = time.perf_counter() - t0
+    sim.restore(f0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss32, g7_32 = sim.adjoint(T, lw, fp64_reverse=False)
+    t_adj32 = time.perf_counter() - t0
+    sim.restore(f0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(T)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    sim.close()
+    grad = [g7[0] + g7[1], g7[2] + g7[3], g7[4], g7[5]]
+    grad32 = [g7_32[0] + g7_32[1], g7_32[2] + g7_32[3], g7_32[4], g7_32[5]]
+    keys = ("G1", "G2", "G_AB", "g_x")
+    out = {"workload": f"confined emulsion channel {lx}x{ly}, G1 = -9.0, G2 = 8.1 both species, g = 1e-6, "
+                       f"fraction 0.8, seed 5, {prerelax} FP64 steps of pre-relaxation, then T = {T}",
+           "storage": "FP32 forward (and recompute), FP64 checkpoints every ceil(sqrt(T)) steps, reverse sweep in "
+                      "FP64 (grad) and in FP32 (grad_fp32_reverse)",
+           "loss": loss, "grad": dict(zip(keys, grad)), "grad_fp32_reverse": dict(zip(keys, grad32)),
+           "seconds_adjoint": t_adj, "seconds_adjoint_fp32_reverse": t_adj32, "seconds_forward_only": t_fwd,
+           "adjoint_over_forward": t_adj / t_fwd}
+    if check_fd:
+        def fwd_loss(**kw):
+            p = dict(base, **kw)
+            sm = Sim(lx, ly, rho, storage="f64", **p)
+            sm.restore(f0)
+            sm.set_reduce_every(1)
+            sm.wall_stress(reset=True)
+            q = 0.0
+            for _ in range(T):
+                q += sm.totals()[2]
+                sm.step(1)
+            wb, wt = sm.wall_stress(reset=True)
+            sm.close()
+            return lw[0] * 0.5 * (wb + wt) + lw[1] * q / T
+        names = ("g1", "g2", "gab", "body")
+        vals = (-9.0, 8.1, lbgen.EMULSION_GAB, 1e-6)
+        fd = []
+        for name, v in zip(names, vals):
+            h = 1e-4 * abs(v)
+            def kw(x):
+                return {name: (x, x)} if name in ("g1", "g2") else ({name: x} if name == "gab" else {name: (x, 0.0)})
+            fd.append((fwd_loss(**kw(v + h)) - fwd_loss(**kw(v - h))) / (2 * h))
+        out["fd_central_h1e-4"] = dict(zip(("G1", "G2", "G_AB", "g_x"), fd))
+        out["rel_err_vs_fd"] = dict(zip(keys, [abs(a - b) / abs(b) for a, b in zip(grad, fd)]))
+        out["rel_err_vs_fd_fp32_reverse"] = dict(zip(keys, [abs(a - b) / abs(b) for a, b in zip(grad32, fd)]))
+        out["loss_fp64_forward"] = fwd_loss()
+    return out
+
+
 def copy_reference(nbytes, steps):
     """Plain device-to-device copy of one population buffer (torch's copy kernel), timed the
     same way: the practical streaming ceiling at this footprint, and the known-size kernel that
@@ -328,6 +404,7 @@ def main():
         "copy_reference": copy,
         "beyond_infinity_cache": channel_beyond_cache(max(50, args.steps // 4)),
         "batched_sweep": batched_sweep(max(100, args.steps // 10)),
+        "adjoint": adjoint_channel(check_fd=not args.no_cpu),
         "kernel_source_hash": khash,
     }
     if not args.no_cpu:

@@ -192,14 +192,18 @@ int lb_set_couplings(lb_ctx *ctx, const lb_couplings *cpl);
  * *loss = L and grad[7] = dL/d(G_AA,1, G_BB,1, G_AA,2, G_BB,2, G_AB, g_x, g_y).
  * The forward pass keeps an FP64 checkpoint of the populations every `every` steps
  * (every <= 0: ceil(sqrt(T))); the reverse sweep recomputes each segment's states from its
- * checkpoint and runs the hand-written reverse step (FP64 for LB_F64 contexts, FP32
- * otherwise).  workspace: device buffer of lb_adjoint_workspace_bytes(ctx, T, every) bytes,
+ * checkpoint and runs the hand-written reverse step (FP64 for LB_F64 contexts or with
+ * flags & LB_ADJ_FP64, FP32 otherwise).  workspace: device buffer of
+ * lb_adjoint_workspace_bytes(ctx, T, every, flags) bytes,
  * owned by the caller.  On return the context holds the state after T steps, bit for bit as
  * lb_step(ctx, T) would leave it, and lb_time has advanced by T; the running wall-stress
  * average is reset.  Synchronises. */
-size_t lb_adjoint_workspace_bytes(const lb_ctx *ctx, int64_t T, int32_t every);
-int lb_adjoint(lb_ctx *ctx, int64_t T, int32_t every, const double loss_weights[2], double *loss, double grad[7],
-               void *workspace, size_t workspace_bytes);
+enum lb_adjoint_flags {
+  LB_ADJ_FP64 = 1  /* reverse sweep in FP64 also for FP32 / BF16 contexts (forward stays in the storage mode) */
+};
+size_t lb_adjoint_workspace_bytes(const lb_ctx *ctx, int64_t T, int32_t every, int32_t flags);
+int lb_adjoint(lb_ctx *ctx, int64_t T, int32_t every, int32_t flags, const double loss_weights[2], double *loss,
+               double grad[7], void *workspace, size_t workspace_bytes);
 
 /* Message of the last failure on ctx (ctx = NULL: last failure of lb_init in this thread). */
 const char *lb_last_error(const lb_ctx *ctx);

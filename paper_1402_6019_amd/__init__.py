@@ -145,19 +145,21 @@ class Sim:
         self._chk(self._lib.lb_set_couplings(self._h, ctypes.byref(cpl)))
         self.cpl = cpl
 
-    def adjoint(self, T, loss_weights=(1.0, 0.0), every=0):
+    def adjoint(self, T, loss_weights=(1.0, 0.0), every=0, fp64_reverse=False):
         """Loss L = lw0 <(W_bot + W_top)/2> + lw1 <Q> over the next T steps and its gradient
         dL/d(G_AA,1, G_BB,1, G_AA,2, G_BB,2, G_AB, g_x, g_y) by the hand-written adjoint with
-        checkpoints every `every` steps (0: sqrt(T)).  Advances the state by T steps."""
+        checkpoints every `every` steps (0: sqrt(T)); fp64_reverse runs the reverse sweep in
+        FP64 for FP32 / BF16 storage.  Advances the state by T steps."""
         torch = self.torch
-        nbytes = self._lib.lb_adjoint_workspace_bytes(self._h, int(T), int(every))
+        flags = B.LB_ADJ_FP64 if fp64_reverse else 0
+        nbytes = self._lib.lb_adjoint_workspace_bytes(self._h, int(T), int(every), flags)
         if nbytes == 0:
             raise LbError(B.LB_EINVAL, "invalid adjoint request")
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         lw = (ctypes.c_double * 2)(*[float(v) for v in loss_weights])
         loss = ctypes.c_double()
         grad = (ctypes.c_double * 7)()
-        self._chk(self._lib.lb_adjoint(self._h, int(T), int(every), lw, ctypes.byref(loss), grad,
+        self._chk(self._lib.lb_adjoint(self._h, int(T), int(every), flags, lw, ctypes.byref(loss), grad,
                                        ctypes.c_void_p(ws.data_ptr()), nbytes))
         del ws
         return loss.value, np.array(grad[:])

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblb355.so")
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_F64, LB_F32, LB_BF16DEV = 0, 1, 2
 LB_OUT_F64, LB_OUT_F32 = 0, 1
+LB_ADJ_FP64 = 1
 STATUS_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_EDEVICE",
                 LB_EUNSTABLE: "LB_EUNSTABLE", LB_ESTATE: "LB_ESTATE"}
 
@@ -62,8 +63,8 @@ SIGNATURES = {
     "lb_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "lb_set_graph": (ctypes.c_int, [_vp, _i32]),
     "lb_set_couplings": (ctypes.c_int, [_vp, ctypes.POINTER(LbCouplings)]),
-    "lb_adjoint_workspace_bytes": (_sz, [_vp, _i64, _i32]),
-    "lb_adjoint": (ctypes.c_int, [_vp, _i64, _i32, _dp, _dp, _dp, _vp, _sz]),
+    "lb_adjoint_workspace_bytes": (_sz, [_vp, _i64, _i32, _i32]),
+    "lb_adjoint": (ctypes.c_int, [_vp, _i64, _i32, _i32, _dp, _dp, _dp, _vp, _sz]),
     "lb_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]),
     "lb_last_error": (ctypes.c_char_p, [_vp]),
     "lb_destroy": (None, [_vp]),

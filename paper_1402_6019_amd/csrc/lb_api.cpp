@@ -489,13 +489,15 @@ struct AdjLayout {
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-AdjLayout adjoint_layout(const lb_ctx *c, int64_t T, int32_t every) {
+bool adjoint_fp64(const lb_ctx *c, int32_t flags) { return c->lat.storage == LB_F64 || (flags & LB_ADJ_FP64); }
+
+AdjLayout adjoint_layout(const lb_ctx *c, int64_t T, int32_t every, int32_t flags) {
   AdjLayout L;
   L.every = every > 0 ? every : std::max<int>(1, (int)std::ceil(std::sqrt((double)T)));
   L.every = (int)std::min<int64_t>(L.every, std::max<int64_t>(T, 1));
   L.ncp = (int)((T + L.every - 1) / L.every);
   L.nsite = (size_t)c->lat.lx * c->lat.ly;
-  const size_t rs = c->lat.storage == LB_F64 ? 8 : 4;
+  const size_t rs = adjoint_fp64(c, flags) ? 8 : 4;
   const int ns = c->lat.n_species;
   L.s64 = align256((size_t)ns * 9 * L.nsite * 8);
   L.lamb = align256((size_t)ns * 9 * L.nsite * rs);
@@ -548,18 +550,19 @@ AdjArgs adjoint_args(const lb_ctx *c, double lw0, double lw1, int64_t T) {
 
 extern "C" {
 
-size_t lb_adjoint_workspace_bytes(const lb_ctx *c, int64_t T, int32_t every) {
+size_t lb_adjoint_workspace_bytes(const lb_ctx *c, int64_t T, int32_t every, int32_t flags) {
   if (!c || T < 1) return 0;
-  return adjoint_layout(c, T, every).total;
+  return adjoint_layout(c, T, every, flags).total;
 }
 
-int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, const double loss_weights[2], double *loss, double grad[7],
-               void *workspace, size_t workspace_bytes) {
+int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double loss_weights[2], double *loss,
+               double grad[7], void *workspace, size_t workspace_bytes) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (T < 1) return fail(c, LB_EINVAL, "T must be >= 1");
   if (!loss_weights || !grad) return fail(c, LB_EINVAL, "null argument");
   if (!workspace) return fail(c, LB_EINVAL, "null workspace");
-  const AdjLayout L = adjoint_layout(c, T, every);
+  if (flags & ~LB_ADJ_FP64) return fail(c, LB_EINVAL, "unknown adjoint flags");
+  const AdjLayout L = adjoint_layout(c, T, every, flags);
   if (workspace_bytes < L.total) return fail(c, LB_ENOMEM, "workspace smaller than lb_adjoint_workspace_bytes()");
   int rc = poll_health(c, true);
   if (rc) return rc;
@@ -591,7 +594,7 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, const double loss_weights[2]
   a.partials = reinterpret_cast<double *>(ws + L.partials);
   double *acc = reinterpret_cast<double *>(ws + L.acc);
   char *lam_next = ws + L.lam1, *lam_cur = ws + L.lam0;
-  const int fp64 = c->lat.storage == LB_F64;
+  const int fp64 = adjoint_fp64(c, flags) ? 1 : 0;
   for (int k = L.ncp - 1; k >= 0; --k) {
     const int len = (int)std::min<int64_t>(L.every, T - (int64_t)k * L.every);
     if ((rc = lb_restore(c, ws + L.ckpt + (size_t)k * L.s64))) return done(rc);

@@ -98,18 +98,18 @@ def fd_grads(c, T, lw, h_rel=1e-4):
     return np.array(out)
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-4), ("f32", 1e-4)])
-def test_adjoint_against_central_differences(storage, tol):
+@pytest.mark.parametrize("storage,fp64_reverse,tol", [("f64", False, 1e-4), ("f32", False, 1e-4), ("f32", True, 1e-4)])
+def test_adjoint_against_central_differences(storage, fp64_reverse, tol):
     """Within 1e-4 of central differences with a relative step of 1e-4.  The differences'
     own truncation error is of order 1e-5 here (the exact check is the complex-step one)."""
     c = channel(64, 32, storage=storage, seed=12)
     T, lw = 200, (1.0, 0.5)
     sim = make_sim(c)
-    loss, g7 = sim.adjoint(T, lw)
+    loss, g7 = sim.adjoint(T, lw, fp64_reverse=fp64_reverse)
     L_fwd = forward_loss(dict(c, storage="f64"), T, lw)
     fd = fd_grads(c, T, lw)
     err = np.abs(to4(g7) - fd) / np.abs(fd)
-    print(f"{storage}: loss {loss:.10e} (forward reductions {L_fwd:.10e}); adjoint {to4(g7)} fd {fd} "
+    print(f"{storage} fp64_reverse={fp64_reverse}: loss {loss:.10e} (forward reductions {L_fwd:.10e}); adjoint {to4(g7)} fd {fd} "
           f"rel err {err}", flush=True)
     assert loss == pytest.approx(L_fwd, rel=1e-10 if storage == "f64" else 1e-4)
     assert err.max() < tol
@@ -171,3 +171,31 @@ def test_adjoint_full_size_channel_against_oracle_short_horizon():
     assert loss == pytest.approx(L_o, rel=1e-10)
     np.testing.assert_allclose(to4(g7), d_o, rtol=1e-7, atol=1e-12 * np.abs(d_o).max())
     sim.close()
+
+
+def test_adjoint_full_horizon_fp32_forward():
+    """512 x 256 channel after 2000 FP64 steps of pre-relaxation, T = 4000: the gradient of
+    the FP32 forward with the FP64 reverse sweep agrees with the FP64 adjoint (which matches
+    the oracle and central differences above) within 1e-4; the all-FP32 reverse sweep's
+    error is printed (about 1e-3: its lattice sums cancel)."""
+    lx, ly = 512, 256
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.8, seed=5, walls=True)
+    c = dict(lx=lx, ly=ly, ns=2, walls=1, g1=(-9.0, -9.0), g2=(8.1, 8.1), gab=lbgen.EMULSION_GAB, body=(1e-6, 0.0),
+             rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0, rho=rho,
+             storage="f64", rho_ref=(0.0, 0.0))
+    pre = make_sim(c)
+    pre.step(2000)
+    f0 = pre.checkpoint().clone()
+    pre.close()
+    T, lw = 4000, (1.0, 1.0)
+    out = {}
+    for storage, fr in (("f64", False), ("f32", True), ("f32", False)):
+        sim = make_sim(dict(c, storage=storage, rho_ref=(float(rho[0].mean()), float(rho[1].mean()))))
+        sim.restore(f0)
+        out[(storage, fr)] = to4(sim.adjoint(T, lw, fp64_reverse=fr)[1])
+        sim.close()
+    ref = out[("f64", False)]
+    e_mixed = np.abs(out[("f32", True)] - ref) / np.abs(ref)
+    e_f32 = np.abs(out[("f32", False)] - ref) / np.abs(ref)
+    print(f"T=4000: FP32 forward + FP64 reverse rel err {e_mixed}; all-FP32 {e_f32}", flush=True)
+    assert e_mixed.max() < 1e-4
