@@ -9,7 +9,7 @@ The headline value is the FP32-storage throughput in MLUPS (million lattice-site
 second, a two-component site counting once), with the FP64 path, the BF16-deviation path and
 the FP32/BF16 error against the FP64 CPU oracle reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--core]
 """
 
 import argparse
@@ -345,6 +345,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
     ap.add_argument("--tile", type=str, default=None, help="tx,sy launch shape")
+    ap.add_argument("--core", action="store_true",
+                    help="headline lattice and copy only (skip the channel, batched and adjoint legs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -402,9 +404,9 @@ def main():
                             "bf16dev": res["f64"]["ms_per_step"] / res["bf16dev"]["ms_per_step"]},
         "tiles": {k: v["tile"] for k, v in res.items()},
         "copy_reference": copy,
-        "beyond_infinity_cache": channel_beyond_cache(max(50, args.steps // 4)),
-        "batched_sweep": batched_sweep(max(100, args.steps // 10)),
-        "adjoint": adjoint_channel(check_fd=not args.no_cpu),
+        "beyond_infinity_cache": None if args.core else channel_beyond_cache(max(50, args.steps // 4)),
+        "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
+        "adjoint": None if args.core else adjoint_channel(check_fd=not args.no_cpu),
         "kernel_source_hash": khash,
     }
     if not args.no_cpu:
