@@ -435,62 +435,74 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     }
   };
 
-  // Register FIFO of pulled populations, two rows of lookahead.  Rows are named in march
-  // order below (y + 4 means y + 4 dir).  The populations of lead row y+4 are loaded in the
-  // iteration of output row y, turned into psi in the next iteration, and are the stage-2
-  // input of row y+4 four iterations after loading; five row buffers (the main loop is
-  // unrolled by five so their roles rotate statically) mean every population is loaded once
-  // per step, a full iteration of arithmetic before its first use.
-  L B[5][NS][9];
-  L HV[2];  // halo items of the lead row in flight
+  // Register FIFO of pulled populations, D row buffers.  Rows are named in march order below
+  // (y + 4 means y + 4 dir); row y0 + m lives in B[m mod D].  The populations of row y+D-1
+  // are loaded in the iteration of output row y, turned into psi D-4 iterations later (as
+  // ring row y'+3 of output row y' = y+D-4) and are the stage-2 input of their own row D-1
+  // iterations after loading: every population is loaded once per step, D-4 full
+  // iterations before its first use.  The halo items of a lead row are held in registers
+  // for the same D-4 iterations (NHV sets).  D = 5: a deeper FIFO does not help, because a
+  // wave can have at most 63 memory instructions outstanding and one row issues 38 (loads
+  // and stores count alike), so loads two rows ahead cannot be waited for selectively.
+  constexpr int D = 5;
+  constexpr int NHV = D - 4;
+  L B[D][NS][9];
+  L HV[NHV][2];
 
-  // Prologue: ring rows y0-2 .. y0+2 (slots 0..4).  Rows y0 .. y0+2 stay in B[1..3]; the
-  // loads of row y0+3 go to B[4] once row y0-1 has been consumed from it.
+  // Prologue: ring rows y0-2 .. y0+2 (slots 0..4) from B[D-1] (row y0-2), B[D-2] (row y0-1,
+  // then reloaded with row y0+D-2) and B[0..2]; rows y0+3 .. y0+D-3 go to B[3..D-3] with
+  // their halo items in HV[0..D-6], and row y0+D-2's halo items to HV[D-5].
   {
-    constexpr int bufp[5] = {0, 4, 1, 2, 3};
     L HP[5][2];
+    auto load_row = [&](int r, L (&dstb)[NS][9], L (&hv)[2]) {
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r, ly), ly, row_b);
+      load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, dstb);
+      halo_load(pr, hv);
+    };
+    load_row(y0 - 2 * dir, B[D - 1], HP[0]);
+    load_row(y0 - dir, B[D - 2], HP[1]);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(y0 + dir * (k - 2), ly), ly, row_b);
-      load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, B[bufp[k]]);
-      halo_load(pr, HP[k]);
-    }
+    for (int m = 0; m < 3; ++m) load_row(y0 + dir * m, B[m], HP[m + 2]);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      ring_row(k, y0 + dir * (k - 2), B[bufp[k]]);
+    for (int m = 3; m <= D - 3; ++m) load_row(y0 + dir * m, B[m], HV[m - 3]);
+    ring_row(0, y0 - 2 * dir, B[D - 1]);
+    halo_stage(0, HP[0]);
+    ring_row(1, y0 - dir, B[D - 2]);
+    halo_stage(1, HP[1]);
+    load_row(y0 + dir * (D - 2), B[D - 2], HV[D - 5]);
+#pragma unroll
+    for (int k = 2; k < 5; ++k) {
+      ring_row(k, y0 + dir * (k - 2), B[k - 2]);
       halo_stage(k, HP[k]);
-      if (k == 1) {
-        const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(y0 + 3 * dir, ly), ly, row_b);
-        load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, B[4]);
-        halo_load(pr, HV);
-      }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 5; ++k) halo_finish(k, k, y0 + dir * (k - 2));
   }
 
-  // One output row y (march order; FIFO roles: FL <- lead row y+4, f = row y, FR = lead
-  // row y+3):
-  //   stage the halo items of lead row y+3 -> issue the loads of lead row y+4 -> barrier ->
+  // One output row y (march order; FIFO roles: FL <- lead row y+D-1, f = row y, FR = lead
+  // row y+3, hv: halo items of row y+3 in, of row y+D-1 out):
+  //   stage the halo items of lead row y+3 -> issue the loads of lead row y+D-1 -> barrier ->
   //   ring row y+3 (interior and halo) -> force + collision of row y, store.
   // Loads and stores carry no lane or row conditions (lanes past a ragged strip's end store
   // into the row padding), so every wait covers exactly the batch it needs.  The ring slot
   // written last, (y+3) mod 6, is not among the rows y-2..y+2 that slower waves may still
   // read, and the halo staging buffers alternate between iterations.
-  auto step_row = [&](const int y_in, const int lead_slot_in, L (&FL)[NS][9], const L (&fraw)[NS][9],
-                      const L (&FR)[NS][9]) {
+  auto step_row = [&](const int y_in, const int lead_slot_in, const int hbuf_in, L (&FL)[NS][9],
+                      const L (&fraw)[NS][9], const L (&FR)[NS][9], L (&hv)[2]) {
     // the row index is uniform; saying so keeps every row offset in SGPRs
     const int y = (int)uni((uint32_t)y_in);
     const int lead_slot = (int)uni((uint32_t)lead_slot_in);
-    const int hbuf = 5 + ((y + 3) & 1);
+    const int hbuf = (int)uni((uint32_t)hbuf_in);
     const uint32_t rb0 = (uint32_t)y * row_b;
-    halo_stage(hbuf, HV);
-    {
-      const int r4 = dir > 0 ? min(y + 4, ylast) : max(y - 4, ylast);
-      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r4, ly), ly, row_b);
+    halo_stage(hbuf, hv);
+    // lead rows past the last one the segment needs are not loaded (uniform branch); their
+    // buffers then feed only ring rows that no output row reads
+    const int rl = y + dir * (D - 1);
+    if (dir > 0 ? rl <= ylast : rl >= ylast) {
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rl, ly), ly, row_b);
       load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, FL);
-      halo_load(pr, HV);
+      halo_load(pr, hv);
     }
 
     __syncthreads();
@@ -689,22 +701,18 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   int lead_slot = 5;
   auto next_slot = [](int sl) { return sl == 5 ? 0 : sl + 1; };
   const int nrow = yB - yA;
-  for (int i = 0; i < nrow;) {
-    step_row(y0 + dir * i, lead_slot, B[0], B[1], B[4]);
-    lead_slot = next_slot(lead_slot);
-    if (++i >= nrow) break;
-    step_row(y0 + dir * i, lead_slot, B[1], B[2], B[0]);
-    lead_slot = next_slot(lead_slot);
-    if (++i >= nrow) break;
-    step_row(y0 + dir * i, lead_slot, B[2], B[3], B[1]);
-    lead_slot = next_slot(lead_slot);
-    if (++i >= nrow) break;
-    step_row(y0 + dir * i, lead_slot, B[3], B[4], B[2]);
-    lead_slot = next_slot(lead_slot);
-    if (++i >= nrow) break;
-    step_row(y0 + dir * i, lead_slot, B[4], B[0], B[3]);
-    lead_slot = next_slot(lead_slot);
-    ++i;
+  // unrolled by D so the FIFO roles are static; the halo staging buffer alternates with the
+  // parity of the iteration (a fast wave stages the next row while a slow one may still read
+  // the current row's buffer)
+  for (int i0 = 0; i0 < nrow; i0 += D) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (i0 + k < nrow) {
+        step_row(y0 + dir * (i0 + k), lead_slot, 5 + ((i0 + k) & 1), B[(k + D - 1) % D], B[k], B[(k + 3) % D],
+                 HV[k % NHV]);
+        lead_slot = next_slot(lead_slot);
+      }
+    }
   }
 
   if (REDUCE) {
