@@ -349,10 +349,11 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
 
   // Halo columns x0-2, x0-1, x0+w, x0+w+1 (ring slots 0, 1, w+2, w+3).  Their 4 x NS x 9
   // pulled populations per lead row ("halo items", item it: column it / (9 NS), species
-  // (it / 9) % NS, plane it % 9) are spread over the workgroup as single loads, two per
-  // thread (threads without a second item re-load item 0, so no load sits under a lane
-  // condition), staged in LDS and summed in plane order by one lane per (column, species)
-  // in every wave -- the same sum, in the same order, as for an interior column.
+  // (it / 9) % NS, plane it % 9) are spread over the workgroup as single loads: one per
+  // thread, two when the strip has fewer threads than items (threads without an item
+  // re-load item 0, so no load sits under a lane condition); staged in LDS and summed in
+  // plane order by one lane per (column, species) in every wave -- the same sum, in the
+  // same order, as for an interior column.
   constexpr int NI = 36 * NS;
   R *hstage = reinterpret_cast<R *>(psi_ring + (NS == 2 ? 12 : 6) * W4);  // [7][NI]
   const int xhc0 = wrapi(x0 - 2, lx), xhc1 = wrapi(x0 - 1, lx), xhc2 = wrapi(x0 + w, lx),
@@ -400,8 +401,8 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   // finish (after a barrier) into ring slot `slot`.
   auto halo_load = [&](const RowOffs &r, L (&hv)[2]) {
     const Rsrc rs = make_rsrc(src, (uint32_t)NS * spec_b);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) hv[k] = C::bload(rs, halo_offset(hitem[k], r), 0u);
+    hv[0] = C::bload(rs, halo_offset(hitem[0], r), 0u);
+    if (TX < NI) hv[1] = C::bload(rs, halo_offset(hitem[1], r), 0u);  // uniform: narrow strips only
   };
   auto halo_stage = [&](int buf, const L (&hv)[2]) {
 #pragma unroll
