@@ -6,9 +6,9 @@
 //   body force  ->  velocity shift u_eq,s = u' + tau_s F_s / rho_s  ->  BGK collision
 //   ->  store of the post-collision populations (unshifted; the next step pulls them).
 //
-// Layout in HBM: [species][y][l][pitch], x fastest: for each species and row, the nine
-// population rows follow each other, so every load and store of a wavefront touches 64
-// consecutive elements and one row of all planes is one contiguous run.
+// Layout in HBM: [y][l][pitch][species], species fastest: the two species' populations of a
+// site are adjacent, so one load or store instruction moves both (8 bytes per lane in FP32),
+// and the nine plane rows of a lattice row follow each other as one contiguous run.
 //
 // Work decomposition: a workgroup owns a strip of tx columns (one thread per column) and a
 // segment of sy rows, and marches through its rows, down for even segments and up for odd
@@ -42,13 +42,14 @@ extern __shared__ __attribute__((aligned(16))) unsigned char lb_smem[];
 
 // ---------------------------------------------------------------------------------------
 // Storage codecs.  Populations are read and written through raw buffer instructions: the
-// buffer descriptor (one per species, SGPRs) holds the base address, the row and plane
-// offset is a uniform SGPR and only the column byte offset lives in a VGPR, so a load or
-// store costs no vector address arithmetic.  Each species' nine planes must span < 4 GiB.
+// buffer descriptor (SGPRs) holds the base address, the row and plane offset is a uniform
+// SGPR and only the column byte offset lives in a VGPR, so a load or store costs no vector
+// address arithmetic.  A population buffer must span < 4 GiB.
 // ---------------------------------------------------------------------------------------
 
 using Rsrc = __amdgpu_buffer_rsrc_t;
 using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
 // Base addresses and row offsets are uniform by construction (they depend only on the
 // workgroup and the row index); readfirstlane states that to the compiler, which otherwise
@@ -82,6 +83,16 @@ template <> struct Codec<MODE_F64> {
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
   }
+  // both species of a site (adjacent in memory) in one access
+  __device__ static void bload2(Rsrc r, uint32_t voff, uint32_t soff, L &a, L &b) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    a = __builtin_bit_cast(double, u32x2{v[0], v[1]});
+    b = __builtin_bit_cast(double, u32x2{v[2], v[3]});
+  }
+  __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
+    const u32x2 ua = __builtin_bit_cast(u32x2, a), ub = __builtin_bit_cast(u32x2, b);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{ua.x, ua.y, ub.x, ub.y}, r, voff, soff, 0);
+  }
   __device__ static R expo(R v) { return exp(v); }
   __device__ static R rcp(R v) { return 1.0 / v; }
 };
@@ -98,6 +109,17 @@ template <> struct Codec<MODE_F32> {
   }
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+  }
+  __device__ static void bload2(Rsrc r, uint32_t voff, uint32_t soff, L &a, L &b) {
+    // element access by index: with .x / .y and bit_cast this compiler narrowed the load
+    // to its first dword
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    a = __uint_as_float(v[0]);
+    b = __uint_as_float(v[1]);
+  }
+  __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b)},
+                                          r, voff, soff, 0);
   }
   __device__ static R expo(R v) { return __expf(v); }
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
@@ -128,6 +150,14 @@ template <> struct Codec<MODE_BF16> {
   }
   __device__ static R expo(R v) { return __expf(v); }
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
+  __device__ static void bload2(Rsrc r, uint32_t voff, uint32_t soff, L &a, L &b) {
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    a = uint16_t(v);
+    b = uint16_t(v >> 16);
+  }
+  __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)encode(a) | ((uint32_t)encode(b) << 16), r, voff, soff, 0);
+  }
 };
 
 template <typename R, int NS>
@@ -146,7 +176,7 @@ __device__ inline int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a -
 
 // Where the nine populations pulled into one site come from:
 //   f_l(x, y) = f*_l(x - c_l, y - c_l), or f*_opp(l)(x, y) when (x - c_l, y - c_l) is a wall.
-// A load address is  species base (buffer descriptor) + row and plane offset (SGPR) + column
+// A load address is  buffer base (descriptor) + row and plane offset (SGPR) + column
 // offset (VGPR).  Only the column bytes of x, x - 1 and x + 1 live in VGPRs, fixed for the
 // whole kernel; the plane and the source row go into the uniform offset.
 struct RowOffs {
@@ -159,7 +189,7 @@ struct LaneCols {
 };
 
 template <class C, int NS>
-__device__ inline void load_pull(const void *base, uint32_t spec_b, uint32_t plane_b, const LaneCols &col,
+__device__ inline void load_pull(const void *base, uint32_t buf_b, uint32_t plane_b, const LaneCols &col,
                                  const RowOffs &r, typename C::L (&f)[NS][9]) {
   // source of each population: (column offset, row + plane offset)
   const uint32_t P1 = plane_b, P2 = 2 * plane_b, P3 = 3 * plane_b, P4 = 4 * plane_b, P5 = 5 * plane_b,
@@ -176,12 +206,11 @@ __device__ inline void load_pull(const void *base, uint32_t spec_b, uint32_t pla
   vo[4] = col.c;                  so[4] = r.hi ? r.o + P2 : r.p + P4;  // plane 2 at x
   vo[7] = r.hi ? col.c : col.p;   so[7] = r.hi ? r.o + P5 : r.p + P7;  // plane 5 at x
   vo[8] = r.hi ? col.c : col.m;   so[8] = r.hi ? r.o + P6 : r.p + P8;  // plane 6 at x
+  const Rsrc rs = make_rsrc(base, buf_b);
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const Rsrc rs = make_rsrc(static_cast<const char *>(base) + (uint64_t)s * spec_b, spec_b);
-#pragma unroll
-    for (int l = 0; l < 9; ++l)  // W_opp(l) = W_l: a reflected deviation is still a deviation
-      f[s][l] = C::bload(rs, vo[l], uni(so[l]));
+  for (int l = 0; l < 9; ++l) {  // W_opp(l) = W_l: a reflected deviation is still a deviation
+    if (NS == 2) C::bload2(rs, vo[l], uni(so[l]), f[0][l], f[NS - 1][l]);
+    else f[0][l] = C::bload(rs, vo[l], uni(so[l]));
   }
 }
 
@@ -204,8 +233,8 @@ __device__ inline RowOffs row_pull(int r, int ly, uint32_t row_b) {
   return o;
 }
 
-// One pulled population of a halo column: lane offsets (species, plane and column folded
-// in) for the direct and the reflected source, and masks for c_y = +1 / -1 (all ones or 0;
+// One pulled population (both species) of a halo column: lane offsets (plane and column
+// folded in) for the direct and the reflected source, and masks for c_y = +1 / -1 (all ones or 0;
 // mask arithmetic instead of a three-way choice, which the compiler would otherwise turn
 // into a lookup table in scratch memory).
 struct HaloItem {
@@ -213,9 +242,7 @@ struct HaloItem {
   uint32_t up, dn;
 };
 
-template <int NS>
-__device__ inline HaloItem halo_item(int l, int sp, int xh, int lx, uint32_t es, uint32_t plane_b,
-                                     uint32_t spec_b) {
+__device__ inline HaloItem halo_item(int l, int xh, int lx, uint32_t site_b, uint32_t plane_b) {
   int cx = 0, cy = 0, op = 0;
   switch (l) {  // D2Q9 velocities and opposites
     case 0: cx = 0; cy = 0; op = 0; break;
@@ -229,8 +256,8 @@ __device__ inline HaloItem halo_item(int l, int sp, int xh, int lx, uint32_t es,
     default: cx = 1; cy = -1; op = 6; break;
   }
   HaloItem h;
-  h.direct = (uint32_t)sp * spec_b + (uint32_t)l * plane_b + (uint32_t)wrapi(xh - cx, lx) * es;
-  h.reflected = (uint32_t)sp * spec_b + (uint32_t)op * plane_b + (uint32_t)xh * es;
+  h.direct = (uint32_t)l * plane_b + (uint32_t)wrapi(xh - cx, lx) * site_b;
+  h.reflected = (uint32_t)op * plane_b + (uint32_t)xh * site_b;
   h.up = cy == 1 ? 0xffffffffu : 0u;
   h.dn = cy == -1 ? 0xffffffffu : 0u;
   return h;
@@ -300,11 +327,10 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   __shared__ double red_lds[4][RED_N];
 
   const int lx = a.lx, ly = a.ly;
-  // Layout [species][y][l][pitch]: the nine planes of a species are interleaved row by row,
-  // so one row of all nine planes is a single contiguous run (fewer, longer DRAM streams
-  // than whole planes).  plane_b: byte stride between planes l and l+1 of one row; row_b:
-  // byte stride between rows; spec_b: byte stride between species.
-  const uint32_t pitch_b = (uint32_t)a.pitch * sizeof(S);
+  // Layout [y][l][pitch][species]: site_b bytes per site (both species), plane_b: byte
+  // stride between planes l and l+1 of one row, row_b: between rows, buf_b: the buffer.
+  const uint32_t site_b = (uint32_t)(NS * sizeof(S));
+  const uint32_t pitch_b = (uint32_t)a.pitch * site_b;
   const uint32_t plane_b = pitch_b;
   const uint32_t row_b = 9u * pitch_b;
   const int x0 = strip * TX;
@@ -340,32 +366,29 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   // Interior column of this thread (ring slot tid + 2).
   const bool col_ok = tid < w;
   const int xc = x0 + (col_ok ? tid : 0);
-  const uint32_t es = (uint32_t)sizeof(S);
-  const uint32_t spec_b = 9u * (uint32_t)a.plane * (uint32_t)sizeof(S);
-  const LaneCols pcc = {(uint32_t)xc * es, (uint32_t)wrapi(xc - 1, lx) * es, (uint32_t)wrapi(xc + 1, lx) * es};
+  const uint32_t buf_b = 9u * (uint32_t)a.plane * site_b;
+  const LaneCols pcc = {(uint32_t)xc * site_b, (uint32_t)wrapi(xc - 1, lx) * site_b,
+                        (uint32_t)wrapi(xc + 1, lx) * site_b};
   // Store column: lanes past a ragged strip's end write into the row padding (the row
   // pitch is a multiple of the widest strip), which no kernel ever reads.
-  const uint32_t sto = (uint32_t)(x0 + tid) * es;
+  const uint32_t sto = (uint32_t)(x0 + tid) * site_b;
 
-  // Halo columns x0-2, x0-1, x0+w, x0+w+1 (ring slots 0, 1, w+2, w+3).  Their 4 x NS x 9
-  // pulled populations per lead row ("halo items", item it: column it / (9 NS), species
-  // (it / 9) % NS, plane it % 9) are spread over the workgroup as single loads: one per
-  // thread, two when the strip has fewer threads than items (threads without an item
+  // Halo columns x0-2, x0-1, x0+w, x0+w+1 (ring slots 0, 1, w+2, w+3).  Their 4 x 9 pulled
+  // sites per lead row ("halo items", item it: column it / 9, plane it % 9, both species in
+  // one load) are spread over the workgroup, one per thread (threads past the 36 items
   // re-load item 0, so no load sits under a lane condition); staged in LDS and summed in
   // plane order by one lane per (column, species) in every wave -- the same sum, in the
   // same order, as for an interior column.
-  constexpr int NI = 36 * NS;
-  R *hstage = reinterpret_cast<R *>(psi_ring + (NS == 2 ? 12 : 6) * W4);  // [7][NI]
+  constexpr int NI = 36;
+  R *hstage = reinterpret_cast<R *>(psi_ring + (NS == 2 ? 12 : 6) * W4);  // [7][NI][NS]
   const int xhc0 = wrapi(x0 - 2, lx), xhc1 = wrapi(x0 - 1, lx), xhc2 = wrapi(x0 + w, lx),
             xhc3 = wrapi(x0 + w + 1, lx);
-  HaloItem hitem[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    int it = tid + k * TX;
-    if (it >= NI) it = 0;
-    const int hc = it / (9 * NS), sp = (it / 9) % NS, l = it % 9;
+  HaloItem hitem;
+  {
+    const int it = tid < NI ? tid : 0;
+    const int hc = it / 9, l = it % 9;
     const int xh = hc == 0 ? xhc0 : (hc == 1 ? xhc1 : (hc == 2 ? xhc2 : xhc3));
-    hitem[k] = halo_item<NS>(l, sp, xh, lx, es, plane_b, spec_b);
+    hitem = halo_item(l, xh, lx, site_b, plane_b);
   }
 
   double acc[RED_N];
@@ -397,18 +420,17 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     if (NS == 2) rho_ring[slot * W4 + tid + 2] = rh;
   };
 
-  // Stage 1, halo columns: load (two items per thread), stage into LDS buffer `buf`, and
+  // Stage 1, halo columns: load (one item per thread), stage into LDS buffer `buf`, and
   // finish (after a barrier) into ring slot `slot`.
   auto halo_load = [&](const RowOffs &r, L (&hv)[2]) {
-    const Rsrc rs = make_rsrc(src, (uint32_t)NS * spec_b);
-    hv[0] = C::bload(rs, halo_offset(hitem[0], r), 0u);
-    if (TX < NI) hv[1] = C::bload(rs, halo_offset(hitem[1], r), 0u);  // uniform: narrow strips only
+    const Rsrc rs = make_rsrc(src, buf_b);
+    if (NS == 2) C::bload2(rs, halo_offset(hitem, r), 0u, hv[0], hv[1]);
+    else hv[0] = C::bload(rs, halo_offset(hitem, r), 0u);
   };
   auto halo_stage = [&](int buf, const L (&hv)[2]) {
+    if (tid < NI) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int it = tid + k * TX;
-      if (it < NI) hstage[buf * NI + it] = C::dec(hv[k]);
+      for (int s = 0; s < NS; ++s) hstage[(buf * NI + tid) * NS + s] = C::dec(hv[s]);
     }
   };
   auto halo_finish = [&](int buf, int slot, int r) {
@@ -423,10 +445,10 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
         rh = sp == 0 ? rhow[0] : rhow[NS - 1];
         ps = sp == 0 ? psiw[0] : psiw[NS - 1];
       } else {
-        const R *q = hstage + buf * NI + (hc * NS + sp) * 9;
+        const R *q = hstage + (buf * NI + hc * 9) * NS + sp;
         R sum = q[0];
 #pragma unroll
-        for (int l = 1; l < 9; ++l) sum += q[l];
+        for (int l = 1; l < 9; ++l) sum += q[l * NS];
         rh = rr + sum;
         ps = psi0 * (R(1) - C::expo(rh * nirho0));
       }
@@ -457,7 +479,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     L HP[5][2];
     auto load_row = [&](int r, L (&dstb)[NS][9], L (&hv)[2]) {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r, ly), ly, row_b);
-      load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, dstb);
+      load_pull<C, NS>(src, buf_b, plane_b, pcc, pr, dstb);
       halo_load(pr, hv);
     };
     load_row(y0 - 2 * dir, B[D - 1], HP[0]);
@@ -502,7 +524,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     const int rl = y + dir * (D - 1);
     if (dir > 0 ? rl <= ylast : rl >= ylast) {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rl, ly), ly, row_b);
-      load_pull<C, NS>(src, spec_b, plane_b, pcc, pr, FL);
+      load_pull<C, NS>(src, buf_b, plane_b, pcc, pr, FL);
       halo_load(pr, hv);
     }
 
@@ -636,6 +658,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
 
     if (WHAT != WHAT_MOMENTS) {
     double wb = 0.0, wt = 0.0;
+    R fsa[NS][9];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const R ir = C::rcp(rho[s]);
@@ -650,7 +673,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       // relaxation of one population towards W_l (drho - 3/2 rho u.u) + W_l rho cu (3 + 9/2 cu),
       // cu = c_l . u (r = W_l rho, b = the velocity-independent part); opposite links take -cu
       auto relax = [o](R fl, R b, R r, R cu) { return fmadd(o, fmadd(r, cu * fmadd(R(4.5), cu, R(3)), b) - fl, fl); };
-      R fs[9];
+      R (&fs)[9] = fsa[s];
       fs[1] = relax(f[s][1], b9, r9, ux);
       fs[3] = relax(f[s][3], b9, r9, -ux);
       fs[2] = relax(f[s][2], b9, r9, uy);
@@ -662,15 +685,17 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       // rest population closes the mass balance exactly: d*_0 = drho - sum_{l>0} d*_l
       fs[0] = drho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
 
-      if (STORE) {
-#pragma unroll
-        for (int l = 0; l < 9; ++l)
-          C::bstore(make_rsrc(static_cast<char *>(dst) + (uint64_t)s * spec_b, spec_b), sto,
-                    uni(rb0 + (uint32_t)l * plane_b), fs[l]);
-      }
       if (REDUCE && WALLS && col_ok) {
         if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7]));
         if (y == ly - 1) wt += 2.0 * (double(fs[5]) - double(fs[6]));
+      }
+    }
+    if (STORE) {
+      const Rsrc rd = make_rsrc(dst, buf_b);
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        if (NS == 2) C::bstore2(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
+        else C::bstore(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
       }
     }
 
@@ -823,9 +848,9 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const double *partial
 // and its inverse g_l(z) = f_l(z + c_l) if z + c_l is fluid, else f_opp(l)(z).
 // ---------------------------------------------------------------------------------------
 
-// Element index of population l of species s at (x, y): layout [species][y][l][pitch].
-__device__ inline long long pop_index(int s, int l, int y, int x, long long plane, int pitch) {
-  return (long long)s * 9 * plane + ((long long)y * 9 + l) * pitch + x;
+// Element index of population l of species s at (x, y): layout [y][l][pitch][species].
+__device__ inline long long pop_index(int s, int l, int y, int x, int pitch, int ns) {
+  return (((long long)y * 9 + l) * pitch + x) * ns + s;
 }
 
 template <int MODE, bool WALLS>
@@ -850,7 +875,7 @@ __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
         zy = wrapi(zy, a.ly);
       }
       const double v = WD2Q9[l] * rho[s * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + pop_index(s, l, y, x, a.plane, a.pitch), R(v),
+      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), R(v),
                R(WD2Q9[l] * a.rho_ref[s]));
     }
 }
@@ -878,7 +903,7 @@ __global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][l
         zy = wrapi(zy, a.ly);
       }
       const double v = f[(size_t)(s * 9 + lsrc) * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + pop_index(s, l, y, x, a.plane, a.pitch), R(v),
+      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), R(v),
                R(WD2Q9[l] * a.rho_ref[s]));
     }
 }
@@ -905,7 +930,7 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.plane, a.pitch),
+      const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns),
                           R(WD2Q9[lsrc] * a.rho_ref[s]));
       f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] = double(v);
     }
