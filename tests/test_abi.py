@@ -98,3 +98,51 @@ def test_product_package_does_not_reach_the_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text and "lb_oracle" not in text, f
+
+
+def _batch_init(B, lats, tau=None, rho=None, nbytes=1 << 40):
+    lib = B.load()
+    n = len(lats)
+    L = (B.LbLattice * n)(*lats)
+    C = (B.LbCouplings * n)(*[B.default_couplings() for _ in range(n)])
+    P = (B.LbPsiParams * n)(*[B.LbPsiParams(1.0, 1.0, (ctypes.c_double * 2)(0.0, 0.0)) for _ in range(n)])
+    T = (ctypes.c_double * (2 * n))(*(tau or [1.0] * (2 * n)))
+    arrs = rho or [np.ones((max(l.n_species, 1), max(l.ly, 1), max(l.lx, 1))) for l in lats]
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in arrs]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
+    h = ctypes.c_void_p()
+    rc = lib.lb_batch_init(ctypes.byref(h), n, L, C, T, P, ptrs, ctypes.c_void_p(16), ctypes.c_void_p(32), nbytes, None)
+    return rc, lib.lb_batch_last_error(None).decode()
+
+
+def test_batch_init_rejects_invalid_arguments_on_host(B):
+    a = B.LbLattice(16, 16, 2, 1, 1)
+    assert _batch_init(B, [a, B.LbLattice(20, 12, 2, 0, 1)])[0] == B.LB_EINVAL  # walls differ
+    assert "share" in _batch_init(B, [a, B.LbLattice(20, 12, 2, 1, 0)])[1]      # storage differs
+    assert _batch_init(B, [a, B.LbLattice(20, 12, 1, 1, 1)])[0] == B.LB_EINVAL  # species differ
+    rc, msg = _batch_init(B, [a, B.LbLattice(4, 12, 2, 1, 1)])
+    assert rc == B.LB_EINVAL and "instance 1" in msg
+    assert _batch_init(B, [a, a], tau=[1.0, 1.0, 0.4, 1.0])[0] == B.LB_EINVAL
+    bad = np.ones((2, 16, 16))
+    bad[1, 2, 3] = -1.0
+    assert _batch_init(B, [a, a], rho=[np.ones((2, 16, 16)), bad])[0] == B.LB_EINVAL
+    assert _batch_init(B, [a, a], nbytes=1000)[0] == B.LB_ENOMEM
+
+
+def test_batch_pop_bytes_is_the_aligned_sum(B):
+    lib = B.load()
+    lats = [B.LbLattice(300, 17, 2, 1, 1), B.LbLattice(70, 40, 2, 1, 1), B.LbLattice(64, 64, 2, 1, 1)]
+    arr = (B.LbLattice * 3)(*lats)
+    total = sum((B.pop_bytes(l) + 255) // 256 * 256 for l in lats)
+    assert lib.lb_batch_pop_bytes(3, arr) == total
+    assert lib.lb_batch_pop_bytes(0, arr) == 0
+
+
+def test_null_contexts_fail_cleanly(B):
+    lib = B.load()
+    assert lib.lb_step(None, 1) == B.LB_EINVAL
+    assert lib.lb_batch_step(None, 1) == B.LB_EINVAL
+    assert lib.lb_set_couplings(None, None) == B.LB_EINVAL
+    assert lib.lb_adjoint_workspace_bytes(None, 10, 0, 0) == 0
+    assert lib.lb_time(None) == -1
+    assert lib.lb_batch_time(None) == -1
