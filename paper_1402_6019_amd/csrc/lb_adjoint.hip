@@ -265,17 +265,21 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
 #pragma unroll
       for (int l = 0; l < Q; ++l)
         lampart[((size_t)s * Q + l) * v.n + i] = lp[s][l] + rbar[s] + R(CXS[l]) * jbx[s] + R(CYS[l]) * jby[s];
-      fbar[((size_t)s * 2 + 0) * v.n + i] = fbx[s];
-      fbar[((size_t)s * 2 + 1) * v.n + i] = fby[s];
+      // what the gather needs of this site: A_s = psi_s Fbar_s, B_s = r_s Fbar_s
+      fbar[((size_t)s * 4 + 0) * v.n + i] = psi[s] * fbx[s];
+      fbar[((size_t)s * 4 + 1) * v.n + i] = psi[s] * fby[s];
+      fbar[((size_t)s * 4 + 2) * v.n + i] = self[s] * fbx[s];
+      fbar[((size_t)s * 4 + 3) * v.n + i] = self[s] * fby[s];
     }
   }
-  // per-block partial sums (fixed order: waves, then blocks in the second pass)
+  // per-block partial sums, accumulated over the reverse steps in each block's own row
+  // (fixed order: waves, then steps, then blocks in the final pass)
   double vals[ADJ_N] = {dg1[0], dg1[1], dg2[0], dg2[1], dgab, dgx, dgy, loss_w, loss_q};
   const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
   for (int k = 0; k < ADJ_N; ++k) {
     const double t = block_sum(vals[k], sm);
-    if (threadIdx.x == 0) a.partials[blk * ADJ_N + k] = t;
+    if (threadIdx.x == 0) a.partials[blk * ADJ_N + k] += t;
   }
 }
 
@@ -290,16 +294,16 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
   const R *fbar = static_cast<const R *>(a.fbar);
   const R *lampart = static_cast<const R *>(a.lampart);
   R *lam = static_cast<R *>(a.lam);
-  // A_s = psi_s Fbar_s and B_s = r_s Fbar_s at a neighbour (zero on wall rows)
-  auto AB = [&](int k, int s, int dx, int dy, R &bx, R &by) {
+  // A_s = psi_s Fbar_s (which = 0) or B_s = r_s Fbar_s (which = 1) at a neighbour (zero on
+  // wall rows)
+  auto AB = [&](int which, int s, int dx, int dy, R &bx, R &by) {
     size_t j;
     if (!site_of<WALLS>(x + dx, y + dy, v.lx, v.ly, j)) {
       bx = by = 0;
       return;
     }
-    const R f = v.fld(k, s, j);
-    bx = f * fbar[((size_t)s * 2 + 0) * v.n + j];
-    by = f * fbar[((size_t)s * 2 + 1) * v.n + j];
+    bx = fbar[((size_t)s * 4 + 2 * which + 0) * v.n + j];
+    by = fbar[((size_t)s * 4 + 2 * which + 1) * v.n + j];
   };
   R psib[2] = {0, 0}, rbar[2] = {0, 0};
   for (int s = 0; s < NS; ++s) {
@@ -310,8 +314,8 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
 #pragma unroll
     for (int h = 0; h < NHALF; ++h) {
       R px, py, mx, my;
-      AB(1, s, HX[h], HY[h], px, py);
-      AB(1, s, -HX[h], -HY[h], mx, my);
+      AB(0, s, HX[h], HY[h], px, py);
+      AB(0, s, -HX[h], -HY[h], mx, my);
       acc += Kq[HQ[h]] * (R(HX[h]) * (px - mx) + R(HY[h]) * (py - my));
     }
     psib[s] += acc;
@@ -319,13 +323,12 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
   if (NS == 2) {
     for (int s = 0; s < 2; ++s) {  // species s's force depends on species o = 1 - s's field
       const int o = 1 - s;
-      const int k = a.cross_psi ? 1 : 0;
       R acc = 0;
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         R px, py, mx, my;
-        AB(k, s, HX[h], HY[h], px, py);
-        AB(k, s, -HX[h], -HY[h], mx, my);
+        AB(1, s, HX[h], HY[h], px, py);
+        AB(1, s, -HX[h], -HY[h], mx, my);
         acc += R(a.t[HQ[h]]) * (R(HX[h]) * (px - mx) + R(HY[h]) * (py - my));
       }
       // B_s uses species s's own r (r_s Fbar_s); it lands on the other species' field
@@ -360,23 +363,27 @@ __global__ void zero_kernel(uint32_t *p, size_t n) {
 int adj_blocks(int lx, int ly) { return ((lx + 255) / 256) * ly; }
 
 template <typename R, int NS, bool WALLS>
-static hipError_t adj_step_t(const AdjArgs &a, double *acc, hipStream_t st) {
+static hipError_t adj_step_t(const AdjArgs &a, hipStream_t st) {
   const dim3 grid((a.lx + 255) / 256, a.ly), block(256);
   hipLaunchKernelGGL((adj_fields_kernel<R, NS>), grid, block, 0, st, a);
   hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS>), grid, block, 0, st, a);
   hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), grid, block, 0, st, a);
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(256), 0, st, a.partials, (int)(grid.x * grid.y), acc);
   return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t adj_step_r(int ns, int walls, const AdjArgs &a, double *acc, hipStream_t st) {
-  if (ns == 1) return walls ? adj_step_t<R, 1, true>(a, acc, st) : adj_step_t<R, 1, false>(a, acc, st);
-  return walls ? adj_step_t<R, 2, true>(a, acc, st) : adj_step_t<R, 2, false>(a, acc, st);
+static hipError_t adj_step_r(int ns, int walls, const AdjArgs &a, hipStream_t st) {
+  if (ns == 1) return walls ? adj_step_t<R, 1, true>(a, st) : adj_step_t<R, 1, false>(a, st);
+  return walls ? adj_step_t<R, 2, true>(a, st) : adj_step_t<R, 2, false>(a, st);
 }
 
-hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, double *acc, hipStream_t st) {
-  return fp64 ? adj_step_r<double>(ns, walls, a, acc, st) : adj_step_r<float>(ns, walls, a, acc, st);
+hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, hipStream_t st) {
+  return fp64 ? adj_step_r<double>(ns, walls, a, st) : adj_step_r<float>(ns, walls, a, st);
+}
+
+hipError_t launch_adjoint_reduce(const double *partials, int lx, int ly, double *acc, hipStream_t st) {
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(256), 0, st, partials, adj_blocks(lx, ly), acc);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {

@@ -99,6 +99,21 @@ hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st) {
   return launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
 }
 
+// Canonical FP64 pre-collision populations of buffer `from` into dst, on stream st.
+hipError_t launch_checkpoint_from(const lb_ctx *c, int from, void *dst, hipStream_t st) {
+  LayoutArgs la{};
+  la.in = c->pop[from];
+  la.out = dst;
+  la.plane = c->plane;
+  la.lx = c->lat.lx;
+  la.ly = c->lat.ly;
+  la.pitch = c->pitch;
+  la.ns = c->lat.n_species;
+  la.rho_ref[0] = c->psi.rho_ref[0];
+  la.rho_ref[1] = c->psi.rho_ref[1];
+  return launch_checkpoint(c->lat.storage, c->lat.walls, la, st);
+}
+
 // One launch of the fused kernel on the current buffer.
 int run_step_kernel(lb_ctx *c, int what, void *out_rho, void *out_u, int out_f32) {
   int nseg = 0;
@@ -509,7 +524,7 @@ AdjLayout adjoint_layout(const lb_ctx *c, int64_t T, int32_t every, int32_t flag
   L.lam1 = o; o += L.lamb;
   L.lampart = o; o += L.lamb;
   L.fields = o; o += align256(8 * L.nsite * rs);
-  L.fbar = o; o += align256(4 * L.nsite * rs);
+  L.fbar = o; o += align256(8 * L.nsite * rs);
   L.partials = o; o += align256((size_t)adj_blocks(c->lat.lx, c->lat.ly) * ADJ_N * 8);
   L.acc = o; o += align256(ADJ_N * 8);
   L.total = o;
@@ -585,6 +600,8 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   hipError_t e = hipMemcpyAsync(ws + L.fin, c->pop[cur_final], popb, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = launch_zero(ws + L.lam1, L.lamb, c->stream);
   if (e == hipSuccess) e = launch_zero(ws + L.acc, ADJ_N * 8, c->stream);
+  if (e == hipSuccess)
+    e = launch_zero(ws + L.partials, (size_t)adj_blocks(c->lat.lx, c->lat.ly) * ADJ_N * 8, c->stream);
   if (e != hipSuccess) return done(hip_fail(c, e, "adjoint setup"));
   // reverse sweep, one checkpoint segment at a time
   AdjArgs a = adjoint_args(c, loss_weights[0], loss_weights[1], T);
@@ -593,24 +610,62 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   a.fbar = ws + L.fbar;
   a.partials = reinterpret_cast<double *>(ws + L.partials);
   double *acc = reinterpret_cast<double *>(ws + L.acc);
-  char *lam_next = ws + L.lam1, *lam_cur = ws + L.lam0;
+  char *lam_buf[2] = {ws + L.lam1, ws + L.lam0};  // lambda(t+1) is lam_buf[q], lambda(t) lam_buf[q ^ 1]
+  int q = 0;
   const int fp64 = adjoint_fp64(c, flags) ? 1 : 0;
+  // A full segment's recompute (checkpoint each state, step) and its reverse sweep are the
+  // same launches for every full segment up to the ping-pong parities: each is captured
+  // once per parity as a HIP graph and replayed; a shorter last segment runs eagerly.
+  auto recompute = [&](int from, int len, hipStream_t st) -> hipError_t {
+    hipError_t er = hipSuccess;
+    for (int jj = 0; jj < len && er == hipSuccess; ++jj) {
+      er = launch_checkpoint_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.s64, st);
+      if (er == hipSuccess && jj + 1 < len) er = launch_plain_step(c, from ^ (jj & 1), st);
+    }
+    return er;
+  };
+  auto reverse = [&](int q0, int len, hipStream_t st) -> hipError_t {
+    hipError_t er = hipSuccess;
+    int qq = q0;
+    for (int jj = len - 1; jj >= 0 && er == hipSuccess; --jj) {
+      a.x = reinterpret_cast<const double *>(ws + L.seg + (size_t)jj * L.s64);
+      a.lam_next = lam_buf[qq];
+      a.lam = lam_buf[qq ^ 1];
+      er = launch_adjoint_step(fp64, c->lat.n_species, c->lat.walls, a, st);
+      qq ^= 1;
+    }
+    return er;
+  };
+  GraphCache g_fwd, g_rev;
+  g_fwd.steps = g_rev.steps = 1;
+  auto graphs_done = [&](int code) {
+    g_fwd.destroy();
+    g_rev.destroy();
+    return done(code);
+  };
   for (int k = L.ncp - 1; k >= 0; --k) {
     const int len = (int)std::min<int64_t>(L.every, T - (int64_t)k * L.every);
-    if ((rc = lb_restore(c, ws + L.ckpt + (size_t)k * L.s64))) return done(rc);
-    for (int j = 0; j < len; ++j) {  // recompute the segment's states
-      if ((rc = lb_checkpoint(c, ws + L.seg + (size_t)j * L.s64))) return done(rc);
-      if (j + 1 < len && (rc = lb_step(c, 1))) return done(rc);
+    if ((rc = lb_restore(c, ws + L.ckpt + (size_t)k * L.s64))) return graphs_done(rc);
+    const int from = c->cur;
+    if (len == L.every) {
+      hipGraphExec_t gf = nullptr, gr = nullptr;
+      e = g_fwd.get(from, [&](int, hipStream_t st) { return recompute(from, len, st); }, &gf);
+      if (e == hipSuccess) e = hipGraphLaunch(gf, c->stream);
+      const int q0 = q;
+      if (e == hipSuccess) e = g_rev.get(q0, [&](int, hipStream_t st) { return reverse(q0, len, st); }, &gr);
+      if (e == hipSuccess) e = hipGraphLaunch(gr, c->stream);
+    } else {
+      e = recompute(from, len, c->stream);
+      if (e == hipSuccess) e = reverse(q, len, c->stream);
     }
-    for (int j = len - 1; j >= 0; --j) {
-      a.x = reinterpret_cast<const double *>(ws + L.seg + (size_t)j * L.s64);
-      a.lam_next = lam_next;
-      a.lam = lam_cur;
-      e = launch_adjoint_step(fp64, c->lat.n_species, c->lat.walls, a, acc, c->stream);
-      if (e != hipSuccess) return done(hip_fail(c, e, "adjoint step"));
-      std::swap(lam_next, lam_cur);
-    }
+    if (e != hipSuccess) return graphs_done(hip_fail(c, e, "adjoint sweep"));
+    c->cur = from ^ ((len - 1) & 1);
+    q ^= (len & 1);
   }
+  e = launch_adjoint_reduce(a.partials, c->lat.lx, c->lat.ly, acc, c->stream);
+  if (e != hipSuccess) return graphs_done(hip_fail(c, e, "adjoint reduction"));
+  g_fwd.destroy();
+  g_rev.destroy();
   // back to the state after T steps
   e = hipMemcpyAsync(c->pop[cur_final], ws + L.fin, popb, hipMemcpyDeviceToDevice, c->stream);
   double h[ADJ_N];

@@ -87,7 +87,7 @@ struct AdjArgs {
   void *lam;             // lambda(t) (R, written)
   void *lampart;         // local part of lambda(t) (R, scratch)
   void *fields;          // [4][2][y][x] (R): rho, psi, jx, jy of f(t)
-  void *fbar;            // [2][2][y][x] (R): force adjoint
+  void *fbar;            // [2][4][y][x] (R): psi_s Fbar_s and r_s Fbar_s (x, y components)
   double *partials;      // [blocks][ADJ_N]
   int lx, ly;
   int cross_psi, pad_;
@@ -104,7 +104,10 @@ struct AdjArgs {
 enum AdjSlot { ADJ_G1A = 0, ADJ_G1B, ADJ_G2A, ADJ_G2B, ADJ_GAB, ADJ_GX, ADJ_GY, ADJ_LW, ADJ_LQ, ADJ_N };
 
 int adj_blocks(int lx, int ly);
-hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, double *acc, hipStream_t st);
+// One reverse step; adds this step's per-block sensitivities to a.partials.
+hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, hipStream_t st);
+// acc[k] += sum over blocks of partials[block][k] (fixed order).
+hipError_t launch_adjoint_reduce(const double *partials, int lx, int ly, double *acc, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 
 // Host-side launchers (lb_kernels.hip).  Return hipSuccess or the launch error.
