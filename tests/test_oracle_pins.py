@@ -21,7 +21,7 @@ FILM = dict(g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0))
 
 
 # ----------------------------------------------------------------------------------------
-# P5: stencil tables and weights (Fig. 1, Appendix B)
+# Stencil tables and weights (Fig. 1, Appendix B)
 # ----------------------------------------------------------------------------------------
 
 def test_shell_counts():
@@ -139,7 +139,7 @@ def oracle_weights():
 
 
 # ----------------------------------------------------------------------------------------
-# P4: equilibrium moments and the velocity shift
+# Equilibrium moments and the velocity shift
 # ----------------------------------------------------------------------------------------
 
 def _random_state(shape, seed=3, base=None):
@@ -190,7 +190,7 @@ def test_collision_relaxes_moments_by_one_over_tau():
 
 
 # ----------------------------------------------------------------------------------------
-# P3, P6: uniform states and closed forms of the stencil
+# Uniform states and closed forms of the stencil
 # ----------------------------------------------------------------------------------------
 
 def test_uniform_state_invariant():
@@ -314,10 +314,10 @@ def test_pair_forces_cancel_newton_third_law():
 
 
 # ----------------------------------------------------------------------------------------
-# P1, P2, P14: conservation laws
+# Conservation laws
 # ----------------------------------------------------------------------------------------
 
-def test_mass_momentum_single_component_cfg1():
+def test_mass_momentum_single_component_noise_64():
     """64x64 periodic, film couplings, 1000 steps from noise (phase separates)."""
     P = Params(lx=64, ly=64, ns=1, **FILM)
     o = Oracle(P, rho_init=lbgen.uniform_noise(64, 64, 1.0, 0.01, seed=1)[None])
@@ -359,7 +359,7 @@ def test_momentum_balance_channel_with_body_force():
 
 
 # ----------------------------------------------------------------------------------------
-# P7, P8, P9: flat interface equilibrium (BULK), exact mechanical balance, surface stress
+# Flat interface: bulk equation of state (BULK), exact mechanical balance, surface stress
 # ----------------------------------------------------------------------------------------
 
 def _tanh_slab(lx, rho_in, rho_out, x0, x1, width=3.0):
@@ -432,7 +432,7 @@ def test_flat_interface_surface_stress_pattern(flat_interface):
 
 
 # ----------------------------------------------------------------------------------------
-# P10: Laplace law for static droplets
+# Laplace law for static droplets
 # ----------------------------------------------------------------------------------------
 
 @pytest.mark.slow
@@ -464,7 +464,7 @@ def test_laplace_law(flat_interface):
 
 
 # ----------------------------------------------------------------------------------------
-# P11: Poiseuille flow between bounce-back walls
+# Poiseuille flow between bounce-back walls
 # ----------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("tau", [1.0, 0.8])
@@ -490,7 +490,7 @@ def test_poiseuille(tau):
 
 
 # ----------------------------------------------------------------------------------------
-# P12, P13: emulsion couplings -- coexistence and two-component mechanical balance
+# Emulsion couplings: coexistence and two-component mechanical balance
 # ----------------------------------------------------------------------------------------
 
 @pytest.mark.slow
@@ -520,7 +520,7 @@ def test_two_component_lamella():
 
 
 # ----------------------------------------------------------------------------------------
-# P16: the oracle's complex-step gradient of the time-averaged loss
+# The oracle's complex-step gradient of the time-averaged loss
 #   L = lw0 <(W_bot + W_top)/2> + lw1 <Q>   (wall stress and flow rate, emulsion section)
 # ----------------------------------------------------------------------------------------
 
