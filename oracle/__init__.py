@@ -66,7 +66,7 @@ class OrcConfig(ctypes.Structure):
         ("w", ctypes.c_double * 5), ("p", ctypes.c_double * 5), ("t", ctypes.c_double * 2),
         ("body", ctypes.c_double * 2), ("rho_wall", ctypes.c_double * 2), ("tau", ctypes.c_double * 2),
         ("psi0", ctypes.c_double), ("rho0", ctypes.c_double),
-        ("cross_psi", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("cross_psi", ctypes.c_int32), ("pad_", ctypes.c_int32), ("u_wall", ctypes.c_double * 2),
     ]
 
 
@@ -102,6 +102,7 @@ class Params:
     p: Sequence[float] = field(default_factory=default_p)
     t: Sequence[float] = field(default_factory=default_t)
     cross_psi: int = 0
+    u_wall: Sequence[float] = (0.0, 0.0)
 
     def to_c(self):
         c = OrcConfig()
@@ -115,6 +116,7 @@ class Params:
         c.t[0], c.t[1] = self.t[0], self.t[1]
         c.psi0, c.rho0 = self.psi0, self.rho0
         c.cross_psi = self.cross_psi
+        c.u_wall[0], c.u_wall[1] = self.u_wall[0], self.u_wall[1]
         return c
 
     def shell_k(self, s=0):

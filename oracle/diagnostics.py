@@ -15,7 +15,7 @@ Readings of the paper used here:
 
 import numpy as np
 
-from . import CX, CY
+from . import CX, CY, WL
 
 CS2 = 1.0 / 3.0
 
@@ -166,3 +166,117 @@ def droplet_radius(rho, rho_in, rho_out):
     """Equimolar radius of a single circular droplet: area = (M - rho_out A) / (rho_in - rho_out)."""
     area = (rho.sum() - rho_out * rho.size) / (rho_in - rho_out)
     return np.sqrt(abs(area) / np.pi)
+
+
+def shear_profile(orc):
+    """Stream-wise averaged velocity and shear stress of the current state of an Oracle
+    (emulsion section: the averaged profiles ubar_x(z) and sigma(z) of the confined flows,
+    from which the local fluidity of eq. (fluidity) / eq. (predict) is taken).
+
+    Returns (ubar [ly], sigma [ly + 1]):
+      ubar(y)  = (1/lx) sum_x u_x(x, y), u the half-force velocity of the oracle's fields;
+      sigma(k) = x-force per unit length exerted, in this step, by everything above the
+                 horizontal line k (between rows k-1 and k) on everything below it: the pair
+                 forces of eq. (FORCE) and of the A-B repulsion between fluid sites on either
+                 side of the line, minus the x-momentum that streaming carries up across the
+                 line (post-collision populations with c_y = +1 below it, minus those with
+                 c_y = -1 above it).  On a channel, sigma(0) and sigma(ly) are the momentum
+                 exchanged with the bottom wall (W_bot, force on the wall) and the top wall
+                 (-W_top, force of the wall on the fluid), moving walls included.  On a
+                 periodic lattice sigma(ly) = sigma(0).
+    Every pair is enumerated explicitly (no regrouping)."""
+    P = orc.params
+    fl = orc.fields(fstar=True)
+    fs, psi, rho, u = fl["fstar"], fl["psi"], fl["rho"], fl["u"]
+    ns, ly, lx = P.ns, P.ly, P.lx
+    walls = bool(P.walls)
+    ubar = u[0].sum(axis=1) / lx
+
+    # x-momentum of the populations leaving each row upward / downward, summed over x
+    kup = np.zeros(ly)
+    kdn = np.zeros(ly)
+    for s in range(ns):
+        for l in range(9):
+            if CY[l] == 1:
+                kup += CX[l] * fs[s, l].sum(axis=1)
+            if CY[l] == -1:
+                kdn += CX[l] * fs[s, l].sum(axis=1)
+
+    cross = P.ns == 2 and P.gab != 0.0
+    rsrc = psi if P.cross_psi else rho
+
+    def pair_force(k):
+        """x-force on the fluid rows below line k from the fluid rows above it."""
+        tot = 0.0
+        for ay in (k - 1, k - 2):
+            if walls and ay < 0:
+                continue
+            ayw = ay % ly
+            for li in range(1, 25):
+                cx, cy = LINKS[li]
+                if cy < 1 or ay + cy < k:
+                    continue
+                by = ay + cy
+                if walls and by > ly - 1:
+                    continue  # partner is a wall ghost: wall force, not fluid stress
+                byw = by % ly
+                q = SHELL_OF[cx * cx + cy * cy]
+                for s in range(ns):
+                    Ks = P.shell_k(s)[q]
+                    a_val = psi[s, ayw]
+                    b_val = np.roll(psi[s, byw], -cx)  # psi(x + cx, by)
+                    tot += -Ks * cx * float((a_val * b_val).sum())
+                    if cross and li <= 8:
+                        t = P.t[q]
+                        a_r = rsrc[s, ayw]
+                        b_r = np.roll(rsrc[1 - s, byw], -cx)
+                        tot += -P.gab * t * cx * float((a_r * b_r).sum())
+        return tot
+
+    sigma = np.zeros(ly + 1)
+    lines = range(1, ly) if walls else range(0, ly)
+    for k in lines:
+        below, above = (k - 1) % ly, k % ly
+        sigma[k] = (pair_force(k) - kup[below] + kdn[above]) / lx
+    if walls:
+        # reflected population off a wall moving with U: f*_out + 6 W_l rho_w (c_l . U)
+        wb = wt = 0.0
+        for s in range(ns):
+            for l in range(9):
+                lo = int(np.nonzero((CX == -CX[l]) & (CY == -CY[l]))[0][0])
+                if CY[l] == -1:
+                    out = fs[s, l, 0]
+                    refl = out + 6.0 * WL[lo] * P.rho_wall[s] * (CX[lo] * P.u_wall[0])
+                    wb += float((CX[l] * out - CX[lo] * refl).sum())
+                if CY[l] == 1:
+                    out = fs[s, l, ly - 1]
+                    refl = out + 6.0 * WL[lo] * P.rho_wall[s] * (CX[lo] * P.u_wall[1])
+                    wt += float((CX[l] * out - CX[lo] * refl).sum())
+        sigma[0] = wb / lx
+        sigma[ly] = -wt / lx
+    else:
+        sigma[ly] = sigma[0]
+    return ubar, sigma
+
+
+def fluidity(ubar, sigma, walls=True, u_wall=(0.0, 0.0)):
+    """Local fluidity at the lines k = 0..ly: the velocity difference across the line over
+    the stress through it, f(k) = (ubar(k) - ubar(k-1)) / sigma(k); at a wall the difference
+    is taken to the wall velocity over half a site (periodic lattices wrap)."""
+    ly = len(ubar)
+    f = np.empty(ly + 1)
+    for k in range(ly + 1):
+        if walls and k == 0:
+            du = 2.0 * (ubar[0] - u_wall[0])
+        elif walls and k == ly:
+            du = 2.0 * (u_wall[1] - ubar[ly - 1])
+        else:
+            kk = k % ly
+            du = ubar[kk] - ubar[(kk - 1) % ly]
+        f[k] = du / sigma[k]
+    return f
+
+
+def cooperative_shape(z, H, zeta):
+    """Right-hand side of eq. (predict): cosh((z - H/2) / zeta) / cosh(H / (2 zeta))."""
+    return np.cosh((np.asarray(z) - H / 2.0) / zeta) / np.cosh(H / (2.0 * zeta))

@@ -27,6 +27,10 @@
 //   * Planar channel (emulsion section: no-slip walls at z=0 and z=H, volume force):
 //     halfway bounce-back with walls at y=-1/2 and y=ly-1/2; wall ghost sites carry the
 //     densities rho_wall (wetting); body force rho_s g per species.
+//   * Planar Couette cell (same section: the walls move with velocities +-U_w along x):
+//     bounce-back off a wall moving with velocity U adds 6 W_l rho_w c_l . U to the reflected
+//     population (the wall's momentum density is read as rho_wall[s] U per species; the
+//     added terms of one site sum to zero, so mass is conserved).
 //
 // Conventions fixed here (the paper is silent): state = pre-collision populations f(x,t);
 // arrays are [species][l][y][x], x fastest; sums run in increasing l.
@@ -54,6 +58,7 @@ typedef struct {
   double psi0, rho0;
   int32_t cross_psi;           // 0: cross term uses rho (default reading), 1: uses psi
   int32_t pad_;
+  double u_wall[2];            // x-velocity of the bottom and the top wall (channel only)
 } orc_config;
 }
 
@@ -98,6 +103,7 @@ struct Sim {
   size_t nsite;
   // Couplings and parameters in the scalar type (complex-step perturbs them).
   T g1[2], g2[2], gab, body[2], tau[2], psi0, rho0, rho_wall[2];
+  double u_wall[2];
   double w[5], p[5], t[2];
   std::vector<T> f, fs;             // pre- and post-collision populations [s][l][y][x]
   std::vector<T> rho, jx, jy, psi;  // [s][y][x]
@@ -112,6 +118,7 @@ struct Sim {
       body[s] = c.body[s];
     }
     gab = c.gab; psi0 = c.psi0; rho0 = c.rho0;
+    u_wall[0] = c.u_wall[0]; u_wall[1] = c.u_wall[1];
     for (int q = 0; q < 5; ++q) { w[q] = c.w[q]; p[q] = c.p[q]; }
     t[0] = c.t[0]; t[1] = c.t[1];
     f.assign((size_t)ns * 9 * nsite, T(0));
@@ -233,6 +240,14 @@ struct Sim {
       }
   }
 
+  // Population that bounces back into direction l (c_ly = +1 off the bottom wall, -1 off
+  // the top wall) at a site whose outgoing population was fout: halfway bounce-back plus
+  // the momentum the moving wall hands over, 6 W_l rho_w,s (c_l . U).
+  T reflected(int s, int l, const T &fout) const {
+    const double U = CY[l] > 0 ? u_wall[0] : u_wall[1];
+    return fout + 6.0 * WL[l] * rho_wall[s] * (double(CX[l]) * U);
+  }
+
   // Stage 4: streaming f_l(x, t+1) = f*_l(x - c_l, t); halfway bounce-back off solid rows.
   void stream() {
 #pragma omp parallel for schedule(static)
@@ -244,14 +259,15 @@ struct Sim {
             if (fluid(x - CX[l], y - CY[l], xi, yi))
               f[at(s, l, y, x)] = fs[at(s, l, yi, xi)];
             else
-              f[at(s, l, y, x)] = fs[at(s, OPP[l], y, x)];
+              f[at(s, l, y, x)] = reflected(s, l, fs[at(s, OPP[l], y, x)]);
           }
   }
 
   // Observables of the step just collided: [mass_0, mass_1, P_x, P_y, W_bot, W_top, Q, 0].
   //   mass, momentum: of the pre-collision state f(t).
   //   W_bot/W_top: x-momentum per unit wall length handed to the bottom/top wall by the
-  //   populations that bounce back in this step (2 c_x f* per reflected population).
+  //   populations that bounce back in this step: c_x f* of the outgoing population minus
+  //   c_x of the reflected one, i.e. 2 c_x f* less what a moving wall adds.
   //   Q: (1/lx) sum_x,y u_x with u = (sum_s j_s + F_s/2) / sum_s rho_s.
   void record(T *out) const {
     T mass[2] = {0, 0}, px = 0, py = 0, wb = 0, wt = 0, q = 0;
@@ -274,8 +290,14 @@ struct Sim {
       for (int s = 0; s < ns; ++s)
         for (int x = 0; x < lx; ++x)
           for (int l = 0; l < 9; ++l) {
-            if (CY[l] == -1) wb += 2.0 * double(CX[l]) * fs[at(s, l, 0, x)];
-            if (CY[l] == +1) wt += 2.0 * double(CX[l]) * fs[at(s, l, ly - 1, x)];
+            if (CY[l] == -1) {
+              const T out = fs[at(s, l, 0, x)];
+              wb += double(CX[l]) * out - double(CX[OPP[l]]) * reflected(s, OPP[l], out);
+            }
+            if (CY[l] == +1) {
+              const T out = fs[at(s, l, ly - 1, x)];
+              wt += double(CX[l]) * out - double(CX[OPP[l]]) * reflected(s, OPP[l], out);
+            }
           }
     }
     out[0] = mass[0]; out[1] = mass[1]; out[2] = px; out[3] = py;

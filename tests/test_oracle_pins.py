@@ -4,7 +4,9 @@ Every test here checks the oracle against something other than itself: the isotr
 constraints as printed in Appendix B, closed forms of the stencil on sinusoids, exact
 invariants (mass, momentum, uniform states), the equilibrium's printed second moment, the
 bulk equation of state (BULK), the exact mechanical balance across a flat interface, the
-surface-stress analysis of Appendix A, the Laplace law and the Poiseuille profile.
+surface-stress analysis of Appendix A, the Laplace law, the Poiseuille and Couette profiles,
+the exact lattice momentum balance of the shear-stress profile, and the cooperative-length
+prediction of the Couette-cell fluidity.
 """
 
 from fractions import Fraction
@@ -487,6 +489,107 @@ def test_poiseuille(tau):
     y = np.arange(ly)
     ref = g / (2 * nu) * (y + 0.5) * (ly - 0.5 - y)
     assert np.abs(ux - ref).max() / ref.max() < 2e-3
+
+
+# ----------------------------------------------------------------------------------------
+# Planar Couette cell: walls sliding with -U_w and +U_w (emulsion section)
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.7])
+def test_couette_linear_profile_and_uniform_stress(tau):
+    """Steady simple shear between walls moving with U_bot and U_top: the velocity is exactly
+    linear, u(y) = U_bot + (U_top - U_bot)(y + 1/2)/ly (walls half-way to the ghost rows), the
+    shear stress through every line, the walls included, is rho nu S with nu = (tau - 1/2)/3
+    and S = (U_top - U_bot)/ly, and the fluidity S / sigma is 1 / (rho nu) everywhere."""
+    lx, ly, ub, ut = 4, 12, -0.01, 0.015
+    P = Params(lx=lx, ly=ly, ns=1, walls=1, rho_wall=(1.0, 0.0), tau=(tau, tau), u_wall=(ub, ut))
+    o = Oracle(P, rho_init=np.ones((1, ly, lx)))
+    o.step(20000)
+    ubar, sigma = dg.shear_profile(o)
+    y = np.arange(ly)
+    S = (ut - ub) / ly
+    assert np.abs(ubar - (ub + S * (y + 0.5))).max() < 1e-12 * abs(ut)
+    nu = (tau - 0.5) / 3
+    np.testing.assert_allclose(sigma, nu * S, rtol=1e-10)
+    rec = o.step(1, record=True)
+    assert rec[0, 4] == pytest.approx(nu * S, rel=1e-10)
+    assert rec[0, 5] == pytest.approx(-nu * S, rel=1e-10)
+    np.testing.assert_allclose(dg.fluidity(ubar, sigma, True, (ub, ut)), 1.0 / nu, rtol=1e-9)
+
+
+def test_walls_moving_together_carry_a_uniform_flow():
+    """Both walls moving with U and a uniform equilibrium at velocity U whose densities are
+    the walls' own: bounce-back off the moving walls returns exactly the equilibrium
+    populations, so the state never changes (two components, all couplings on)."""
+    lx, ly, U = 6, 8, 0.03
+    rw = (0.9, 0.4)
+    P = Params(lx=lx, ly=ly, ns=2, walls=1, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+               rho0=lbgen.EMULSION_RHO0, rho_wall=rw, u_wall=(U, U))
+    cu = CX * U
+    f = np.stack([np.broadcast_to((WL * r * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * U * U))[:, None, None], (9, ly, lx))
+                  for r in rw])
+    o = Oracle(P, f=f)
+    o.step(40)
+    np.testing.assert_allclose(o.get_f(), f, rtol=1e-14, atol=0)
+
+
+def test_moving_walls_conserve_mass_and_balance_momentum():
+    """Sliding walls exchange momentum only: species masses stay exact and
+    P_x(t+1) - P_x(t) = g M - lx (W_bot + W_top) each step, W counting the momentum the
+    moving wall hands to the reflected populations."""
+    lx, ly, g = 40, 24, 1e-5
+    P = Params(lx=lx, ly=ly, ns=2, walls=1, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2,
+               gab=lbgen.EMULSION_GAB, rho0=lbgen.EMULSION_RHO0, body=(g, 0.0), rho_wall=(0.2, 1.2),
+               u_wall=(-0.02, 0.02))
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.6, seed=8, walls=True, rmin=5, rmax=8)
+    o = Oracle(P, rho_init=rho)
+    rec = o.step(300, record=True)
+    M = rec[0, 0] + rec[0, 1]
+    dP = np.diff(rec[:, 2])
+    pred = g * M - lx * (rec[:-1, 4] + rec[:-1, 5])
+    assert np.abs(dP - pred).max() < 1e-13 * M
+    for s in range(2):
+        assert np.abs(rec[:, s] - rec[0, s]).max() / rec[0, s] < 1e-12
+    # the walls drag the fluid: bottom wall (moving -x) feels a +x force on average
+    assert rec[:, 4].mean() > 0 and rec[:, 5].mean() < 0
+
+
+@pytest.mark.parametrize("walls", [True, False])
+def test_shear_profile_is_the_exact_momentum_flux(walls):
+    """The x-momentum of every row changes in one step by exactly the stress difference
+    across its two bounding lines plus the body force on it:
+    P_row(y, t+1) - P_row(y, t) = lx (sigma(y+1) - sigma(y)) + g_x M_row(y, t)
+    (emulsion, moving walls and body force, or periodic)."""
+    lx, ly = 40, 24
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.7, seed=7, walls=walls, rmin=4, rmax=7)
+    P = Params(lx=lx, ly=ly, ns=2, walls=1 if walls else 0, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2,
+               gab=lbgen.EMULSION_GAB, rho0=lbgen.EMULSION_RHO0, body=(2e-5, 0.0),
+               rho_wall=lbgen.EMULSION_POOR if walls else (0.0, 0.0), u_wall=(-0.02, 0.03) if walls else (0.0, 0.0))
+    o = Oracle(P, rho_init=rho)
+    o.step(30)
+    for _ in range(3):
+        f0 = o.fields()
+        _, sigma = dg.shear_profile(o)
+        o.step(1)
+        f1 = o.fields()
+        dP = f1["j"][:, 0].sum(axis=(0, 2)) - f0["j"][:, 0].sum(axis=(0, 2))
+        pred = lx * (sigma[1:] - sigma[:-1]) + P.body[0] * f0["rho"].sum(axis=(0, 2))
+        assert np.abs(dP - pred).max() < 1e-12 * np.abs(dP).max()
+        assert np.abs(dP).max() > 1e-3  # the stresses are not trivially zero
+
+
+def test_cooperative_length_prediction_shape():
+    """Eq. (predict) is the solution of the nonlocal fluidity equation zeta^2 f'' = f - f_b
+    with f = f_w at both walls (the printed eq. (fluidity) lacks the square that makes it
+    dimensionally consistent; the cosh profile of eq. (predict) solves the squared form)."""
+    H, zeta, fb, fw = 100.0, 17.0, 0.2, 1.3
+    z = np.linspace(0, H, 20001)
+    f = fb + (fw - fb) * dg.cooperative_shape(z, H, zeta)
+    assert f[0] == pytest.approx(fw, rel=1e-14) and f[-1] == pytest.approx(fw, rel=1e-14)
+    dz = z[1] - z[0]
+    d2 = (f[2:] - 2 * f[1:-1] + f[:-2]) / dz ** 2
+    np.testing.assert_allclose(zeta ** 2 * d2, f[1:-1] - fb, rtol=1e-5, atol=1e-9)
+    assert f.min() == pytest.approx(fb + (fw - fb) / np.cosh(H / (2 * zeta)), rel=1e-12)
 
 
 # ----------------------------------------------------------------------------------------
