@@ -10,7 +10,8 @@
  * components (emulsion section of the paper) each species s in {A, B} has its own
  * populations and couplings G_ss,1, G_ss,2, and the species repel each other with strength
  * G_AB over the first belt.  Optional planar channel: halfway bounce-back walls at
- * y = -1/2 and y = ly - 1/2 with a uniform body force (the confined Poiseuille flows).
+ * y = -1/2 and y = ly - 1/2 with a uniform body force (the confined Poiseuille flows), and
+ * walls that slide along x (the planar Couette cell, walls moving with +-U_w).
  *
  * Conventions
  *   - Lattice units (dx = dt = 1, c_s^2 = 1/3).  x is the streamwise (periodic) direction,
@@ -93,6 +94,12 @@ typedef struct {
   /* 0: A-B repulsion between densities (default); 1: between pseudopotentials. */
   int32_t cross_uses_psi;
   int32_t reserved_;
+  /* Channel only: x-velocity of the bottom and the top wall (planar Couette cell: -U_w, +U_w).
+     Bounce-back off a wall moving with velocity U hands the reflected population the momentum
+     6 W_l rho_wall[s] (c_l . U): the wall's momentum density is rho_wall[s] U per species, so
+     set rho_wall to the densities of the phase that wets the walls (one component: its density).
+     Must be 0 on periodic lattices. */
+  double wall_velocity[2];
 } lb_couplings;
 
 typedef struct {
@@ -139,7 +146,9 @@ int lb_moments(lb_ctx *ctx, void *rho, void *u, int32_t dtype);
 
 /* Time-averaged x-force per unit wall length on the bottom and top walls (host out[2]),
    averaged over the reduced steps since the last reset; momentum exchange of the bounced
-   populations, 2 c_x f*.  reset != 0 clears the running average after reading.
+   populations, c_x f* out minus c_x of the reflected population (2 c_x f* for walls at rest,
+   less rho_wall[s] U / 3 per site and species for a wall moving with U).
+   reset != 0 clears the running average after reading.
    Channel lattices only (LB_ESTATE otherwise).  Synchronises. */
 int lb_wall_stress(lb_ctx *ctx, double out[2], int32_t reset);
 
@@ -179,9 +188,59 @@ int lb_set_graph(lb_ctx *ctx, int32_t steps);
    population buffer, so the state is unchanged.  Synchronises. */
 int lb_autotune(lb_ctx *ctx, int32_t trial_steps, int32_t *tx, int32_t *sy, double *ms);
 
-/* Replace the couplings (G_ss,1, G_ss,2, G_AB, weights, body force, wall densities) of a
-   running simulation; validated as in lb_init.  Takes effect at the next step.  Host call. */
+/* Replace the couplings (G_ss,1, G_ss,2, G_AB, weights, body force, wall densities and
+   velocities) of a running simulation; validated as in lb_init.  Takes effect at the next
+   step.  Host call. */
 int lb_set_couplings(lb_ctx *ctx, const lb_couplings *cpl);
+
+/*
+ * Stream-wise averaged profiles for the rheology of the confined flows (emulsion section:
+ * the averaged velocity profile and stress of the pressure-driven channel and of the planar
+ * Couette cell, from which the local fluidity f(z) = (du/dz) / sigma and the cooperative
+ * length of eq. (fluidity) / eq. (predict) follow; and the stress correlator of eq.
+ * (correlator)).
+ *
+ * lb_profile writes, for the current state at time t, out[0 .. ly-1] = ubar(y), the x-average
+ * of the velocity u_x of lb_moments in row y, and out[ly .. 2 ly] = sigma(k), k = 0..ly, the
+ * x-averaged shear stress through the horizontal line k between rows k-1 and k: the x-force
+ * per unit length that the material above the line exerts on the material below it in step
+ * t, i.e. the pair forces of eq. (FORCE) (and of the A-B repulsion) between sites on the two
+ * sides, minus the x-momentum the streaming populations carry upward across the line.
+ * sigma(0) = W_bot(t) and sigma(ly) = -W_top(t) on channel lattices (the walls' momentum
+ * exchange of lb_wall_stress); on periodic lattices sigma(ly) = sigma(0).  Exact lattice
+ * momentum balance: the x-momentum of the rows between lines k1 < k2 changes in step t by
+ * lx (sigma(k2) - sigma(k1)) + g_x times their mass.  out: device, 2 ly + 1 doubles.
+ * One read of the state (a step without the store) plus a small second pass; the state
+ * is not changed.  Asynchronous.
+ */
+int lb_profile(lb_ctx *ctx, double *out);
+
+/*
+ * Time statistics of n >= 1 profiles samples (device, [n][2 ly + 1], as written by
+ * lb_profile), written to out (device, 4 ly + 3 doubles):
+ *   out[0 .. ly-1]             <ubar(y)>
+ *   out[ly .. 2ly]             <sigma(k)>, k = 0..ly
+ *   out[2ly+1 .. 3ly+1]        <f(k)>, the time average of the local fluidity
+ *                              f(k) = (ubar(k) - ubar(k-1)) / sigma(k) at line k; at the walls of a
+ *                              channel the velocity difference is taken to the wall, over half a
+ *                              site: f(0) = 2 (ubar(0) - U_bot) / sigma(0), f(ly) = 2 (U_top - ubar(ly-1)) / sigma(ly)
+ *   out[3ly+2 .. 4ly+2]        C_sigma(k, k0) of eq. (correlator): the covariance of sigma(k) and
+ *                              sigma(k0) over the samples divided by the variance of sigma(k0)
+ *                              (NaN if that variance is 0)
+ * with 0 <= k0 <= ly.  Sums run over the samples in order, in FP64.  Asynchronous.
+ */
+int lb_profile_stats(lb_ctx *ctx, const double *samples, int64_t n, int32_t k0, double *out);
+
+/*
+ * Least-squares fit of the cooperative-length prediction, eq. (predict), to a fluidity
+ * profile: f(z) = f_b + (f_w - f_b) cosh((z - H/2) / zeta) / cosh(H / (2 zeta)) over the n >= 3
+ * points (z[i], f[i]) (host arrays), 0 <= z <= H.  For each zeta the model is linear in f_b and
+ * f_w (solved exactly); zeta is searched on a logarithmic grid over [zeta_min, zeta_max]
+ * (0 < zeta_min < zeta_max) and refined by golden section.  out (host): zeta, f_b, f_w and
+ * the rms residual.  Pure host call.
+ */
+int lb_fit_cooperative_length(const double *z, const double *f, int32_t n, double H, double zeta_min,
+                              double zeta_max, double out[4]);
 
 /*
  * Adjoint (reverse-time) gradient of the time-averaged wall stress and flow rate (emulsion

@@ -14,7 +14,7 @@ from ._binding import LB_BF16DEV, LB_F32, LB_F64, LbError
 
 STORAGE = {"f64": LB_F64, "f32": LB_F32, "bf16dev": LB_BF16DEV}
 
-__all__ = ["Sim", "Batch", "LbError", "STORAGE", "default_weights"]
+__all__ = ["Sim", "Batch", "LbError", "STORAGE", "default_weights", "fit_cooperative_length"]
 
 
 def default_weights():
@@ -31,7 +31,7 @@ def _pair(v):
 
 
 def _couplings(g1=(0.0, 0.0), g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0), rho_wall=(0.0, 0.0), w=None, p=None, t=None,
-               cross_psi=False):
+               cross_psi=False, u_wall=(0.0, 0.0)):
     cpl = B.default_couplings()
     cpl.g1[:] = _pair(g1)
     cpl.g2[:] = _pair(g2)
@@ -45,6 +45,7 @@ def _couplings(g1=(0.0, 0.0), g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0), rho_wall=
     cpl.body_force[:] = _pair(body) if len(body) == 2 else body
     cpl.rho_wall[:] = _pair(rho_wall)
     cpl.cross_uses_psi = 1 if cross_psi else 0
+    cpl.wall_velocity[:] = tuple(float(v) for v in u_wall)
     return cpl
 
 
@@ -66,12 +67,14 @@ class Sim:
     tau, pseudopotential psi0 (1 - exp(-rho / rho0)); rho_init is the initial density
     [n_species, ly, lx] (host array), started from rest equilibrium.  rho_ref: reference
     density per species for the FP32/BF16 deviation storage (default: mean of rho_init).
+    u_wall: x-velocities of the bottom and top walls (channel only; the planar Couette cell
+    of the emulsion section moves them with -U_w and +U_w).
     """
 
     def __init__(self, lx, ly, rho_init, n_species=1, walls=False, storage="f64", g1=(0.0, 0.0),
                  g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0), rho_wall=(0.0, 0.0), tau=(1.0, 1.0), psi0=1.0,
                  rho0=1.0, rho_ref=None, w=None, p=None, t=None, cross_psi=False, device="cuda",
-                 tile=None):
+                 tile=None, u_wall=(0.0, 0.0)):
         import torch
         self._lib = B.load()
         self.torch = torch
@@ -79,9 +82,10 @@ class Sim:
         self.lx, self.ly, self.ns = int(lx), int(ly), int(n_species)
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         self.lat = B.LbLattice(self.lx, self.ly, self.ns, 1 if walls else 0, self.storage)
-        cpl = _couplings(g1, g2, gab, body, rho_wall, w, p, t, cross_psi)
+        cpl = _couplings(g1, g2, gab, body, rho_wall, w, p, t, cross_psi, u_wall)
         self.cpl = cpl
-        self._ckw = dict(g1=g1, g2=g2, gab=gab, body=body, rho_wall=rho_wall, w=w, p=p, t=t, cross_psi=cross_psi)
+        self._ckw = dict(g1=g1, g2=g2, gab=gab, body=body, rho_wall=rho_wall, w=w, p=p, t=t, cross_psi=cross_psi,
+                         u_wall=u_wall)
         self.tau = (ctypes.c_double * 2)(*_pair(tau))
         rho = _density(rho_init, self.ns, self.ly, self.lx)
         self.psi = _psi_params(psi0, rho0, rho_ref, rho)
@@ -138,8 +142,8 @@ class Sim:
         return tx.value, sy.value
 
     def set_couplings(self, **kw):
-        """Replace couplings (any of g1, g2, gab, body, rho_wall, w, p, t, cross_psi); the
-        others keep their current values."""
+        """Replace couplings (any of g1, g2, gab, body, rho_wall, w, p, t, cross_psi, u_wall);
+        the others keep their current values."""
         self._ckw.update(kw)
         cpl = _couplings(**self._ckw)
         self._chk(self._lib.lb_set_couplings(self._h, ctypes.byref(cpl)))
@@ -197,6 +201,44 @@ class Sim:
         self._chk(self._lib.lb_wall_stress(self._h, out, 1 if reset else 0))
         return out[0], out[1]
 
+    def profile(self, out=None):
+        """Stream-wise averaged profiles of the current state (device FP64 tensor of 2 ly + 1):
+        [0:ly] the x-averaged velocity ubar(y), [ly:] the shear stress sigma(k) through the
+        lines k = 0..ly between rows k-1 and k (sigma(0) = W_bot, sigma(ly) = -W_top on a
+        channel)."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty(2 * self.ly + 1, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != 2 * self.ly + 1:
+            raise ValueError("out must be a contiguous float64 tensor of 2 ly + 1 elements")
+        self._chk(self._lib.lb_profile(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def sample_profiles(self, n, every):
+        """n profiles, one after every `every` steps (advances n * every steps): [n, 2 ly + 1]."""
+        torch = self.torch
+        out = torch.empty((int(n), 2 * self.ly + 1), dtype=torch.float64, device=self.device)
+        for i in range(int(n)):
+            self.step(every)
+            self.profile(out[i])
+        return out
+
+    def profile_stats(self, samples, k0=None):
+        """Time statistics of profile samples [n, 2 ly + 1]: dict of <ubar> [ly], <sigma> [ly+1],
+        the time-averaged local fluidity <f> [ly+1] and the stress correlator C_sigma(k, k0)
+        [ly+1] (k0 default: the centre line)."""
+        torch = self.torch
+        ly = self.ly
+        samples = samples.to(dtype=torch.float64, device=self.device).contiguous()
+        if samples.dim() != 2 or samples.shape[1] != 2 * ly + 1:
+            raise ValueError("samples must have shape (n, 2 ly + 1)")
+        k0 = ly // 2 if k0 is None else int(k0)
+        out = torch.empty(4 * ly + 3, dtype=torch.float64, device=self.device)
+        self._chk(self._lib.lb_profile_stats(self._h, ctypes.c_void_p(samples.data_ptr()), samples.shape[0], k0,
+                                             ctypes.c_void_p(out.data_ptr())))
+        return dict(u=out[:ly], sigma=out[ly:2 * ly + 1], fluidity=out[2 * ly + 1:3 * ly + 2],
+                    corr=out[3 * ly + 2:])
+
     def checkpoint(self):
         """Canonical FP64 pre-collision populations f[ns, 9, ly, lx] (device tensor)."""
         f = self.torch.empty((self.ns, 9, self.ly, self.lx), dtype=self.torch.float64, device=self.device)
@@ -211,11 +253,30 @@ class Sim:
         self._chk(self._lib.lb_restore(self._h, ctypes.c_void_p(f.data_ptr())))
 
 
+def fit_cooperative_length(z, f, H, zeta_range=None):
+    """Least-squares fit of eq. (predict) to a fluidity profile f(z), 0 <= z <= H:
+    f = f_b + (f_w - f_b) cosh((z - H/2)/zeta) / cosh(H/(2 zeta)).  Returns
+    dict(zeta, f_b, f_w, rms).  zeta_range: search interval (default (H/1000, 100 H))."""
+    lib = B.load()
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if z.shape != f.shape or z.ndim != 1:
+        raise ValueError("z and f must be 1-D arrays of the same length")
+    lo, hi = zeta_range if zeta_range is not None else (H / 1000.0, 100.0 * H)
+    out = (ctypes.c_double * 4)()
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.lb_fit_cooperative_length(z.ctypes.data_as(dp), f.ctypes.data_as(dp), len(z), float(H), float(lo),
+                                       float(hi), out)
+    if rc != B.LB_OK:
+        raise LbError(rc, "invalid fit input")
+    return dict(zeta=out[0], f_b=out[1], f_w=out[2], rms=out[3])
+
+
 class Batch:
     """Many independent lattices stepped together by one persistent launch per time step.
 
     instances: list of dicts with the keyword arguments of Sim (lx, ly, rho_init, and any of
-    g1, g2, gab, body, rho_wall, tau, psi0, rho0, rho_ref, w, p, t, cross_psi); storage,
+    g1, g2, gab, body, rho_wall, tau, psi0, rho0, rho_ref, w, p, t, cross_psi, u_wall); storage,
     n_species and walls are common to all instances.
     """
 
@@ -240,7 +301,8 @@ class Batch:
             self.lats[i] = B.LbLattice(lx, ly, self.ns, 1 if walls else 0, self.storage)
             self.cpls[i] = _couplings(inst.get("g1", (0.0, 0.0)), inst.get("g2", (0.0, 0.0)), inst.get("gab", 0.0),
                                       inst.get("body", (0.0, 0.0)), inst.get("rho_wall", (0.0, 0.0)), inst.get("w"),
-                                      inst.get("p"), inst.get("t"), inst.get("cross_psi", False))
+                                      inst.get("p"), inst.get("t"), inst.get("cross_psi", False),
+                                      inst.get("u_wall", (0.0, 0.0)))
             tau = _pair(inst.get("tau", (1.0, 1.0)))
             self.taus[2 * i], self.taus[2 * i + 1] = tau
             rho = _density(inst["rho_init"], self.ns, ly, lx)

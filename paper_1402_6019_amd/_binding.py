@@ -28,7 +28,8 @@ class LbCouplings(ctypes.Structure):
     _fields_ = [("g1", ctypes.c_double * 2), ("g2", ctypes.c_double * 2), ("g_ab", ctypes.c_double),
                 ("w", ctypes.c_double * 5), ("p", ctypes.c_double * 5), ("t", ctypes.c_double * 2),
                 ("body_force", ctypes.c_double * 2), ("rho_wall", ctypes.c_double * 2),
-                ("cross_uses_psi", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("cross_uses_psi", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("wall_velocity", ctypes.c_double * 2)]
 
 
 class LbPsiParams(ctypes.Structure):
@@ -66,6 +67,10 @@ SIGNATURES = {
     "lb_adjoint_workspace_bytes": (_sz, [_vp, _i64, _i32, _i32]),
     "lb_adjoint": (ctypes.c_int, [_vp, _i64, _i32, _i32, _dp, _dp, _dp, _vp, _sz]),
     "lb_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]),
+    "lb_profile": (ctypes.c_int, [_vp, _vp]),
+    "lb_profile_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp]),
+    "lb_fit_cooperative_length": (ctypes.c_int, [_dp, _dp, _i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                 _dp]),
     "lb_last_error": (ctypes.c_char_p, [_vp]),
     "lb_destroy": (None, [_vp]),
     # batches

@@ -208,10 +208,12 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
       const R wl = R(WD2Q9[l]);
       const R feq = wl * rho[s] * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
       if (WALLS && ((y == 0 && CYS[l] == -1) || (y == v.ly - 1 && CYS[l] == 1))) {
-        // wall stress: d/dy_l of cW (1/2)(1/lx) 2 c_lx y_l
+        // wall stress: d/dy_l of cW (1/2)(1/lx) (2 c_lx y_l - 6 W_l rho_w c_lx^2 U); the
+        // moving wall's share is constant
         al += cW * R(CXS[l]) / R(v.lx);
         const R yl = (R(1) - om) * R(a.x[((size_t)s * Q + l) * v.n + i]) + om * feq;  // post-collision
-        if (live) loss_w += double(cW * R(CXS[l]) * yl) / v.lx;
+        const R mw = R(3) * wl * R(a.rho_w[s]) * R(CXS[l] * CXS[l]) * R(y == 0 ? a.u_wall[0] : a.u_wall[1]);
+        if (live) loss_w += double(cW * (R(CXS[l]) * yl - mw)) / v.lx;
       }
       lp[s][l] = (R(1) - om) * al;
       rb += om * al * feq / rho[s];

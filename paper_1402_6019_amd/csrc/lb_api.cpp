@@ -50,6 +50,8 @@ struct lb_ctx {
   bool check_pending = false;
   bool unstable = false;
   GraphCache graph;  // graph.steps > 0: plain steps are replayed from captured graphs
+  double *d_prof = nullptr;      // profile pass: [ncb][ly][PROF_N]
+  size_t prof_cap = 0;           // doubles
   std::string err;
 };
 
@@ -431,6 +433,53 @@ int lb_set_couplings(lb_ctx *c, const lb_couplings *cpl) {
   return LB_OK;
 }
 
+int lb_profile(lb_ctx *c, double *out) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!out) return fail(c, LB_EINVAL, "null output");
+  int nseg = 0;
+  const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
+  const int ncb = ((c->lat.lx + c->tx - 1) / c->tx) * (c->tx / 64);
+  const size_t need = (size_t)ncb * c->lat.ly * PROF_N;
+  if (need > c->prof_cap) {
+    if (c->d_prof) (void)hipFree(c->d_prof);
+    c->d_prof = nullptr;
+    c->prof_cap = 0;
+    hipError_t e = hipMalloc(&c->d_prof, need * sizeof(double));
+    if (e != hipSuccess) return fail(c, LB_ENOMEM, std::string("profile buffer: ") + hipGetErrorString(e));
+    c->prof_cap = need;
+  }
+  StepArgs a;
+  fill_step_args(c, a);
+  a.nseg = nseg;
+  a.src = c->pop[c->cur];
+  a.dst = c->pop[c->cur ^ 1];  // not written
+  a.prof = c->d_prof;
+  a.ncb = ncb;
+  hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_PROFILE, c->tx, nb, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "profile kernel launch");
+  // the walls' share of their momentum exchange: sum_s rho_w,s U / 3 per unit length
+  double wb0 = 0.0, wt0 = 0.0;
+  if (c->lat.walls)
+    for (int s = 0; s < c->lat.n_species; ++s) {
+      wb0 += 2.0 * a.wall_mom[0][s];
+      wt0 += 2.0 * a.wall_mom[1][s];
+    }
+  e = launch_profile_finish(c->d_prof, ncb, c->lat.lx, c->lat.ly, c->lat.walls, wb0, wt0, out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "profile finish launch");
+  return LB_OK;
+}
+
+int lb_profile_stats(lb_ctx *c, const double *samples, int64_t n, int32_t k0, double *out) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!samples || !out) return fail(c, LB_EINVAL, "null argument");
+  if (n < 1) return fail(c, LB_EINVAL, "n must be >= 1");
+  if (k0 < 0 || k0 > c->lat.ly) return fail(c, LB_EINVAL, "k0 must be in [0, ly]");
+  const double ub = c->lat.walls ? c->cpl.wall_velocity[0] : 0.0, ut = c->lat.walls ? c->cpl.wall_velocity[1] : 0.0;
+  hipError_t e = launch_profile_stats(samples, (long long)n, c->lat.ly, c->lat.walls, k0, ub, ut, out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "profile statistics launch");
+  return LB_OK;
+}
+
 int lb_set_graph(lb_ctx *c, int32_t steps) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (steps < 0 || (steps & 1)) return fail(c, LB_EINVAL, "graph steps must be even and >= 0");
@@ -558,6 +607,8 @@ AdjArgs adjoint_args(const lb_ctx *c, double lw0, double lw1, int64_t T) {
   a.irho0 = 1.0 / c->psi.rho0;
   a.cW = lw0 / (double)T;
   a.cQ = lw1 / (double)T;
+  a.u_wall[0] = c->lat.walls ? c->cpl.wall_velocity[0] : 0.0;
+  a.u_wall[1] = c->lat.walls ? c->cpl.wall_velocity[1] : 0.0;
   return a;
 }
 
@@ -687,6 +738,7 @@ void lb_destroy(lb_ctx *c) {
   if (c->check_pending && c->ev) (void)hipEventSynchronize(c->ev);
   (void)hipStreamSynchronize(c->stream);
   if (c->d_partials) (void)hipFree(c->d_partials);
+  if (c->d_prof) (void)hipFree(c->d_prof);
   if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->d_acc) (void)hipFree(c->d_acc);
   if (c->h_acc) (void)hipHostFree(c->h_acc);

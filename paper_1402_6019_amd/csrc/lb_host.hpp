@@ -55,6 +55,14 @@ inline int validate(const lb_lattice *lat, const lb_couplings *cpl, const double
     return LB_EINVAL;
   }
   if (cpl->cross_uses_psi != 0 && cpl->cross_uses_psi != 1) { msg = "cross_uses_psi must be 0 or 1"; return LB_EINVAL; }
+  if (!std::isfinite(cpl->wall_velocity[0]) || !std::isfinite(cpl->wall_velocity[1])) {
+    msg = "non-finite wall velocity";
+    return LB_EINVAL;
+  }
+  if (!lat->walls && (cpl->wall_velocity[0] != 0.0 || cpl->wall_velocity[1] != 0.0)) {
+    msg = "wall_velocity needs a channel lattice (walls = 1)";
+    return LB_EINVAL;
+  }
   return LB_OK;
 }
 
@@ -97,6 +105,10 @@ inline StepArgs make_step_args(const lb_lattice &lat, const lb_couplings &cpl, c
   a.body[1] = cpl.body_force[1];
   a.psi0 = psi.psi0;
   a.irho0 = 1.0 / psi.rho0;
+  // moving walls: a reflected population gains 6 W_l rho_w,s (c_l . U) = +-rho_w,s U / 6
+  for (int w = 0; w < 2; ++w)
+    for (int s = 0; s < 2; ++s) a.wall_mom[w][s] = lat.walls ? cpl.rho_wall[s] * cpl.wall_velocity[w] / 6.0 : 0.0;
+  a.moving = lat.walls && (cpl.wall_velocity[0] != 0.0 || cpl.wall_velocity[1] != 0.0);
   return a;
 }
 

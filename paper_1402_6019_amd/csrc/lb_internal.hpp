@@ -14,8 +14,17 @@ enum StepWhat {
   WHAT_STEP = 0,         // stream + force + collide, store f*
   WHAT_STEP_REDUCE = 1,  // same, plus FP64 per-workgroup partial sums
   WHAT_MOMENTS = 2,      // write rho_s and the half-force velocity, store nothing
-  WHAT_OBSERVE = 3       // partial sums of the current state, store nothing
+  WHAT_OBSERVE = 3,      // partial sums of the current state, store nothing
+  WHAT_PROFILE = 4       // per-row sums of the current state (velocity, stress parts), store nothing
 };
+
+// Per-row sums written by a WHAT_PROFILE launch, per 64-column block of a row:
+//   PROF_U   sum of the half-force velocity u_x
+//   PROF_KUP sum_s (f*_5 - f*_6): x-momentum the populations with c_y = +1 carry up
+//   PROF_KDN sum_s (f*_8 - f*_7): x-momentum the populations with c_y = -1 carry down
+//   PROF_I1  x-force on the row's sites from partners at c_y >= 1 (pairs crossing line y + 1/2)
+//   PROF_I2  the part of PROF_I1 from partners at c_y = 2 (pairs also crossing line y + 3/2)
+enum ProfSlot { PROF_U = 0, PROF_KUP, PROF_KDN, PROF_I1, PROF_I2, PROF_N };
 
 // Partial-sum slots written per workgroup (and totals after the second pass).
 enum RedSlot {
@@ -42,6 +51,10 @@ struct StepArgs {
   double rho_w[2], psi_w[2];  // wall ghost rows (channel)
   double rho_ref[2];          // FP32 / BF16 deviation reference
   long long offset;           // batch: byte offset of this instance in each population buffer
+  double wall_mom[2][2];      // [bottom, top][species]: rho_w,s U / 6, added on reflection
+  int moving;                 // some wall moves (wall_mom != 0)
+  int ncb;                    // profile: 64-column blocks per row in prof
+  double *prof;               // profile: [ncb][ly][PROF_N]
 };
 
 // Batched launches: one tile of one instance.
@@ -98,6 +111,7 @@ struct AdjArgs {
   double psi0, irho0;
   double rho_w[2], psi_w[2];
   double cW, cQ;         // per-step loss weights
+  double u_wall[2];      // x-velocity of the bottom and top wall
 };
 
 // Per-block partial sums of the adjoint: parameter sensitivities and the loss.
@@ -120,6 +134,13 @@ hipError_t launch_checkpoint(int mode, int walls, const LayoutArgs &a, hipStream
 hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t st);
 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+
+// Profile second pass: out[0..ly) = ubar, out[ly..2ly] = sigma (see lb_profile).  wb0, wt0:
+// sum_s rho_w,s U / 3 of the bottom and top wall.
+hipError_t launch_profile_finish(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
+                                 double *out, hipStream_t st);
+hipError_t launch_profile_stats(const double *samples, long long n, int ly, int walls, int k0, double u_bot,
+                                double u_top, double *out, hipStream_t st);
 
 hipError_t launch_batch_step(int mode, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
                              hipStream_t st);

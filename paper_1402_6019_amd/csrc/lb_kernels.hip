@@ -319,6 +319,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   using V = Vec<R, NS>;
   constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_REDUCE);
   constexpr bool REDUCE = (WHAT == WHAT_STEP_REDUCE || WHAT == WHAT_OBSERVE);
+  constexpr bool PROFILE = (WHAT == WHAT_PROFILE);
 
   const int TX = blockDim.x;
   const int W4 = TX + 4;
@@ -686,8 +687,75 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       fs[0] = drho[s] - ((((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8]))));
 
       if (REDUCE && WALLS && col_ok) {
-        if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7]));
-        if (y == ly - 1) wt += 2.0 * (double(fs[5]) - double(fs[6]));
+        // momentum handed to the wall: c_x f* out minus c_x of the reflected population,
+        // which a moving wall raises by 6 W_l rho_w (c_l . U) = +-rho_w U / 6
+        if (y == 0) wb += 2.0 * (double(fs[8]) - double(fs[7])) - 2.0 * a.wall_mom[0][s];
+        if (y == ly - 1) wt += 2.0 * (double(fs[5]) - double(fs[6])) - 2.0 * a.wall_mom[1][s];
+      }
+    }
+    if (PROFILE) {
+      // x-momentum crossing the lines above (c_y = +1) and below (c_y = -1) the row when
+      // these populations stream, before any wall term
+      double kup = 0.0, kdn = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        kup += double(fsa[s][5] - fsa[s][6]);
+        kdn += double(fsa[s][8] - fsa[s][7]);
+      }
+      // pair forces on this site from partners above it, x components: eq. (FORCE) over the
+      // links with c_y = 1 (|c|^2 = 2, 5) and c_y = 2 (|c|^2 = 5, 8), and the A-B term over
+      // c = (+-1, 1); each +-c_x pair as one difference, as in the force itself
+      double i1 = 0.0, i2 = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const R up1 = fmadd(K2[s], ne.v[s] - nw.v[s], K5[s] * (R(2) * (qa.v[s] - qB.v[s])));
+        const R up2 = fmadd(K5[s], qc.v[s] - qD.v[s], K8[s] * (d8a.v[s] - d8B.v[s]));
+        i1 += double(-pc.v[s] * (up1 + up2));
+        i2 += double(-pc.v[s] * up2);
+      }
+      if (NS == 2) {
+        const V *base = a.cross_psi ? psi_ring : rho_ring;
+        int sl0 = lead_slot + 3, sl1 = lead_slot + 3 + dir;
+        sl0 = sl0 >= 6 ? sl0 - 6 : sl0;
+        sl1 = sl1 >= 6 ? sl1 - 6 : (sl1 < 0 ? sl1 + 6 : sl1);
+        const V c0 = base[sl0 * W4 + tid + 2];
+        const V xne = base[sl1 * W4 + tid + 3], xnw = base[sl1 * W4 + tid + 1];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) i1 += double(-c0.v[s] * (T2 * (xne.v[1 - s] - xnw.v[1 - s])));
+      }
+      R sr = rho[0], mx = jx[0] + R(0.5) * Fx[0];
+#pragma unroll
+      for (int s = 1; s < NS; ++s) {
+        sr += rho[s];
+        mx += jx[s] + R(0.5) * Fx[s];
+      }
+      double pv[PROF_N] = {double(mx / sr), kup, kdn, i1, i2};
+      const int lane = tid & 63, wv = tid >> 6;
+      double *row = a.prof + ((size_t)(strip * (TX >> 6) + wv) * ly + y) * PROF_N;
+#pragma unroll
+      for (int k = 0; k < PROF_N; ++k) {
+        const double v = wave_sum(col_ok ? pv[k] : 0.0);
+        if (lane == 0) row[k] = v;
+      }
+    }
+    if (STORE && WALLS && a.moving) {
+      // reflected populations of a moving wall: the stored outgoing population is only ever
+      // pulled back into its opposite at the same site, so the wall's momentum goes in here:
+      // f_5 = f*_7 + rho_w U_bot / 6, f_6 = f*_8 - rho_w U_bot / 6 off the bottom wall,
+      // f_8 = f*_6 + rho_w U_top / 6, f_7 = f*_5 - rho_w U_top / 6 off the top wall
+      if (y == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          fsa[s][7] += R(a.wall_mom[0][s]);
+          fsa[s][8] -= R(a.wall_mom[0][s]);
+        }
+      }
+      if (y == ly - 1) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          fsa[s][6] += R(a.wall_mom[1][s]);
+          fsa[s][5] -= R(a.wall_mom[1][s]);
+        }
       }
     }
     if (STORE) {
@@ -959,6 +1027,9 @@ static hipError_t launch_step_t(int what, int tx, int nb, const StepArgs &a, hip
     case WHAT_OBSERVE:
       hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_OBSERVE>), dim3(nb), dim3(tx), lds, st, a);
       break;
+    case WHAT_PROFILE:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_PROFILE>), dim3(nb), dim3(tx), lds, st, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1050,6 +1121,91 @@ hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nb, co
 __global__ void fill_kernel(double *p, double v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Profile second pass, one thread per row y (ubar) and per line k (sigma): sums the 64-column
+// blocks of each row in fixed order.  Line k lies between rows k-1 and k; its stress is
+//   sigma(k) = (I1(k-1) + I2(k-2) - Kup(k-1) + Kdn(k)) / lx
+// (pair forces across the line on the rows below it, minus the x-momentum streaming up
+// across it), with rows wrapping on periodic lattices.  On channels, sigma(0) and sigma(ly)
+// are the walls' momentum exchange: 2 Kdn(0) / lx - wb0 and -(2 Kup(ly-1) / lx - wt0).
+__global__ void profile_finish_kernel(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
+                                      double *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > ly) return;
+  auto row = [&](int y, int slot) {
+    double v = 0.0;
+    for (int b = 0; b < ncb; ++b) v += prof[((size_t)b * ly + y) * PROF_N + slot];
+    return v;
+  };
+  const double ilx = 1.0 / lx;
+  if (k < ly) out[k] = row(k, PROF_U) * ilx;
+  double sig;
+  if (walls && k == 0) {
+    sig = 2.0 * row(0, PROF_KDN) * ilx - wb0;
+  } else if (walls && k == ly) {
+    sig = -(2.0 * row(ly - 1, PROF_KUP) * ilx - wt0);
+  } else {
+    const int kk = k == ly ? 0 : k;  // periodic: line ly is line 0
+    const int ym1 = kk - 1 < 0 ? kk - 1 + ly : kk - 1;
+    const int ym2 = kk - 2 < 0 ? kk - 2 + ly : kk - 2;
+    double i = row(ym1, PROF_I1);
+    if (!walls || kk >= 2) i += row(ym2, PROF_I2);  // on channels a partner two rows down is a wall
+    sig = (i - row(ym1, PROF_KUP) + row(kk, PROF_KDN)) * ilx;
+  }
+  out[ly + k] = sig;
+}
+
+// Time statistics of n profile samples [n][2 ly + 1], one thread per row / line; the
+// covariances are taken about the means (two passes over the samples).
+__global__ void profile_stats_kernel(const double *smp, long long n, int ly, int walls, int k0, double u_bot,
+                                     double u_top, double *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > ly) return;
+  const size_t len = 2 * (size_t)ly + 1;
+  const double in = 1.0 / (double)n;
+  double su = 0.0, ss = 0.0, sf = 0.0, s0 = 0.0;
+  for (long long t = 0; t < n; ++t) {
+    const double *p = smp + (size_t)t * len;
+    const double sig = p[ly + k];
+    if (k < ly) su += p[k];
+    ss += sig;
+    s0 += p[ly + k0];
+    double du;
+    if (walls && k == 0) du = 2.0 * (p[0] - u_bot);
+    else if (walls && k == ly) du = 2.0 * (u_top - p[ly - 1]);
+    else {
+      const int kk = k == ly ? 0 : k;
+      du = p[kk] - p[kk == 0 ? ly - 1 : kk - 1];
+    }
+    sf += du / sig;
+  }
+  const double mk = ss * in, m0 = s0 * in;
+  double c00 = 0.0, ck0 = 0.0;
+  for (long long t = 0; t < n; ++t) {
+    const double *p = smp + (size_t)t * len;
+    const double d0 = p[ly + k0] - m0;
+    c00 += d0 * d0;
+    ck0 += (p[ly + k] - mk) * d0;
+  }
+  if (k < ly) out[k] = su * in;
+  out[ly + k] = mk;
+  out[2 * ly + 1 + k] = sf * in;
+  out[3 * ly + 2 + k] = c00 > 0.0 ? ck0 / c00 : NAN;
+}
+
+hipError_t launch_profile_finish(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
+                                 double *out, hipStream_t st) {
+  hipLaunchKernelGGL(profile_finish_kernel, dim3((ly + 1 + 255) / 256), dim3(256), 0, st, prof, ncb, lx, ly, walls, wb0,
+                     wt0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_profile_stats(const double *samples, long long n, int ly, int walls, int k0, double u_bot,
+                                double u_top, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(profile_stats_kernel, dim3((ly + 1 + 255) / 256), dim3(256), 0, st, samples, n, ly, walls, k0,
+                     u_bot, u_top, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st) {

@@ -27,7 +27,8 @@ def emulsion_case(lx, ly, walls=False, fraction=0.8, seed=2, storage="f64", g=1e
 def oracle_params(c):
     from oracle import Params
     return Params(lx=c["lx"], ly=c["ly"], ns=c["ns"], walls=c["walls"], g1=c["g1"], g2=c["g2"], gab=c["gab"],
-                  body=c["body"], rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"])
+                  body=c["body"], rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"],
+                  u_wall=c.get("u_wall", (0.0, 0.0)))
 
 
 def make_oracle(c):
@@ -40,7 +41,7 @@ def make_sim(c, tile=None, storage=None):
     return Sim(c["lx"], c["ly"], c["rho"], n_species=c["ns"], walls=bool(c["walls"]),
                storage=storage or c["storage"], g1=c["g1"], g2=c["g2"], gab=c["gab"], body=c["body"],
                rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"], rho_ref=c["rho_ref"],
-               tile=tile)
+               tile=tile, u_wall=c.get("u_wall", (0.0, 0.0)))
 
 
 def rel_err(a, b):

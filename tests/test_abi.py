@@ -57,9 +57,10 @@ def test_pop_bytes(B, storage, es):
     assert B.pop_bytes(B.LbLattice(10, 10, 3, 0, storage)) == 0
 
 
-def _init(B, lat, tau=(1.0, 1.0), rho=None, nbytes=None, psi=(1.0, 1.0)):
+def _init(B, lat, tau=(1.0, 1.0), rho=None, nbytes=None, psi=(1.0, 1.0), u_wall=(0.0, 0.0)):
     lib = B.load()
     cpl = B.default_couplings()
+    cpl.wall_velocity[:] = u_wall
     t = (ctypes.c_double * 2)(*tau)
     pp = B.LbPsiParams(psi[0], psi[1], (ctypes.c_double * 2)(0.0, 0.0))
     if rho is None:
@@ -88,6 +89,10 @@ def test_init_rejects_invalid_arguments_on_host(B):
     assert _init(B, ok, rho=bad)[0] == B.LB_EINVAL
     assert _init(B, ok, psi=(1.0, 0.0))[0] == B.LB_EINVAL
     assert _init(B, ok, nbytes=100)[0] == B.LB_ENOMEM
+    # sliding walls need walls
+    rc, msg = _init(B, ok, u_wall=(0.0, 0.01))
+    assert rc == B.LB_EINVAL and "wall_velocity" in msg
+    assert _init(B, B.LbLattice(16, 16, 1, 1, 0), u_wall=(np.inf, 0.0))[0] == B.LB_EINVAL
 
 
 def test_product_package_does_not_reach_the_oracle():
@@ -146,3 +151,35 @@ def test_null_contexts_fail_cleanly(B):
     assert lib.lb_adjoint_workspace_bytes(None, 10, 0, 0) == 0
     assert lib.lb_time(None) == -1
     assert lib.lb_batch_time(None) == -1
+
+
+def test_cooperative_length_fit_recovers_the_prediction(B):
+    """The host fit of eq. (predict): exact profiles give back (zeta, f_b, f_w); on noisy
+    data it agrees with scipy's general least squares started from the truth."""
+    from scipy.optimize import curve_fit
+    from paper_1402_6019_amd import fit_cooperative_length
+    H = 120.0
+    z = np.arange(1.0, H)
+
+    def model(z, zeta, fb, fw):
+        return fb + (fw - fb) * np.cosh((z - H / 2) / zeta) / np.cosh(H / (2 * zeta))
+
+    for zeta, fb, fw in ((18.0, 0.05, 0.9), (68.0, 0.3, 1.1), (4.0, 1e-3, 0.2)):
+        r = fit_cooperative_length(z, model(z, zeta, fb, fw), H)
+        assert r["zeta"] == pytest.approx(zeta, rel=1e-7)
+        assert r["f_b"] == pytest.approx(fb, rel=1e-6, abs=1e-9)
+        assert r["f_w"] == pytest.approx(fw, rel=1e-6)
+        assert r["rms"] < 1e-9
+    rng = np.random.default_rng(3)
+    f = model(z, 25.0, 0.1, 0.8) + 0.01 * rng.standard_normal(z.size)
+    r = fit_cooperative_length(z, f, H)
+    (zs, fbs, fws), _ = curve_fit(model, z, f, p0=(25.0, 0.1, 0.8))
+    assert r["zeta"] == pytest.approx(zs, rel=1e-5)
+    assert r["f_b"] == pytest.approx(fbs, rel=1e-5)
+    assert r["f_w"] == pytest.approx(fws, rel=1e-5)
+    lib = B.load()
+    dp = ctypes.POINTER(ctypes.c_double)
+    out = (ctypes.c_double * 4)()
+    zz = np.array([0.0, 1.0, 200.0])  # outside [0, H]
+    assert lib.lb_fit_cooperative_length(zz.ctypes.data_as(dp), zz.ctypes.data_as(dp), 3, H, 1.0, 10.0, out) == B.LB_EINVAL
+    assert lib.lb_fit_cooperative_length(z.ctypes.data_as(dp), f.ctypes.data_as(dp), 2, H, 1.0, 10.0, out) == B.LB_EINVAL
