@@ -134,6 +134,62 @@ def batched_sweep(steps, n=64):
             "footprint_mb": 144 * sites / 1e6}
 
 
+def couette_cell(steps, sample_every=100):
+    """Planar Couette cell of the emulsion section at its 1040 x 1040 domain: confined
+    emulsion (volume fraction 0.8, seed 6), walls wetted by B sliding with -U_w and +U_w
+    (U_w = 0.01), FP32.  Times the plain step, the profile pass (lb_profile: a step's read of
+    the state without the store, plus a small second pass) and a run that takes a profile
+    every `sample_every` steps followed by the statistics pass.  The launch shape is the
+    autotuner's (1040 columns do not fill whole 256-wide strips)."""
+    import torch
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    lx = ly = 1040
+    uw = 0.01
+    rho, info = lbgen.emulsion(lx, ly, fraction=0.8, seed=6, walls=True)
+    sim = Sim(lx, ly, rho, n_species=2, walls=True, storage="f32", g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2,
+              gab=lbgen.EMULSION_GAB, rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0,
+              rho0=lbgen.EMULSION_RHO0, u_wall=(-uw, uw))
+    sim.step(200)
+    default_tile = sim.get_tile()
+    tile, _ = sim.autotune(trial_steps=20)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        start.record(sim.stream)
+        for _ in range(reps):
+            fn()
+        stop.record(sim.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / reps
+
+    ms_step = timed(lambda: sim.step(1), steps)
+    nprof = 50
+    buf = torch.empty((nprof, 2 * ly + 1), dtype=torch.float64, device="cuda")
+    it = iter(range(nprof))
+    ms_prof = timed(lambda: sim.profile(buf[next(it)]), nprof)
+    nsamp = max(2, steps // sample_every)
+    start.record(sim.stream)
+    samples = sim.sample_profiles(nsamp, sample_every)
+    st = sim.profile_stats(samples)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    ms_run = start.elapsed_time(stop) / (nsamp * sample_every)
+    sig = st["sigma"].cpu().numpy()
+    sim.close()
+    read_bytes = 9 * 2 * 4 * lx * ly
+    return {"workload": f"Couette cell {lx}x{ly}, confined emulsion, volume fraction 0.8, seed 6, walls +-{uw}, FP32",
+            "mass_fraction": info["mass_fraction"], "tile": list(tile), "default_tile": list(default_tile),
+            "ms_per_step": ms_step, "mlups": lx * ly / (ms_step * 1e-3) / 1e6,
+            "gbs": 144 * lx * ly / (ms_step * 1e-3) / 1e9,
+            "ms_per_profile": ms_prof, "profile_read_gbs": read_bytes / (ms_prof * 1e-3) / 1e9,
+            "profile_every": sample_every, "ms_per_step_with_profiles": ms_run,
+            "profile_overhead": ms_run / ms_step - 1.0, "samples": nsamp,
+            "mean_wall_stress": [float(sig[0]), float(-sig[-1])]}
+
+
 def adjoint_channel(T=4000, prerelax=2000, check_fd=True):
     """Gradient of L = <(W_bot + W_top)/2> + <Q> over T steps with respect to (G1, G2, G_AB,
     g_x) on a 512 x 256 confined emulsion channel (G1, G2 shared by both species), after an
@@ -406,6 +462,7 @@ def main():
         "copy_reference": copy,
         "beyond_infinity_cache": None if args.core else channel_beyond_cache(max(50, args.steps // 4)),
         "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
+        "couette_cell": None if args.core else couette_cell(max(200, args.steps // 2)),
         "adjoint": None if args.core else adjoint_channel(check_fd=not args.no_cpu),
         "kernel_source_hash": khash,
     }

@@ -50,7 +50,7 @@ struct lb_ctx {
   bool check_pending = false;
   bool unstable = false;
   GraphCache graph;  // graph.steps > 0: plain steps are replayed from captured graphs
-  double *d_prof = nullptr;      // profile pass: [ncb][ly][PROF_N]
+  double *d_prof = nullptr;      // profile pass: [ncb][ly][PROF_N] block sums, then [ly][PROF_N] row sums
   size_t prof_cap = 0;           // doubles
   std::string err;
 };
@@ -439,7 +439,7 @@ int lb_profile(lb_ctx *c, double *out) {
   int nseg = 0;
   const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
   const int ncb = ((c->lat.lx + c->tx - 1) / c->tx) * (c->tx / 64);
-  const size_t need = (size_t)ncb * c->lat.ly * PROF_N;
+  const size_t need = ((size_t)ncb + 1) * c->lat.ly * PROF_N;  // block sums, then the row sums
   if (need > c->prof_cap) {
     if (c->d_prof) (void)hipFree(c->d_prof);
     c->d_prof = nullptr;
@@ -464,7 +464,8 @@ int lb_profile(lb_ctx *c, double *out) {
       wb0 += 2.0 * a.wall_mom[0][s];
       wt0 += 2.0 * a.wall_mom[1][s];
     }
-  e = launch_profile_finish(c->d_prof, ncb, c->lat.lx, c->lat.ly, c->lat.walls, wb0, wt0, out, c->stream);
+  e = launch_profile_finish(c->d_prof, ncb, c->lat.lx, c->lat.ly, c->lat.walls, wb0, wt0,
+                            c->d_prof + (size_t)ncb * c->lat.ly * PROF_N, out, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "profile finish launch");
   return LB_OK;
 }

@@ -136,9 +136,9 @@ hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
 
 // Profile second pass: out[0..ly) = ubar, out[ly..2ly] = sigma (see lb_profile).  wb0, wt0:
-// sum_s rho_w,s U / 3 of the bottom and top wall.
+// sum_s rho_w,s U / 3 of the bottom and top wall; rows: scratch of ly * PROF_N doubles.
 hipError_t launch_profile_finish(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
-                                 double *out, hipStream_t st);
+                                 double *rows, double *out, hipStream_t st);
 hipError_t launch_profile_stats(const double *samples, long long n, int ly, int walls, int k0, double u_bot,
                                 double u_top, double *out, hipStream_t st);
 

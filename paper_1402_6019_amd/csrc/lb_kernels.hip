@@ -1123,21 +1123,28 @@ __global__ void fill_kernel(double *p, double v, int n) {
   if (i < n) p[i] = v;
 }
 
-// Profile second pass, one thread per row y (ubar) and per line k (sigma): sums the 64-column
-// blocks of each row in fixed order.  Line k lies between rows k-1 and k; its stress is
+// Profile second pass, part 1: the per-row sums rows[y][slot] = sum over the 64-column
+// blocks b of prof[b][y][slot], in increasing b (one thread per row and slot).
+__global__ void profile_rows_kernel(const double *prof, int ncb, int ly, double *rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ly * PROF_N) return;
+  const size_t stride = (size_t)ly * PROF_N;
+  double v = 0.0;
+  for (int b = 0; b < ncb; ++b) v += prof[b * stride + i];
+  rows[i] = v;
+}
+
+// Part 2, one thread per row y (ubar) and per line k (sigma).  Line k lies between rows
+// k-1 and k; its stress is
 //   sigma(k) = (I1(k-1) + I2(k-2) - Kup(k-1) + Kdn(k)) / lx
 // (pair forces across the line on the rows below it, minus the x-momentum streaming up
 // across it), with rows wrapping on periodic lattices.  On channels, sigma(0) and sigma(ly)
 // are the walls' momentum exchange: 2 Kdn(0) / lx - wb0 and -(2 Kup(ly-1) / lx - wt0).
-__global__ void profile_finish_kernel(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
+__global__ void profile_finish_kernel(const double *rows, int lx, int ly, int walls, double wb0, double wt0,
                                       double *out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > ly) return;
-  auto row = [&](int y, int slot) {
-    double v = 0.0;
-    for (int b = 0; b < ncb; ++b) v += prof[((size_t)b * ly + y) * PROF_N + slot];
-    return v;
-  };
+  auto row = [&](int y, int slot) { return rows[(size_t)y * PROF_N + slot]; };
   const double ilx = 1.0 / lx;
   if (k < ly) out[k] = row(k, PROF_U) * ilx;
   double sig;
@@ -1195,8 +1202,11 @@ __global__ void profile_stats_kernel(const double *smp, long long n, int ly, int
 }
 
 hipError_t launch_profile_finish(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
-                                 double *out, hipStream_t st) {
-  hipLaunchKernelGGL(profile_finish_kernel, dim3((ly + 1 + 255) / 256), dim3(256), 0, st, prof, ncb, lx, ly, walls, wb0,
+                                 double *rows, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(profile_rows_kernel, dim3((ly * PROF_N + 255) / 256), dim3(256), 0, st, prof, ncb, ly, rows);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(profile_finish_kernel, dim3((ly + 1 + 255) / 256), dim3(256), 0, st, rows, lx, ly, walls, wb0,
                      wt0, out);
   return hipGetLastError();
 }
