@@ -87,6 +87,7 @@ int ensure_partials(lb_ctx *c, int nb) {
 
 void fill_step_args(const lb_ctx *c, StepArgs &a) {
   a = make_step_args(c->lat, c->cpl, c->psi, c->tau, c->pitch, c->plane, c->sy);
+  a.stream_stores = streaming_stores(lb_pop_bytes(&c->lat));
 }
 
 // One plain step launch (no reductions) from buffer `from` to the other one, on stream st.

@@ -37,6 +37,7 @@ struct lb_batch {
   void *pop[2]{nullptr, nullptr};
   int cur = 0;
   size_t pop_bytes = 0;
+  size_t footprint = 0;  // lb_batch_pop_bytes of the instances (one buffer)
   hipStream_t stream = nullptr;
   int tx = 256, sy = 8, grid = 0;  // grid: persistent workgroups (0: one per tile)
   int n_cu = 256;
@@ -95,6 +96,7 @@ int build_tiles(lb_batch *b, int tx, int sy) {
     const long long plane = (long long)L.ly * pitch;
     const int syi = std::min(sy, L.ly);
     args[i] = make_step_args(L, b->cpl[i], b->psi[i], &b->tau[2 * i], pitch, plane, syi);
+    args[i].stream_stores = streaming_stores(b->footprint);
     const int nstrip = (L.lx + tx - 1) / tx, nseg = (L.ly + syi - 1) / syi;
     args[i].nseg = nseg;
     args[i].offset = (long long)b->off[i];
@@ -164,6 +166,7 @@ hipError_t launch_tiles(const lb_batch *b, int what, int from, int first, int co
   a.out_rho = out_rho;
   a.out_u = out_u;
   a.out_f32 = out_f32;
+  a.stream_stores = streaming_stores(b->footprint);
   return launch_batch_step(b->storage, b->ns, b->walls, what, b->tx, launch_grid(b, count), a, st);
 }
 
@@ -260,6 +263,7 @@ int lb_batch_init(lb_batch **out, int32_t n, const lb_lattice *lats, const lb_co
   b->pop[0] = pop_a;
   b->pop[1] = pop_b;
   b->pop_bytes = pop_bytes;
+  b->footprint = need;
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->n_cu = device_cu_count();
 

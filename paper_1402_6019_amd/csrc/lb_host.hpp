@@ -19,6 +19,11 @@ namespace host {
 
 constexpr int kPitchAlign = 256;  // elements: a multiple of the widest strip (see the step kernel's stores)
 constexpr int kMaxBlocks = 1 << 20;
+constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;  // MI355X last-level (Infinity) cache
+
+// Non-temporal population stores when the two population buffers cannot stay resident in
+// the Infinity Cache together (see the store policy in the step kernel).
+inline int streaming_stores(size_t one_buffer_bytes) { return 2 * one_buffer_bytes > kInfinityCacheBytes ? 1 : 0; }
 
 inline size_t elem_size(int storage) { return storage == LB_F64 ? 8 : (storage == LB_F32 ? 4 : 2); }
 inline int row_pitch(int lx) { return (lx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }

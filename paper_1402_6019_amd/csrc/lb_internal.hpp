@@ -55,6 +55,7 @@ struct StepArgs {
   int moving;                 // some wall moves (wall_mom != 0)
   int ncb;                    // profile: 64-column blocks per row in prof
   double *prof;               // profile: [ncb][ly][PROF_N]
+  int stream_stores;          // both population buffers exceed the Infinity Cache: non-temporal stores
 };
 
 // Batched launches: one tile of one instance.
@@ -75,6 +76,7 @@ struct BatchArgs {
   double *partials;      // [tiles][RED_N]
   void *out_rho, *out_u; // WHAT_MOMENTS (the launch then covers one instance)
   int out_f32;
+  int stream_stores;     // non-temporal population stores (see StepArgs)
 };
 
 // Second reduction pass of one batch instance: partial rows [p0, p0 + n).

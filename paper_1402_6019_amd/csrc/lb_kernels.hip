@@ -33,6 +33,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lb_internal.hpp"
 #include "lb_tables.hpp"
 
@@ -64,6 +66,17 @@ __device__ inline Rsrc make_rsrc(const void *p, uint32_t bytes) {
 
 template <int MODE> struct Codec;
 
+// Cache policy of the population stores (the buffer instructions' cache-policy operand):
+// SC1 (bit 4) gives the store device scope, so it is written through the XCD's L2 instead
+// of staying there dirty, which leaves L2 to the rows and halo columns that neighbouring
+// workgroups read twice; NT (bit 1) additionally marks it non-temporal, so it does not
+// displace the next step's reads from the Infinity Cache.  That pays when both population
+// buffers together exceed the Infinity Cache (the state cannot stay resident anyway) and
+// costs when they fit (the next step would have read them from it), so the host picks the
+// kernel instantiation per lattice from the footprint.
+constexpr int kStoreWriteThrough = 16;      // SC1
+constexpr int kStoreStreaming = 16 | 2;     // SC1 | NT
+
 // Every storage mode holds deviations d_l = f_l - W_l rho_ref from the rest equilibrium of a
 // per-species reference density.  load/store (layout kernels) convert to and from f; the
 // step works on deviations directly (bload/bstore), which costs nothing and keeps the
@@ -80,8 +93,9 @@ template <> struct Codec<MODE_F64> {
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
+  template <int AUX>
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
   }
   // both species of a site (adjacent in memory) in one access
   __device__ static void bload2(Rsrc r, uint32_t voff, uint32_t soff, L &a, L &b) {
@@ -89,9 +103,10 @@ template <> struct Codec<MODE_F64> {
     a = __builtin_bit_cast(double, u32x2{v[0], v[1]});
     b = __builtin_bit_cast(double, u32x2{v[2], v[3]});
   }
+  template <int AUX>
   __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
     const u32x2 ua = __builtin_bit_cast(u32x2, a), ub = __builtin_bit_cast(u32x2, b);
-    __builtin_amdgcn_raw_buffer_store_b128(u32x4{ua.x, ua.y, ub.x, ub.y}, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{ua.x, ua.y, ub.x, ub.y}, r, voff, soff, AUX);
   }
   __device__ static R expo(R v) { return exp(v); }
   __device__ static R rcp(R v) { return 1.0 / v; }
@@ -107,8 +122,9 @@ template <> struct Codec<MODE_F32> {
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
+  template <int AUX>
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, AUX);
   }
   __device__ static void bload2(Rsrc r, uint32_t voff, uint32_t soff, L &a, L &b) {
     // element access by index: with .x / .y and bit_cast this compiler narrowed the load
@@ -117,9 +133,10 @@ template <> struct Codec<MODE_F32> {
     a = __uint_as_float(v[0]);
     b = __uint_as_float(v[1]);
   }
+  template <int AUX>
   __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
     __builtin_amdgcn_raw_buffer_store_b64(u32x2{__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b)},
-                                          r, voff, soff, 0);
+                                          r, voff, soff, AUX);
   }
   __device__ static R expo(R v) { return __expf(v); }
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
@@ -145,8 +162,9 @@ template <> struct Codec<MODE_BF16> {
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
   }
+  template <int AUX>
   __device__ static void bstore(Rsrc r, uint32_t voff, uint32_t soff, R v) {
-    __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(encode(v), r, voff, soff, AUX);
   }
   __device__ static R expo(R v) { return __expf(v); }
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
@@ -155,8 +173,9 @@ template <> struct Codec<MODE_BF16> {
     a = uint16_t(v);
     b = uint16_t(v >> 16);
   }
+  template <int AUX>
   __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
-    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)encode(a) | ((uint32_t)encode(b) << 16), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)encode(a) | ((uint32_t)encode(b) << 16), r, voff, soff, AUX);
   }
 };
 
@@ -308,7 +327,7 @@ __device__ inline T wave_sum(T v) {
 // One tile: strip `strip` (tx = blockDim.x columns) and segment `seg` (a.sy rows) of the
 // lattice described by a, read from src and written to dst.  part: this tile's row of
 // reduction partials; out_*: moments output (WHAT_MOMENTS).
-template <int MODE, int NS, bool WALLS, int WHAT>
+template <int MODE, int NS, bool WALLS, int WHAT, int STP>
 __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const src, void *const dst, const int strip,
                                          const int seg, double *const part, void *const out_rho,
                                          void *const out_u, const int out_f32) {
@@ -760,11 +779,15 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     }
     if (STORE) {
       const Rsrc rd = make_rsrc(dst, buf_b);
+      auto store_row = [&](auto policy) {
+        constexpr int AUX = decltype(policy)::value;
 #pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        if (NS == 2) C::bstore2(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
-        else C::bstore(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
-      }
+        for (int l = 0; l < 9; ++l) {
+          if (NS == 2) C::template bstore2<AUX>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
+          else C::template bstore<AUX>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
+        }
+      };
+      store_row(std::integral_constant<int, STP>{});
     }
 
     if (REDUCE && col_ok) {
@@ -827,14 +850,14 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
 }
 
 // One lattice: one workgroup per tile, tiles in band-major order spread over the XCDs.
-template <int MODE, int NS, bool WALLS, int WHAT>
+template <int MODE, int NS, bool WALLS, int WHAT, int STP = kStoreWriteThrough>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step_kernel(StepArgs a) {
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int nstrip = (int)gridDim.x / a.nseg;
   const int seg = logical / nstrip;
   const int strip = logical - seg * nstrip;
-  run_tile<MODE, NS, WALLS, WHAT>(a, a.src, a.dst, strip, seg, a.partials + (size_t)blockIdx.x * RED_N, a.out_rho,
-                                  a.out_u, a.out_f32);
+  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, a.partials + (size_t)blockIdx.x * RED_N,
+                                       a.out_rho, a.out_u, a.out_f32);
 }
 
 // Many independent lattices in one persistent launch.  The host lists every tile of every
@@ -842,7 +865,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
 // rounds of gridDim.x, each round spread over the XCDs like the single-lattice grid, and
 // read the instance's sizes, couplings and buffer offsets from b.inst.  Tiles of one round
 // that neighbour each other share their overlap rows and columns through L2.
-template <int MODE, int NS, bool WALLS, int WHAT>
+template <int MODE, int NS, bool WALLS, int WHAT, int STP = kStoreWriteThrough>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void batch_step_kernel(BatchArgs b) {
   const int G = (int)gridDim.x;
   const int mine = xcd_remap(blockIdx.x, G);
@@ -853,7 +876,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
     const int ti = (int)__builtin_amdgcn_readfirstlane((uint32_t)(b.tile0 + t));
     const TileDesc td = b.tiles[ti];
     const StepArgs &a = b.inst[td.inst];
-    run_tile<MODE, NS, WALLS, WHAT>(a, b.src + a.offset, b.dst + a.offset, td.strip, td.seg,
+    run_tile<MODE, NS, WALLS, WHAT, STP>(a, b.src + a.offset, b.dst + a.offset, td.strip, td.seg,
                                     b.partials + (size_t)td.part * RED_N, b.out_rho, b.out_u, b.out_f32);
   }
 }
@@ -1017,9 +1040,18 @@ template <int MODE, int NS, bool WALLS>
 static hipError_t launch_step_t(int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
   const size_t lds = step_lds_bytes(MODE, NS, tx);
   switch (what) {
-    case WHAT_STEP: hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(nb), dim3(tx), lds, st, a); break;
+    case WHAT_STEP:
+      if (a.stream_stores)
+        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP, kStoreStreaming>), dim3(nb), dim3(tx), lds, st, a);
+      else
+        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(nb), dim3(tx), lds, st, a);
+      break;
     case WHAT_STEP_REDUCE:
-      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(nb), dim3(tx), lds, st, a);
+      if (a.stream_stores)
+        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE, kStoreStreaming>), dim3(nb), dim3(tx), lds,
+                           st, a);
+      else
+        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(nb), dim3(tx), lds, st, a);
       break;
     case WHAT_MOMENTS:
       hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_MOMENTS>), dim3(nb), dim3(tx), lds, st, a);
@@ -1046,10 +1078,18 @@ static hipError_t launch_batch_t(int what, int tx, int grid, const BatchArgs &b,
   const size_t lds = step_lds_bytes(MODE, NS, tx);
   switch (what) {
     case WHAT_STEP:
-      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(grid), dim3(tx), lds, st, b);
+      if (b.stream_stores)
+        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP, kStoreStreaming>), dim3(grid), dim3(tx), lds,
+                           st, b);
+      else
+        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(grid), dim3(tx), lds, st, b);
       break;
     case WHAT_STEP_REDUCE:
-      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(grid), dim3(tx), lds, st, b);
+      if (b.stream_stores)
+        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE, kStoreStreaming>), dim3(grid), dim3(tx),
+                           lds, st, b);
+      else
+        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(grid), dim3(tx), lds, st, b);
       break;
     case WHAT_MOMENTS:
       hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_MOMENTS>), dim3(grid), dim3(tx), lds, st, b);
