@@ -168,7 +168,7 @@ def droplet_radius(rho, rho_in, rho_out):
     return np.sqrt(abs(area) / np.pi)
 
 
-def shear_profile(orc):
+def shear_profile(orc, parts=False):
     """Stream-wise averaged velocity and shear stress of the current state of an Oracle
     (emulsion section: the averaged profiles ubar_x(z) and sigma(z) of the confined flows,
     from which the local fluidity of eq. (fluidity) / eq. (predict) is taken).
@@ -184,7 +184,8 @@ def shear_profile(orc):
                  exchanged with the bottom wall (W_bot, force on the wall) and the top wall
                  (-W_top, force of the wall on the fluid), moving walls included.  On a
                  periodic lattice sigma(ly) = sigma(0).
-    Every pair is enumerated explicitly (no regrouping)."""
+    Every pair is enumerated explicitly (no regrouping).  With parts=True also returns the
+    pair-force part of sigma alone (zero on wall lines)."""
     P = orc.params
     fl = orc.fields(fstar=True)
     fs, psi, rho, u = fl["fstar"], fl["psi"], fl["rho"], fl["u"]
@@ -234,9 +235,11 @@ def shear_profile(orc):
         return tot
 
     sigma = np.zeros(ly + 1)
+    pair = np.zeros(ly + 1)
     lines = range(1, ly) if walls else range(0, ly)
     for k in lines:
         below, above = (k - 1) % ly, k % ly
+        pair[k] = pair_force(k) / lx
         sigma[k] = (pair_force(k) - kup[below] + kdn[above]) / lx
     if walls:
         # reflected population off a wall moving with U: f*_out + 6 W_l rho_w (c_l . U)
@@ -256,7 +259,95 @@ def shear_profile(orc):
         sigma[ly] = -wt / lx
     else:
         sigma[ly] = sigma[0]
+        pair[ly] = pair[0]
+    if parts:
+        return ubar, sigma, pair
     return ubar, sigma
+
+
+def _at(a, dx, dy, walls, fill):
+    """a(x + dx, y + dy) for a field a[ly, lx]: periodic in x; in y periodic, or the wall
+    ghost value `fill` beyond the rows of a channel."""
+    b = np.roll(a, -dx, axis=1)
+    if not walls:
+        return np.roll(b, -dy, axis=0)
+    out = np.full_like(b, fill)
+    ly = a.shape[0]
+    if dy >= 0:
+        out[:ly - dy] = b[dy:]
+    else:
+        out[-dy:] = b[:ly + dy]
+    return out
+
+
+def stress_field(orc):
+    """Pressure tensor of section "The Stress Field on The lattice" at every site of the
+    current state: sigma_ij = sum_s [c_s^2 rho_s delta_ij + sigma^(int)_s,ij
+    + (tau_s - 1/2)^2 F_s,i F_s,j / rho_s] + sigma^(AB)_ij.  Returns (sxx, sxy, syy), each
+    [ly, lx].
+
+    sigma^(int) follows Appendix A shell by shell, with G_1 w(q) + G_2 p(q) per shell (the
+    long-range terms replace w by p and G_1 by G_2, and both add):
+      shells 1, 2: (G/2) W psi(x) sum_l psi(x + c_l) c_l c_l
+      shells 4, 8: (G/4) W sum_l [psi(x) psi(x + c_l) + psi(x - c_l/2) psi(x + c_l/2)] c_l c_l
+      shell 5:     (G/4) p(5) sum_{l=13..20} psi(x) psi(x + c_l) c_l c_l plus, for l = 13..16,
+                   (G/4) p(5) (psi(x + c_a) psi(x + c_b) + psi(x + c_a') psi(x + c_b')) c_l c_l
+                   over the two pairs of first-belt links whose difference is c_l.
+    The A-B repulsion (the cross-term reading: Shan-Chen form over the first belt) adds, by
+    the same construction as shells 1 and 2, (G_AB / 2) sum_{l=1..8} t(q)
+    [r_A(x) r_B(x + c_l) + r_B(x) r_A(x + c_l)] c_l c_l.  On channels the solid ghost rows carry
+    the wall densities, as in the force."""
+    P = orc.params
+    fl = orc.fields()
+    psi, rho, F = fl["psi"], fl["rho"], fl["force"]
+    walls = bool(P.walls)
+    ly, lx = P.ly, P.lx
+    comps = ((0, 0), (0, 1), (1, 1))
+    out = [np.zeros((ly, lx)) for _ in comps]
+
+    def add(val, c, coef):
+        for k, (i, j) in enumerate(comps):
+            out[k] += coef * c[i] * c[j] * val
+
+    extra = {13: ((5, 3), (1, 7)), 14: ((5, 4), (2, 7)), 15: ((2, 8), (6, 4)), 16: ((6, 1), (3, 8))}
+    for s in range(P.ns):
+        K = P.shell_k(s)
+        ps = psi[s]
+        pw = pseudo(P.rho_wall[s], P.psi0, P.rho0)
+
+        def at(dx, dy):
+            return _at(ps, dx, dy, walls, pw)
+
+        for l in range(1, 25):
+            c = LINKS[l]
+            q = SHELL_OF[c[0] * c[0] + c[1] * c[1]]
+            if q in (0, 1):
+                add(ps * at(*c), c, 0.5 * K[q])
+            elif q in (2, 4):
+                add(ps * at(*c), c, 0.25 * K[q])
+                add(at(-c[0] // 2, -c[1] // 2) * at(c[0] // 2, c[1] // 2), c, 0.25 * K[q])
+            else:
+                add(ps * at(*c), c, 0.25 * K[q])
+        for l, pairs in extra.items():
+            v = sum(at(*LINKS[a]) * at(*LINKS[b]) for a, b in pairs)
+            add(v, LINKS[l], 0.25 * K[3])
+        # ideal part and the discrete forcing correction
+        r = rho[s]
+        out[0] += CS2 * r
+        out[2] += CS2 * r
+        corr = (P.tau[s] - 0.5) ** 2 / r
+        out[0] += corr * F[s, 0] * F[s, 0]
+        out[1] += corr * F[s, 0] * F[s, 1]
+        out[2] += corr * F[s, 1] * F[s, 1]
+    if P.ns == 2 and P.gab != 0.0:
+        src = psi if P.cross_psi else rho
+        fills = [pseudo(P.rho_wall[s], P.psi0, P.rho0) if P.cross_psi else P.rho_wall[s] for s in range(2)]
+        for l in range(1, 9):
+            c = LINKS[l]
+            t = P.t[SHELL_OF[c[0] * c[0] + c[1] * c[1]]]
+            v = (src[0] * _at(src[1], c[0], c[1], walls, fills[1]) + src[1] * _at(src[0], c[0], c[1], walls, fills[0]))
+            add(v, c, 0.5 * P.gab * t)
+    return out[0], out[1], out[2]
 
 
 def fluidity(ubar, sigma, walls=True, u_wall=(0.0, 0.0)):

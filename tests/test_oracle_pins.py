@@ -433,6 +433,87 @@ def test_flat_interface_surface_stress_pattern(flat_interface):
     assert rho.min() < rho[0] - 1e-3  # kink below the gas density
 
 
+def test_flat_interface_stress_tensor_is_uniform(flat_interface):
+    """Sec. "The Stress Field on The lattice" and Appendix A: the site pressure tensor
+    c_s^2 rho + sigma^(int) + (tau - 1/2)^2 F F / rho, with sigma^(int) built shell by shell
+    (midpoint terms for shells 4 and 8, the four extra pair terms of shell 5), has a normal
+    component that is the same at every site across a relaxed flat interface (to machine
+    precision) and equals (BULK); its xx - yy part equals the Appendix A mismatch."""
+    P, o, fl = flat_interface
+    acc = []
+    for _ in range(2):  # average two consecutive steps (period-2 mode)
+        sxx, sxy, syy = dg.stress_field(o)
+        acc.append(sxx[0])
+        o.step(1)
+    sxx_avg = 0.5 * (acc[0] + acc[1])
+    assert np.ptp(sxx_avg) / sxx_avg.mean() < 1e-12
+    rho = o.fields()["rho"][0, 0]
+    assert dg.bulk_pressure(rho[64], P.g1[0] + P.g2[0]) == pytest.approx(sxx_avg.mean(), rel=1e-9)
+    assert np.abs(sxy).max() < 1e-15
+    fl2 = o.fields()
+    psi, r, F = fl2["psi"][0, 0], fl2["rho"][0, 0], fl2["force"][0, :, 0]
+    sxx, _, syy = dg.stress_field(o)
+    corr = (P.tau[0] - 0.5) ** 2 * F[0] * F[0] / r
+    mism = dg.stress_mismatch_a(psi, P.g1[0], P.g2[0], list(P.w), list(P.p))
+    np.testing.assert_allclose((sxx - syy)[0] - corr, mism, atol=1e-15)
+
+
+def test_flat_interface_along_y_stress_tensor_is_uniform():
+    """The same slab turned by 90 degrees: sigma_yy is uniform and sigma_xx - sigma_yy is
+    minus the Appendix A mismatch, which exercises the y components of every shell."""
+    ly = 128
+    P = Params(lx=1, ly=ly, ns=1, **FILM)
+    rho = _tanh_slab(ly, 1.39, 0.28, 32, 96)[0][:, None][None]
+    o = Oracle(P, rho_init=rho)
+    o.step(70000)
+    acc = []
+    for _ in range(2):
+        sxx, sxy, syy = dg.stress_field(o)
+        acc.append(syy[:, 0])
+        o.step(1)
+    syy_avg = 0.5 * (acc[0] + acc[1])
+    assert np.ptp(syy_avg) / syy_avg.mean() < 1e-12
+    fl = o.fields()
+    psi, r, Fy = fl["psi"][0, :, 0], fl["rho"][0, :, 0], fl["force"][0, 1, :, 0]
+    sxx, _, syy = dg.stress_field(o)
+    corr = (P.tau[0] - 0.5) ** 2 * Fy * Fy / r
+    mism = dg.stress_mismatch_a(psi, P.g1[0], P.g2[0], list(P.w), list(P.p))
+    np.testing.assert_allclose((syy - sxx)[:, 0] - corr, mism, atol=1e-15)
+
+
+def test_stress_tensor_uniform_two_component_bulk():
+    """A uniform two-component state: sigma = P_b delta with the two-component (BULK)."""
+    P = Params(lx=8, ly=7, ns=2, g1=(-9.0, -8.0), g2=(8.1, 7.1), gab=0.587, rho0=0.83)
+    rho = np.stack([np.full((7, 8), 0.9), np.full((7, 8), 0.4)])
+    sxx, sxy, syy = dg.stress_field(Oracle(P, rho_init=rho))
+    pb = dg.bulk_pressure_2c(0.9, 0.4, P)
+    np.testing.assert_allclose(sxx, pb, rtol=1e-14)
+    np.testing.assert_allclose(syy, pb, rtol=1e-14)
+    assert np.abs(sxy).max() < 1e-17
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_stress_tensor_shear_component_matches_line_stress(walls):
+    """Each pair's xy contribution is spread over sites so that the row average of
+    sigma^(int)_xy is minus the mean of the pair-force stresses through the row's two
+    bounding lines (the exact momentum flux of the shear-stress profile)."""
+    lx, ly = 40, 24
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.7, seed=7, walls=walls, rmin=4, rmax=7)
+    P = Params(lx=lx, ly=ly, ns=2, walls=1 if walls else 0, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2,
+               gab=lbgen.EMULSION_GAB, rho0=lbgen.EMULSION_RHO0, body=(2e-5, 0.0),
+               rho_wall=lbgen.EMULSION_POOR if walls else (0.0, 0.0), u_wall=(-0.02, 0.03) if walls else (0.0, 0.0))
+    o = Oracle(P, rho_init=rho)
+    o.step(30)
+    sxx, sxy, syy = dg.stress_field(o)
+    fl = o.fields()
+    F, r = fl["force"], fl["rho"]
+    corr = sum((P.tau[s] - 0.5) ** 2 * F[s, 0] * F[s, 1] / r[s] for s in range(2))
+    _, _, pair = dg.shear_profile(o, parts=True)
+    pred = -0.5 * (pair[:-1] + pair[1:])
+    assert np.abs((sxy - corr).mean(axis=1) - pred).max() < 1e-12 * np.abs(pred).max()
+    assert np.abs(pred).max() > 1e-4
+
+
 # ----------------------------------------------------------------------------------------
 # Laplace law for static droplets
 # ----------------------------------------------------------------------------------------
