@@ -144,6 +144,19 @@ int lb_set_reduce_every(lb_ctx *ctx, int32_t k);
    Either pointer may be NULL.  Asynchronous. */
 int lb_moments(lb_ctx *ctx, void *rho, void *u, int32_t dtype);
 
+/* Pressure tensor of the current state at every site (section "The Stress Field on The
+   lattice" and Appendix A): sigma (device, [3][ly][lx], components xx, xy, yy) =
+   sum_s [c_s^2 rho_s delta + sigma^(int)_s + (tau_s - 1/2)^2 F_s F_s / rho_s] + sigma^(AB), with
+   sigma^(int)_s built shell by shell as Appendix A writes it (G_ss,1 w(q) + G_ss,2 p(q) per
+   shell: half of each first- and second-shell pair at its two ends; midpoint terms for shells 4
+   and 8; for shell 5 the pair at its ends plus the four extra pair products), and the A-B pair
+   stress (G_AB / 2) sum_l t(q) [r_A(x) r_B(x + c_l) + r_B(x) r_A(x + c_l)] c_l c_l over the first
+   belt (r = rho, or psi with cross_uses_psi).  Wall ghost rows enter as in the force.  Across a
+   relaxed flat interface the normal component is uniform and equals the bulk pressure (BULK).
+   dtype: lb_dtype.  One read of the state (a step without the store); the state is not
+   changed.  Asynchronous. */
+int lb_stress_field(lb_ctx *ctx, void *sigma, int32_t dtype);
+
 /* Time-averaged x-force per unit wall length on the bottom and top walls (host out[2]),
    averaged over the reduced steps since the last reset; momentum exchange of the bounced
    populations, c_x f* out minus c_x of the reflected population (2 c_x f* for walls at rest,

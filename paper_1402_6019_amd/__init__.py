@@ -201,6 +201,16 @@ class Sim:
         self._chk(self._lib.lb_wall_stress(self._h, out, 1 if reset else 0))
         return out[0], out[1]
 
+    def stress_field(self, dtype=None):
+        """Site pressure tensor of the current state (Appendix A): device tensor [3, ly, lx]
+        with the xx, xy and yy components."""
+        torch = self.torch
+        dtype = dtype or torch.float64
+        out = torch.empty((3, self.ly, self.lx), dtype=dtype, device=self.device)
+        code = B.LB_OUT_F32 if dtype == torch.float32 else B.LB_OUT_F64
+        self._chk(self._lib.lb_stress_field(self._h, ctypes.c_void_p(out.data_ptr()), code))
+        return out
+
     def profile(self, out=None):
         """Stream-wise averaged profiles of the current state (device FP64 tensor of 2 ly + 1):
         [0:ly] the x-averaged velocity ubar(y), [ly:] the shear stress sigma(k) through the

@@ -321,6 +321,24 @@ int lb_moments(lb_ctx *c, void *rho, void *u, int32_t dtype) {
   return run_step_kernel(c, WHAT_MOMENTS, rho, u, dtype == LB_OUT_F32);
 }
 
+int lb_stress_field(lb_ctx *c, void *sigma, int32_t dtype) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!sigma) return fail(c, LB_EINVAL, "null output");
+  if (dtype != LB_OUT_F64 && dtype != LB_OUT_F32) return fail(c, LB_EINVAL, "dtype must be LB_OUT_F64 or LB_OUT_F32");
+  int nseg = 0;
+  const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
+  StepArgs a;
+  fill_step_args(c, a);
+  a.nseg = nseg;
+  a.src = c->pop[c->cur];
+  a.dst = c->pop[c->cur ^ 1];  // not written
+  a.out_sigma = sigma;
+  a.out_f32 = dtype == LB_OUT_F32;
+  hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_STRESS, c->tx, nb, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "stress kernel launch");
+  return LB_OK;
+}
+
 int lb_wall_stress(lb_ctx *c, double out[2], int32_t reset) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (!out) return fail(c, LB_EINVAL, "null output");

@@ -15,7 +15,8 @@ enum StepWhat {
   WHAT_STEP_REDUCE = 1,  // same, plus FP64 per-workgroup partial sums
   WHAT_MOMENTS = 2,      // write rho_s and the half-force velocity, store nothing
   WHAT_OBSERVE = 3,      // partial sums of the current state, store nothing
-  WHAT_PROFILE = 4       // per-row sums of the current state (velocity, stress parts), store nothing
+  WHAT_PROFILE = 4,      // per-row sums of the current state (velocity, stress parts), store nothing
+  WHAT_STRESS = 5        // write the site pressure tensor of the current state, store nothing
 };
 
 // Per-row sums written by a WHAT_PROFILE launch, per 64-column block of a row:
@@ -56,6 +57,7 @@ struct StepArgs {
   int ncb;                    // profile: 64-column blocks per row in prof
   double *prof;               // profile: [ncb][ly][PROF_N]
   int stream_stores;          // both population buffers exceed the Infinity Cache: non-temporal stores
+  void *out_sigma;            // stress: [3][ly][lx] (xx, xy, yy)
 };
 
 // Batched launches: one tile of one instance.

@@ -676,7 +676,83 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       }
     }
 
-    if (WHAT != WHAT_MOMENTS) {
+    if (WHAT == WHAT_STRESS && col_ok) {
+      // Pressure tensor of the lattice stress section, per site: sum over species of
+      // c_s^2 rho_s delta + sigma^(int)_s + (tau_s - 1/2)^2 F_s F_s / rho_s, plus the A-B pair
+      // stress.  sigma^(int) follows Appendix A shell by shell (K(q) = G_1 w(q) + G_2 p(q)):
+      //   shells 1, 2: K/2 psi(x) sum psi(x + c) c c
+      //   shells 4, 8: K/4 sum [psi(x) psi(x + c) + psi(x - c/2) psi(x + c/2)] c c
+      //   shell 5:     K/4 psi(x) sum psi(x + c) c c, plus K/4 (psi(x + c_a) psi(x + c_b) + ...) c c
+      //                over the first-belt pairs whose difference is c13, c14, c15 or c16
+      double sxx = 0.0, sxy = 0.0, syy = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const R k1 = R(a.K[s][0]) * R(0.5), k2 = R(a.K[s][1]) * R(0.5), k4 = R(a.K[s][2]);
+        const R k5 = R(a.K[s][3]) * R(0.25), k8 = R(a.K[s][4]);
+        const R p0 = pc.v[s];
+        const R E = e1.v[s], W = w1.v[s], N = n1.v[s], S = s1.v[s];
+        const R NE = ne.v[s], NW = nw.v[s], SE = se.v[s], SW = sw.v[s];
+        const R diag = (NE + SW) + (NW + SE), dxy = (NE + SW) - (NW + SE);
+        const R d8 = (d8a.v[s] + d8A.v[s]) + (d8b.v[s] + d8B.v[s]), d8xy = (d8a.v[s] + d8A.v[s]) - (d8b.v[s] + d8B.v[s]);
+        const R mid8 = R(2) * (NE * SW + NW * SE), mid8xy = R(2) * (NE * SW - NW * SE);
+        const R qx = (qa.v[s] + qA.v[s]) + (qb.v[s] + qB.v[s]);  // |c_x| = 2
+        const R qy = (qc.v[s] + qC.v[s]) + (qd.v[s] + qD.v[s]);  // |c_y| = 2
+        const R qxy = ((qa.v[s] + qA.v[s]) + (qc.v[s] + qC.v[s])) - ((qb.v[s] + qB.v[s]) + (qd.v[s] + qD.v[s]));
+        const R e13 = NE * W + E * SW, e14 = NE * S + N * SW, e15 = N * SE + NW * S, e16 = NW * E + W * SE;
+        R xx = k1 * p0 * (E + W) + k2 * p0 * diag + k4 * (p0 * (e2.v[s] + w2.v[s]) + R(2) * (E * W)) +
+               k8 * (p0 * d8 + mid8) + k5 * (p0 * (R(4) * qx + qy) + (R(4) * (e13 + e16) + (e14 + e15)));
+        R yy = k1 * p0 * (N + S) + k2 * p0 * diag + k4 * (p0 * (n2.v[s] + s2.v[s]) + R(2) * (N * S)) +
+               k8 * (p0 * d8 + mid8) + k5 * (p0 * (qx + R(4) * qy) + ((e13 + e16) + R(4) * (e14 + e15)));
+        R xy = k2 * p0 * dxy + k8 * (p0 * d8xy + mid8xy) + k5 * R(2) * (p0 * qxy + ((e13 + e14) - (e15 + e16)));
+        // ideal gas and the discrete forcing correction
+        const R cr = (tau[s] - R(0.5)) * (tau[s] - R(0.5)) / rho[s];
+        xx += rho[s] * R(1.0 / 3.0) + cr * Fx[s] * Fx[s];
+        yy += rho[s] * R(1.0 / 3.0) + cr * Fy[s] * Fy[s];
+        xy += cr * Fx[s] * Fy[s];
+        sxx += double(xx);
+        sxy += double(xy);
+        syy += double(yy);
+      }
+      if (NS == 2) {
+        // A-B repulsion: (G_AB / 2) sum_l t(q) [r_A(x) r_B(x + c) + r_B(x) r_A(x + c)] c c
+        const V *base = a.cross_psi ? psi_ring : rho_ring;
+        const V *xr[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          int sl = lead_slot + 3 + dir * (k - 1);
+          sl = sl >= 6 ? sl - 6 : sl;
+          xr[k] = base + sl * W4 + tid + 2;
+        }
+        const V c0 = xr[1][0];
+        R xx = 0, xy = 0, yy = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int o = 1 - s;
+          const R ax = xr[1][1].v[o] + xr[1][-1].v[o], ay = xr[2][0].v[o] + xr[0][0].v[o];
+          const R dg = (xr[2][1].v[o] + xr[0][-1].v[o]) + (xr[2][-1].v[o] + xr[0][1].v[o]);
+          const R dgxy = (xr[2][1].v[o] + xr[0][-1].v[o]) - (xr[2][-1].v[o] + xr[0][1].v[o]);
+          xx += c0.v[s] * (T1 * ax + T2 * dg);
+          yy += c0.v[s] * (T1 * ay + T2 * dg);
+          xy += c0.v[s] * (T2 * dgxy);
+        }
+        sxx += double(R(0.5) * xx);
+        sxy += double(R(0.5) * xy);
+        syy += double(R(0.5) * yy);
+      }
+      const size_t site = (size_t)y * lx + xc;
+      const size_t nsite = (size_t)lx * ly;
+      if (out_f32) {
+        static_cast<float *>(a.out_sigma)[site] = float(sxx);
+        static_cast<float *>(a.out_sigma)[nsite + site] = float(sxy);
+        static_cast<float *>(a.out_sigma)[2 * nsite + site] = float(syy);
+      } else {
+        static_cast<double *>(a.out_sigma)[site] = sxx;
+        static_cast<double *>(a.out_sigma)[nsite + site] = sxy;
+        static_cast<double *>(a.out_sigma)[2 * nsite + site] = syy;
+      }
+    }
+
+    if (WHAT != WHAT_MOMENTS && WHAT != WHAT_STRESS) {
     double wb = 0.0, wt = 0.0;
     R fsa[NS][9];
 #pragma unroll
@@ -1061,6 +1137,9 @@ static hipError_t launch_step_t(int what, int tx, int nb, const StepArgs &a, hip
       break;
     case WHAT_PROFILE:
       hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_PROFILE>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_STRESS:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STRESS>), dim3(nb), dim3(tx), lds, st, a);
       break;
     default: return hipErrorInvalidValue;
   }
