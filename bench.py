@@ -134,6 +134,63 @@ def batched_sweep(steps, n=64):
             "footprint_mb": 144 * sites / 1e6}
 
 
+def auxiliary_passes(rho, kw, reps=200):
+    """Cost of the passes around the plain step on the 1024^2 emulsion, FP32: the step with
+    the FP64 reductions in its epilogue (mass, momentum, wall stress, flow rate, health), the
+    moments output, the profile pass and the site pressure tensor; each timed over `reps`
+    launches with HIP events on the library's stream (the steps as one lb_step call)."""
+    import torch
+    from paper_1402_6019_amd import Sim
+    sim = Sim(LX, LY, rho, storage="f32", **kw)
+    sim.step(50)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        start.record(sim.stream)
+        for _ in range(reps):
+            fn()
+        stop.record(sim.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / reps
+
+    def timed_steps():
+        sim.step(reps)
+        torch.cuda.synchronize()
+        start.record(sim.stream)
+        sim.step(reps)
+        stop.record(sim.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / reps
+
+    out = {}
+    out["step_ms"] = timed_steps()
+    sim.set_reduce_every(1)
+    out["step_with_reductions_ms"] = timed_steps()
+    sim.set_reduce_every(0)
+    rho_o = torch.empty((2, LY, LX), dtype=torch.float32, device="cuda")
+    u_o = torch.empty((2, LY, LX), dtype=torch.float32, device="cuda")
+    import ctypes
+    from paper_1402_6019_amd import _binding as B
+    out["moments_f32_ms"] = timed(lambda: sim._lib.lb_moments(sim._h, ctypes.c_void_p(rho_o.data_ptr()),
+                                                               ctypes.c_void_p(u_o.data_ptr()), B.LB_OUT_F32))
+    prof = torch.empty(2 * LY + 1, dtype=torch.float64, device="cuda")
+    out["profile_ms"] = timed(lambda: sim.profile(prof))
+    sig = torch.empty((3, LY, LX), dtype=torch.float32, device="cuda")
+    out["stress_field_f32_ms"] = timed(lambda: sim._lib.lb_stress_field(sim._h, ctypes.c_void_p(sig.data_ptr()),
+                                                                         B.LB_OUT_F32))
+    sim.close()
+    read = 9 * 2 * 4 * LX * LY
+    out["reduction_overhead"] = out["step_with_reductions_ms"] / out["step_ms"] - 1.0
+    out["moments_gbs"] = (read + 4 * 4 * LX * LY) / (out["moments_f32_ms"] * 1e-3) / 1e9
+    out["stress_field_gbs"] = (read + 3 * 4 * LX * LY) / (out["stress_field_f32_ms"] * 1e-3) / 1e9
+    out["note"] = "moments and stress field: reads of the state plus their own FP32 outputs, per launch"
+    return out
+
+
 def couette_cell(steps, sample_every=100):
     """Planar Couette cell of the emulsion section at its 1040 x 1040 domain: confined
     emulsion (volume fraction 0.8, seed 6), walls wetted by B sliding with -U_w and +U_w
@@ -463,6 +520,7 @@ def main():
         "beyond_infinity_cache": None if args.core else channel_beyond_cache(max(50, args.steps // 4)),
         "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
         "couette_cell": None if args.core else couette_cell(max(200, args.steps // 2)),
+        "auxiliary_passes": None if args.core else auxiliary_passes(rho, kw),
         "adjoint": None if args.core else adjoint_channel(check_fd=not args.no_cpu),
         "kernel_source_hash": khash,
     }

@@ -45,6 +45,10 @@ struct lb_ctx {
   int partial_cap = 0;
   double *d_totals = nullptr;    // [RED_N]
   double *d_acc = nullptr;       // [4]: wall stress sums (bot, top), count, bad
+  double *d_accrows = nullptr;   // [accrow_cap][ACC_N]: per-workgroup running sums of reducing steps
+  int accrow_cap = 0;
+  int acc_nb = 0;                // workgroups of the reducing launches since the last flush
+  int64_t acc_pending = 0;       // reducing launches since the last flush
   double *h_acc = nullptr;       // pinned copy of d_acc for the asynchronous health check
   hipEvent_t ev = nullptr;
   bool check_pending = false;
@@ -117,13 +121,48 @@ hipError_t launch_checkpoint_from(const lb_ctx *c, int from, void *dst, hipStrea
   return launch_checkpoint(c->lat.storage, c->lat.walls, la, st);
 }
 
+// Fold the running sums of the reducing steps since the last flush into d_acc.
+int flush_acc(lb_ctx *c) {
+  if (c->acc_pending == 0) return LB_OK;
+  hipError_t e = launch_flush(c->d_accrows, c->acc_nb, c->d_acc, (double)c->acc_pending, 1.0 / c->lat.lx, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reduction flush");
+  c->acc_pending = 0;
+  return LB_OK;
+}
+
+// Rows of running sums for nb workgroups, zeroed (flushing what they hold first).
+int ensure_accrows(lb_ctx *c, int nb) {
+  if (c->acc_pending > 0 && c->acc_nb != nb) {
+    int rc = flush_acc(c);
+    if (rc) return rc;
+  }
+  if (nb <= c->accrow_cap) return LB_OK;
+  int rc = flush_acc(c);
+  if (rc) return rc;
+  if (c->d_accrows) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->d_accrows);
+  }
+  c->d_accrows = nullptr;
+  c->accrow_cap = 0;
+  hipError_t e = hipMalloc(&c->d_accrows, (size_t)nb * ACC_N * sizeof(double));
+  if (e != hipSuccess) return fail(c, LB_ENOMEM, std::string("reduction rows: ") + hipGetErrorString(e));
+  if ((e = launch_fill(c->d_accrows, 0.0, nb * ACC_N, c->stream)) != hipSuccess) return hip_fail(c, e, "reduction rows");
+  c->accrow_cap = nb;
+  return LB_OK;
+}
+
 // One launch of the fused kernel on the current buffer.
 int run_step_kernel(lb_ctx *c, int what, void *out_rho, void *out_u, int out_f32) {
   int nseg = 0;
   const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
-  const bool reduce = (what == WHAT_STEP_REDUCE || what == WHAT_OBSERVE);
+  const bool reduce = what == WHAT_OBSERVE;
   if (reduce) {
     int rc = ensure_partials(c, nb);
+    if (rc) return rc;
+  }
+  if (what == WHAT_STEP_ACCUM) {
+    int rc = ensure_accrows(c, nb);
     if (rc) return rc;
   }
   StepArgs a;
@@ -132,15 +171,19 @@ int run_step_kernel(lb_ctx *c, int what, void *out_rho, void *out_u, int out_f32
   a.src = c->pop[c->cur];
   a.dst = c->pop[c->cur ^ 1];
   a.partials = c->d_partials;
+  a.accrows = c->d_accrows;
   a.out_rho = out_rho;
   a.out_u = out_u;
   a.out_f32 = out_f32;
   hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, what, c->tx, nb, a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
   if (reduce) {
-    e = launch_reduce(c->d_partials, nb, c->d_totals, c->d_acc, what == WHAT_STEP_REDUCE ? 1 : 0,
-                      1.0 / c->lat.lx, c->stream);
+    e = launch_reduce(c->d_partials, nb, c->d_totals, c->d_acc, 0, 1.0 / c->lat.lx, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+  }
+  if (what == WHAT_STEP_ACCUM) {
+    c->acc_nb = nb;
+    ++c->acc_pending;
   }
   return LB_OK;
 }
@@ -292,13 +335,16 @@ int lb_step(lb_ctx *c, int64_t n) {
   }
   for (int64_t k = 0; k < n; ++k) {
     const bool red = c->reduce_every > 0 && (c->t % c->reduce_every) == 0;
-    rc = run_step_kernel(c, red ? WHAT_STEP_REDUCE : WHAT_STEP, nullptr, nullptr, 0);
+    rc = run_step_kernel(c, red ? WHAT_STEP_ACCUM : WHAT_STEP, nullptr, nullptr, 0);
     if (rc) return rc;
     reduced |= red;
     c->cur ^= 1;
     ++c->t;
   }
   if (reduced) {
+    // one second pass per call: fold the workgroups' running sums, then read back the health
+    rc = flush_acc(c);
+    if (rc) return rc;
     hipError_t e = hipMemcpyAsync(c->h_acc, c->d_acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "health readback");
@@ -343,6 +389,8 @@ int lb_wall_stress(lb_ctx *c, double out[2], int32_t reset) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (!out) return fail(c, LB_EINVAL, "null output");
   if (!c->lat.walls) return fail(c, LB_ESTATE, "wall stress needs a channel lattice");
+  int rc = flush_acc(c);
+  if (rc) return rc;
   double h[4];
   hipError_t e = hipMemcpyAsync(h, c->d_acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -761,6 +809,7 @@ void lb_destroy(lb_ctx *c) {
   if (c->d_prof) (void)hipFree(c->d_prof);
   if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->d_acc) (void)hipFree(c->d_acc);
+  if (c->d_accrows) (void)hipFree(c->d_accrows);
   if (c->h_acc) (void)hipHostFree(c->h_acc);
   if (c->ev) (void)hipEventDestroy(c->ev);
   c->graph.destroy();

@@ -47,6 +47,8 @@ struct lb_batch {
   TileDesc *d_tiles = nullptr;
   ReduceJob *d_jobs = nullptr;
   double *d_partials = nullptr;  // [tiles][RED_N]
+  double *d_accrows = nullptr;   // [tiles][ACC_N]: running sums of reducing steps (zero after a flush)
+  int64_t acc_pending = 0;       // reducing launches since the last flush
   double *d_totals = nullptr;    // [n][RED_N]
   double *d_acc = nullptr;       // [n][4]: wall stress sums (bot, top), count, bad
   double *h_acc = nullptr;       // pinned copy of d_acc
@@ -120,11 +122,15 @@ int build_tiles(lb_batch *b, int tx, int sy) {
   if ((size_t)nt > b->tile_cap) {
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_partials) (void)hipFree(b->d_partials);
+    if (b->d_accrows) (void)hipFree(b->d_accrows);
     b->d_tiles = nullptr;
     b->d_partials = nullptr;
+    b->d_accrows = nullptr;
     b->tile_cap = 0;
     if ((e = hipMalloc(&b->d_tiles, (size_t)nt * sizeof(TileDesc))) != hipSuccess ||
-        (e = hipMalloc(&b->d_partials, (size_t)nt * RED_N * sizeof(double))) != hipSuccess)
+        (e = hipMalloc(&b->d_partials, (size_t)nt * RED_N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&b->d_accrows, (size_t)nt * ACC_N * sizeof(double))) != hipSuccess ||
+        (e = launch_fill(b->d_accrows, 0.0, nt * ACC_N, b->stream)) != hipSuccess)
       return bfail(b, LB_ENOMEM, std::string("tile table: ") + hipGetErrorString(e));
     b->tile_cap = nt;
   }
@@ -146,6 +152,14 @@ int build_tiles(lb_batch *b, int tx, int sy) {
   return LB_OK;
 }
 
+int flush_acc(lb_batch *b) {
+  if (b->acc_pending == 0) return LB_OK;
+  hipError_t e = launch_batch_flush(b->d_accrows, b->d_jobs, b->n, b->d_acc, (double)b->acc_pending, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "reduction flush");
+  b->acc_pending = 0;
+  return LB_OK;
+}
+
 int launch_grid(const lb_batch *b, int ntiles) {
   const int g = b->grid > 0 ? b->grid : ntiles;
   return std::max(1, std::min(g, ntiles));
@@ -163,6 +177,7 @@ hipError_t launch_tiles(const lb_batch *b, int what, int from, int first, int co
   a.src = static_cast<const char *>(b->pop[from]);
   a.dst = static_cast<char *>(b->pop[from ^ 1]);
   a.partials = b->d_partials;
+  a.accrows = b->d_accrows;
   a.out_rho = out_rho;
   a.out_u = out_u;
   a.out_f32 = out_f32;
@@ -342,14 +357,17 @@ int lb_batch_step(lb_batch *b, int64_t n) {
   bool reduced = false;
   for (int64_t k = 0; k < n; ++k) {
     const bool red = b->reduce_every > 0 && (b->t % b->reduce_every) == 0;
-    hipError_t e = launch_tiles(b, red ? WHAT_STEP_REDUCE : WHAT_STEP, b->cur, 0, nt, b->stream);
-    if (e == hipSuccess && red) e = launch_batch_reduce(b->d_partials, b->d_jobs, b->n, b->d_totals, b->d_acc, 1, b->stream);
+    hipError_t e = launch_tiles(b, red ? WHAT_STEP_ACCUM : WHAT_STEP, b->cur, 0, nt, b->stream);
     if (e != hipSuccess) return bhip(b, e, "batch step launch");
     reduced |= red;
+    if (red) ++b->acc_pending;
     b->cur ^= 1;
     ++b->t;
   }
   if (reduced) {
+    // one second pass per call: fold every tile's running sums into its instance
+    int rc = flush_acc(b);
+    if (rc) return rc;
     hipError_t e = hipMemcpyAsync(b->h_acc, b->d_acc, (size_t)b->n * 4 * sizeof(double), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->ev, b->stream);
     if (e != hipSuccess) return bhip(b, e, "health readback");
@@ -489,6 +507,8 @@ int lb_batch_wall_stress(lb_batch *b, double *out, int32_t reset) {
   if (!b) return bfail(nullptr, LB_EINVAL, "null context");
   if (!out) return bfail(b, LB_EINVAL, "null output");
   if (!b->walls) return bfail(b, LB_ESTATE, "wall stress needs channel lattices");
+  int rc = flush_acc(b);
+  if (rc) return rc;
   std::vector<double> h((size_t)b->n * 4);
   hipError_t e = hipMemcpyAsync(h.data(), b->d_acc, h.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -556,7 +576,7 @@ void lb_batch_destroy(lb_batch *b) {
   if (!b) return;
   if (b->check_pending && b->ev) (void)hipEventSynchronize(b->ev);
   (void)hipStreamSynchronize(b->stream);
-  for (void *p : {(void *)b->d_args, (void *)b->d_tiles, (void *)b->d_jobs, (void *)b->d_partials,
+  for (void *p : {(void *)b->d_args, (void *)b->d_tiles, (void *)b->d_jobs, (void *)b->d_partials, (void *)b->d_accrows,
                   (void *)b->d_totals, (void *)b->d_acc})
     if (p) (void)hipFree(p);
   if (b->h_acc) (void)hipHostFree(b->h_acc);

@@ -12,12 +12,15 @@ enum StoreMode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
 // What one launch of the fused step kernel does.
 enum StepWhat {
   WHAT_STEP = 0,         // stream + force + collide, store f*
-  WHAT_STEP_REDUCE = 1,  // same, plus FP64 per-workgroup partial sums
   WHAT_MOMENTS = 2,      // write rho_s and the half-force velocity, store nothing
   WHAT_OBSERVE = 3,      // partial sums of the current state, store nothing
   WHAT_PROFILE = 4,      // per-row sums of the current state (velocity, stress parts), store nothing
-  WHAT_STRESS = 5        // write the site pressure tensor of the current state, store nothing
+  WHAT_STRESS = 5,       // write the site pressure tensor of the current state, store nothing
+  WHAT_STEP_ACCUM = 6    // step, adding wall stress and health counts to per-workgroup FP64 running sums
 };
+
+// Running sums of WHAT_STEP_ACCUM, per workgroup row.
+enum AccSlot { ACC_WBOT = 0, ACC_WTOP, ACC_BAD, ACC_N };
 
 // Per-row sums written by a WHAT_PROFILE launch, per 64-column block of a row:
 //   PROF_U   sum of the half-force velocity u_x
@@ -58,6 +61,7 @@ struct StepArgs {
   double *prof;               // profile: [ncb][ly][PROF_N]
   int stream_stores;          // both population buffers exceed the Infinity Cache: non-temporal stores
   void *out_sigma;            // stress: [3][ly][lx] (xx, xy, yy)
+  double *accrows;            // WHAT_STEP_ACCUM: [gridDim.x][ACC_N] running sums
 };
 
 // Batched launches: one tile of one instance.
@@ -79,6 +83,7 @@ struct BatchArgs {
   void *out_rho, *out_u; // WHAT_MOMENTS (the launch then covers one instance)
   int out_f32;
   int stream_stores;     // non-temporal population stores (see StepArgs)
+  double *accrows;       // WHAT_STEP_ACCUM: [tiles][ACC_N] running sums, row TileDesc::part
 };
 
 // Second reduction pass of one batch instance: partial rows [p0, p0 + n).
@@ -138,6 +143,12 @@ hipError_t launch_checkpoint(int mode, int walls, const LayoutArgs &a, hipStream
 hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t st);
 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+// acc[0..1] += (column sums of rows' wall stress) * inv_lx, acc[2] += count, acc[3] += bad;
+// rows are cleared.
+hipError_t launch_flush(double *rows, int nrows, double *acc, double count, double inv_lx, hipStream_t st);
+// The same per batch instance: rows of job i into acc[4 i ..].
+hipError_t launch_batch_flush(double *rows, const ReduceJob *jobs, int njobs, double *acc, double count,
+                              hipStream_t st);
 
 // Profile second pass: out[0..ly) = ubar, out[ly..2ly] = sigma (see lb_profile).  wb0, wt0:
 // sum_s rho_w,s U / 3 of the bottom and top wall; rows: scratch of ly * PROF_N doubles.

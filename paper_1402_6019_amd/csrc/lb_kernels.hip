@@ -336,8 +336,12 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   using S = typename C::S;
   using L = typename C::L;
   using V = Vec<R, NS>;
-  constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_REDUCE);
-  constexpr bool REDUCE = (WHAT == WHAT_STEP_REDUCE || WHAT == WHAT_OBSERVE);
+  constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_ACCUM);
+  constexpr bool REDUCE = (WHAT == WHAT_OBSERVE || WHAT == WHAT_STEP_ACCUM);
+  // WHAT_STEP_ACCUM keeps only what stepping averages (wall stress) and the health count,
+  // added to this workgroup's own row of running sums; the second pass runs when the host
+  // reads them, not every step
+  constexpr bool ACCUM = (WHAT == WHAT_STEP_ACCUM);
   constexpr bool PROFILE = (WHAT == WHAT_PROFILE);
 
   const int TX = blockDim.x;
@@ -866,7 +870,15 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       store_row(std::integral_constant<int, STP>{});
     }
 
-    if (REDUCE && col_ok) {
+    if (ACCUM && col_ok) {
+      bool bad = !(rho[0] > R(0) && rho[0] < R(INFINITY));
+#pragma unroll
+      for (int s = 1; s < NS; ++s) bad = bad || !(rho[s] > R(0) && rho[s] < R(INFINITY));
+      acc[RED_WBOT] += wb;
+      acc[RED_WTOP] += wt;
+      acc[RED_BAD] += bad ? 1.0 : 0.0;
+    }
+    if (REDUCE && !ACCUM && col_ok) {
       R sr = rho[0], mx = jx[0] + R(0.5) * Fx[0];
       bool bad = !(rho[0] > R(0) && rho[0] < R(INFINITY));
 #pragma unroll
@@ -908,7 +920,22 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     }
   }
 
-  if (REDUCE) {
+  if (ACCUM) {
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int slot[ACC_N] = {RED_WBOT, RED_WTOP, RED_BAD};
+#pragma unroll
+    for (int k = 0; k < ACC_N; ++k) {
+      const double v = wave_sum(acc[slot[k]]);
+      if (lane == 0) red_lds[wv][k] = v;
+    }
+    __syncthreads();
+    if (tid < ACC_N) {
+      double v = 0.0;
+      const int nw = (TX + 63) >> 6;
+      for (int i = 0; i < nw; ++i) v += red_lds[i][tid];
+      part[tid] += v;  // this workgroup's running sums (ACC_N per row)
+    }
+  } else if (REDUCE) {
     const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
     for (int k = 0; k < RED_N; ++k) {
@@ -932,8 +959,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   const int nstrip = (int)gridDim.x / a.nseg;
   const int seg = logical / nstrip;
   const int strip = logical - seg * nstrip;
-  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, a.partials + (size_t)blockIdx.x * RED_N,
-                                       a.out_rho, a.out_u, a.out_f32);
+  double *const part = WHAT == WHAT_STEP_ACCUM ? a.accrows + (size_t)blockIdx.x * ACC_N
+                                               : a.partials + (size_t)blockIdx.x * RED_N;
+  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, part, a.out_rho, a.out_u, a.out_f32);
 }
 
 // Many independent lattices in one persistent launch.  The host lists every tile of every
@@ -952,8 +980,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
     const int ti = (int)__builtin_amdgcn_readfirstlane((uint32_t)(b.tile0 + t));
     const TileDesc td = b.tiles[ti];
     const StepArgs &a = b.inst[td.inst];
-    run_tile<MODE, NS, WALLS, WHAT, STP>(a, b.src + a.offset, b.dst + a.offset, td.strip, td.seg,
-                                    b.partials + (size_t)td.part * RED_N, b.out_rho, b.out_u, b.out_f32);
+    double *const part = WHAT == WHAT_STEP_ACCUM ? b.accrows + (size_t)td.part * ACC_N
+                                                 : b.partials + (size_t)td.part * RED_N;
+    run_tile<MODE, NS, WALLS, WHAT, STP>(a, b.src + a.offset, b.dst + a.offset, td.strip, td.seg, part, b.out_rho,
+                                         b.out_u, b.out_f32);
   }
 }
 
@@ -998,6 +1028,49 @@ __device__ __forceinline__ void reduce_block(const double *partials, int nblocks
 __global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int nblocks, double *totals, double *acc,
                                                      int accumulate, double inv_lx) {
   reduce_block(partials, nblocks, totals, acc, accumulate, inv_lx);
+}
+
+// Second pass of the stepping sums: rows [nrows][ACC_N] of running sums (one per workgroup of
+// the reducing launches since the last flush) are summed in fixed order into acc (wall stress
+// sums per unit length, reduced-step count, bad-site count) and cleared.  One workgroup.
+__device__ __forceinline__ void flush_block(double *rows, int nrows, double *acc, double count, double inv_lx) {
+  __shared__ double sm[256][ACC_N];
+  const int tid = threadIdx.x;
+  double v[ACC_N] = {0.0, 0.0, 0.0};
+  for (int b = tid; b < nrows; b += 256) {
+#pragma unroll
+    for (int k = 0; k < ACC_N; ++k) {
+      v[k] += rows[(size_t)b * ACC_N + k];
+      rows[(size_t)b * ACC_N + k] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < ACC_N; ++k) sm[tid][k] = v[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h)
+#pragma unroll
+      for (int k = 0; k < ACC_N; ++k) sm[tid][k] += sm[tid + h][k];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    acc[0] += sm[0][0] * inv_lx;
+    acc[1] += sm[0][1] * inv_lx;
+    acc[2] += count;
+    acc[3] += sm[0][2];
+  }
+}
+
+__global__ __launch_bounds__(256) void flush_kernel(double *rows, int nrows, double *acc, double count,
+                                                    double inv_lx) {
+  flush_block(rows, nrows, acc, count, inv_lx);
+}
+
+// The same for a batch, one workgroup per instance (its tiles' rows are a contiguous range).
+__global__ __launch_bounds__(256) void batch_flush_kernel(double *rows, const ReduceJob *jobs, double *acc,
+                                                          double count) {
+  const ReduceJob j = jobs[blockIdx.x];
+  flush_block(rows + (size_t)j.p0 * ACC_N, j.n, acc + (size_t)blockIdx.x * 4, count, j.inv_lx);
 }
 
 // One workgroup per instance of a batch: its tiles' partials are a contiguous range.
@@ -1122,12 +1195,12 @@ static hipError_t launch_step_t(int what, int tx, int nb, const StepArgs &a, hip
       else
         hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(nb), dim3(tx), lds, st, a);
       break;
-    case WHAT_STEP_REDUCE:
+    case WHAT_STEP_ACCUM:
       if (a.stream_stores)
-        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE, kStoreStreaming>), dim3(nb), dim3(tx), lds,
+        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_ACCUM, kStoreStreaming>), dim3(nb), dim3(tx), lds,
                            st, a);
       else
-        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(nb), dim3(tx), lds, st, a);
+        hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_ACCUM>), dim3(nb), dim3(tx), lds, st, a);
       break;
     case WHAT_MOMENTS:
       hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_MOMENTS>), dim3(nb), dim3(tx), lds, st, a);
@@ -1163,12 +1236,12 @@ static hipError_t launch_batch_t(int what, int tx, int grid, const BatchArgs &b,
       else
         hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP>), dim3(grid), dim3(tx), lds, st, b);
       break;
-    case WHAT_STEP_REDUCE:
+    case WHAT_STEP_ACCUM:
       if (b.stream_stores)
-        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE, kStoreStreaming>), dim3(grid), dim3(tx),
+        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_ACCUM, kStoreStreaming>), dim3(grid), dim3(tx),
                            lds, st, b);
       else
-        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_REDUCE>), dim3(grid), dim3(tx), lds, st, b);
+        hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STEP_ACCUM>), dim3(grid), dim3(tx), lds, st, b);
       break;
     case WHAT_MOMENTS:
       hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_MOMENTS>), dim3(grid), dim3(tx), lds, st, b);
@@ -1334,6 +1407,18 @@ hipError_t launch_profile_stats(const double *samples, long long n, int ly, int 
                                 double u_top, double *out, hipStream_t st) {
   hipLaunchKernelGGL(profile_stats_kernel, dim3((ly + 1 + 255) / 256), dim3(256), 0, st, samples, n, ly, walls, k0,
                      u_bot, u_top, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(double *rows, int nrows, double *acc, double count, double inv_lx, hipStream_t st) {
+  hipLaunchKernelGGL(flush_kernel, dim3(1), dim3(256), 0, st, rows, nrows, acc, count, inv_lx);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_flush(double *rows, const ReduceJob *jobs, int njobs, double *acc, double count,
+                              hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_flush_kernel, dim3(njobs), dim3(256), 0, st, rows, jobs, acc, count);
   return hipGetLastError();
 }
 
