@@ -45,6 +45,20 @@ def disc(lx, ly, radius, rho_in, rho_out, cx=None, cy=None):
     return np.where(inside, float(rho_in), float(rho_out))
 
 
+def facing_bubbles(lx, ly, radius, gap, rho_in=0.28, rho_out=1.39, width=1.5):
+    """Two half-discs of the gas phase (rho_in) in the liquid (rho_out), their flat faces
+    facing each other across a liquid gap of `gap` sites at the lattice centre (the thin-film
+    setup: two bubbles pressed against each other with a film between them).  The bubble
+    centres of curvature are at (lx/2 -+ gap/2, ly/2); the profile is a tanh of the signed
+    distance to the nearer half-disc, of width `width`.  Shape [ly, lx]."""
+    y, x = np.mgrid[0:ly, 0:lx] + 0.5
+    xl, xr, cy = lx / 2.0 - gap / 2.0, lx / 2.0 + gap / 2.0, ly / 2.0
+    dl = np.maximum(np.hypot(x - xl, y - cy) - radius, x - xl)
+    dr = np.maximum(np.hypot(x - xr, y - cy) - radius, xr - x)
+    d = np.minimum(dl, dr)
+    return rho_in + (rho_out - rho_in) * 0.5 * (1.0 + np.tanh(d / width))
+
+
 def _expected_area(rmin, rmax):
     er2 = (rmax ** 3 - rmin ** 3) / (3.0 * (rmax - rmin))
     return math.pi * er2

@@ -674,6 +674,40 @@ def test_cooperative_length_prediction_shape():
 
 
 # ----------------------------------------------------------------------------------------
+# Two bubbles pressed together: the thin film between them (disjoining-pressure section)
+# ----------------------------------------------------------------------------------------
+
+def _film_case(g1, g2, radius=16, gap=6, steps=10000):
+    lx, ly = 2 * radius + 60, 2 * radius + 40
+    P = Params(lx=lx, ly=ly, ns=1, g1=(g1, 0.0), g2=(g2, 0.0))
+    o = Oracle(P, rho_init=lbgen.facing_bubbles(lx, ly, radius, gap)[None])
+    o.step(steps)
+    rho = o.fields()["rho"][0]
+    sxx, _, syy = dg.stress_field(o)
+    yc, xf, xb = ly // 2, lx // 2, int(lx / 2 - gap / 2 - radius / 2)
+    p = 0.5 * (sxx + syy)
+    return dict(rho_film=rho[yc, xf], rho_bubble=rho[yc, xb], rho_outer=rho[2, 2],
+                pi_cap=p[yc, xb] - p[2, 2], line=rho[yc])
+
+
+def test_frustrated_film_resists_coalescence():
+    """The disjoining-pressure section's film: with the frustrated couplings G1 = -20.4,
+    G2 = 16 the liquid film between two bubbles pressed together survives (a positive
+    disjoining pressure balances the capillary pressure, which is positive); with a plain
+    attraction of the same G1 + G2 (same bulk equation of state, (BULK)) it ruptures and the
+    bubbles merge."""
+    fr = _film_case(lbgen.FILM_G1, lbgen.FILM_G2)
+    mid = 0.5 * (fr["rho_bubble"] + fr["rho_outer"])
+    assert fr["rho_film"] > mid and fr["rho_film"] > 1.3
+    assert fr["pi_cap"] > 0
+    assert fr["rho_bubble"] < 0.3 < 1.3 < fr["rho_outer"]
+    plain = _film_case(lbgen.FILM_G1 + lbgen.FILM_G2, 0.0)
+    assert plain["rho_film"] < 0.5 * (plain["rho_bubble"] + plain["rho_outer"])
+    # the liquid outside is near the same bulk density, fixed by G1 + G2 through (BULK)
+    assert abs(plain["rho_outer"] - fr["rho_outer"]) < 0.03
+
+
+# ----------------------------------------------------------------------------------------
 # Emulsion couplings: coexistence and two-component mechanical balance
 # ----------------------------------------------------------------------------------------
 
