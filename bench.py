@@ -247,6 +247,32 @@ def couette_cell(steps, sample_every=100):
             "mean_wall_stress": [float(sig[0]), float(-sig[-1])]}
 
 
+def film_sweep(radii=(16, 24, 32, 48, 64), steps=30000):
+    """Disjoining pressure of the thin film between two gas bubbles pressed together
+    (single component, G1 = -20.4, G2 = 16, FP64): for each bubble radius, the film thickness
+    h on the axis and the capillary pressure between the bubble and outer bulk, which equals
+    the film's disjoining pressure at equilibrium; `steps` graph-replayed steps per radius."""
+    import torch
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    from paper_1402_6019_amd.film import film_observables
+    gap = 6
+    rows = []
+    t0 = time.perf_counter()
+    for R in radii:
+        lx, ly = 2 * R + 60, 2 * R + 40
+        sim = Sim(lx, ly, lbgen.facing_bubbles(lx, ly, R, gap)[None], n_species=1, storage="f64",
+                  g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0))
+        sim.set_graph(1000)
+        sim.step(steps)
+        o = film_observables(sim, ly // 2, lx // 2, int(lx / 2 - gap / 2 - R / 2), (2, 2))
+        torch.cuda.synchronize()
+        rows.append({"radius": R, "h": o["h"], "pi": o["pi_capillary"], "pn_film": o["pn_film"]})
+        sim.close()
+    return {"workload": f"two facing half-disc bubbles, gap {gap}, G1 = -20.4, G2 = 16, FP64, {steps} steps each",
+            "points": rows, "seconds": time.perf_counter() - t0}
+
+
 def adjoint_channel(T=4000, prerelax=2000, check_fd=True):
     """Gradient of L = <(W_bot + W_top)/2> + <Q> over T steps with respect to (G1, G2, G_AB,
     g_x) on a 512 x 256 confined emulsion channel (G1, G2 shared by both species), after an
@@ -521,6 +547,7 @@ def main():
         "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
         "couette_cell": None if args.core else couette_cell(max(200, args.steps // 2)),
         "auxiliary_passes": None if args.core else auxiliary_passes(rho, kw),
+        "film_sweep": None if args.core else film_sweep(),
         "adjoint": None if args.core else adjoint_channel(check_fd=not args.no_cpu),
         "kernel_source_hash": khash,
     }
