@@ -367,7 +367,7 @@ int adj_blocks(int lx, int ly) { return ((lx + 255) / 256) * ly; }
 template <typename R, int NS, bool WALLS>
 static hipError_t adj_step_t(const AdjArgs &a, hipStream_t st) {
   const dim3 grid((a.lx + 255) / 256, a.ly), block(256);
-  hipLaunchKernelGGL((adj_fields_kernel<R, NS>), grid, block, 0, st, a);
+  if (!a.fields_ready) hipLaunchKernelGGL((adj_fields_kernel<R, NS>), grid, block, 0, st, a);
   hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS>), grid, block, 0, st, a);
   hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), grid, block, 0, st, a);
   return hipGetLastError();

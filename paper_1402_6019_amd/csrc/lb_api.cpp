@@ -106,8 +106,9 @@ hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st) {
   return launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
 }
 
-// Canonical FP64 pre-collision populations of buffer `from` into dst, on stream st.
-hipError_t launch_checkpoint_from(const lb_ctx *c, int from, void *dst, hipStream_t st) {
+// Canonical FP64 pre-collision populations of buffer `from` into dst, and the reverse step's
+// fields of that state (rho, psi, j per species; FP64 if fp64) into fields, on stream st.
+hipError_t launch_checkpoint_fields_from(const lb_ctx *c, int from, void *dst, void *fields, int fp64, hipStream_t st) {
   LayoutArgs la{};
   la.in = c->pop[from];
   la.out = dst;
@@ -118,7 +119,10 @@ hipError_t launch_checkpoint_from(const lb_ctx *c, int from, void *dst, hipStrea
   la.ns = c->lat.n_species;
   la.rho_ref[0] = c->psi.rho_ref[0];
   la.rho_ref[1] = c->psi.rho_ref[1];
-  return launch_checkpoint(c->lat.storage, c->lat.walls, la, st);
+  la.fields = fields;
+  la.psi0 = c->psi.psi0;
+  la.irho0 = 1.0 / c->psi.rho0;
+  return launch_checkpoint_fields(c->lat.storage, c->lat.walls, fp64, la, st);
 }
 
 // Fold the running sums of the reducing steps since the last flush into d_acc.
@@ -614,7 +618,7 @@ namespace {
 
 struct AdjLayout {
   int every = 1, ncp = 1;
-  size_t s64 = 0, lamb = 0, nsite = 0;
+  size_t s64 = 0, lamb = 0, nsite = 0, fb = 0;
   size_t ckpt = 0, seg = 0, fin = 0, lam0 = 0, lam1 = 0, lampart = 0, fields = 0, fbar = 0, partials = 0, acc = 0;
   size_t total = 0;
 };
@@ -640,7 +644,8 @@ AdjLayout adjoint_layout(const lb_ctx *c, int64_t T, int32_t every, int32_t flag
   L.lam0 = o; o += L.lamb;
   L.lam1 = o; o += L.lamb;
   L.lampart = o; o += L.lamb;
-  L.fields = o; o += align256(8 * L.nsite * rs);
+  L.fb = align256(8 * L.nsite * rs);
+  L.fields = o; o += (size_t)L.every * L.fb;  // one set per state of a segment
   L.fbar = o; o += align256(8 * L.nsite * rs);
   L.partials = o; o += align256((size_t)adj_blocks(c->lat.lx, c->lat.ly) * ADJ_N * 8);
   L.acc = o; o += align256(ADJ_N * 8);
@@ -725,7 +730,7 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   // reverse sweep, one checkpoint segment at a time
   AdjArgs a = adjoint_args(c, loss_weights[0], loss_weights[1], T);
   a.lampart = ws + L.lampart;
-  a.fields = ws + L.fields;
+  a.fields_ready = 1;
   a.fbar = ws + L.fbar;
   a.partials = reinterpret_cast<double *>(ws + L.partials);
   double *acc = reinterpret_cast<double *>(ws + L.acc);
@@ -738,7 +743,8 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   auto recompute = [&](int from, int len, hipStream_t st) -> hipError_t {
     hipError_t er = hipSuccess;
     for (int jj = 0; jj < len && er == hipSuccess; ++jj) {
-      er = launch_checkpoint_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.s64, st);
+      er = launch_checkpoint_fields_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.s64,
+                                         ws + L.fields + (size_t)jj * L.fb, fp64, st);
       if (er == hipSuccess && jj + 1 < len) er = launch_plain_step(c, from ^ (jj & 1), st);
     }
     return er;
@@ -748,6 +754,7 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
     int qq = q0;
     for (int jj = len - 1; jj >= 0 && er == hipSuccess; --jj) {
       a.x = reinterpret_cast<const double *>(ws + L.seg + (size_t)jj * L.s64);
+      a.fields = ws + L.fields + (size_t)jj * L.fb;
       a.lam_next = lam_buf[qq];
       a.lam = lam_buf[qq ^ 1];
       er = launch_adjoint_step(fp64, c->lat.n_species, c->lat.walls, a, st);

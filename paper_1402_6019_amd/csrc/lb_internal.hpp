@@ -99,6 +99,10 @@ struct LayoutArgs {
   long long plane;
   int lx, ly, pitch, ns;
   double rho_ref[2];
+  // checkpoint with fields (adjoint recompute): rho, psi, jx, jy of each species of the
+  // canonical state, [4][2][ly][lx] in the adjoint's precision
+  void *fields;
+  double psi0, irho0;
 };
 
 // Reverse step of the adjoint (lb_adjoint.hip).  Arrays are canonical [..][y][x]; R is
@@ -121,6 +125,7 @@ struct AdjArgs {
   double rho_w[2], psi_w[2];
   double cW, cQ;         // per-step loss weights
   double u_wall[2];      // x-velocity of the bottom and top wall
+  int fields_ready;      // fields already hold rho, psi, j of x (written with the checkpoint)
 };
 
 // Per-block partial sums of the adjoint: parameter sensitivities and the loss.
@@ -140,6 +145,8 @@ hipError_t launch_reduce(const double *partials, int nblocks, double *totals, do
                          double inv_lx, hipStream_t st);
 hipError_t launch_init(int mode, int walls, const LayoutArgs &a, hipStream_t st);
 hipError_t launch_checkpoint(int mode, int walls, const LayoutArgs &a, hipStream_t st);
+// The same, also writing the fields rho, psi, jx, jy (FP64 if fp64, else FP32) to a.fields.
+hipError_t launch_checkpoint_fields(int mode, int walls, int fp64, const LayoutArgs &a, hipStream_t st);
 hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t st);
 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);

@@ -1176,6 +1176,50 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
     }
 }
 
+// Checkpoint of the adjoint's recompute: the canonical state as checkpoint_kernel writes it,
+// and from the same values the moments and pseudopotential the reverse step needs
+// (rho_s = sum_l f_l, psi_s = psi0 (1 - exp(-rho_s / rho0)), j_s = sum_l c_l f_l), summed in
+// l order in the adjoint's precision RA.
+template <int MODE, bool WALLS, typename RA>
+__global__ void checkpoint_fields_kernel(LayoutArgs a) {
+  using C = Codec<MODE>;
+  using S = typename C::S;
+  using R = typename C::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.lx) return;
+  const S *in = static_cast<const S *>(a.in);
+  double *f = static_cast<double *>(a.out);
+  RA *fl = static_cast<RA *>(a.fields);
+  const size_t nsite = (size_t)a.lx * a.ly;
+  const size_t i = (size_t)y * a.lx + x;
+  for (int s = 0; s < a.ns; ++s) {
+    RA r = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      int zx = x - CXS[l], zy = y - CYS[l], lsrc = l;
+      if (WALLS && (zy < 0 || zy >= a.ly)) {
+        zx = x;
+        zy = y;
+        lsrc = OPPS[l];
+      } else {
+        zx = wrapi(zx, a.lx);
+        zy = wrapi(zy, a.ly);
+      }
+      const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), R(WD2Q9[lsrc] * a.rho_ref[s]));
+      const double fv = double(v);
+      f[(size_t)(s * 9 + l) * nsite + i] = fv;
+      const RA g = RA(fv);
+      r += g;
+      jx += RA(CXS[l]) * g;
+      jy += RA(CYS[l]) * g;
+    }
+    fl[(size_t)(0 * 2 + s) * nsite + i] = r;
+    fl[(size_t)(1 * 2 + s) * nsite + i] = RA(a.psi0) * (RA(1) - exp(-r * RA(a.irho0)));
+    fl[(size_t)(2 * 2 + s) * nsite + i] = jx;
+    fl[(size_t)(3 * 2 + s) * nsite + i] = jy;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
@@ -1454,6 +1498,29 @@ hipError_t launch_reduce(const double *partials, int nblocks, double *totals, do
 LB_LAYOUT_LAUNCHER(launch_init, init_kernel)
 LB_LAYOUT_LAUNCHER(launch_restore, restore_kernel)
 LB_LAYOUT_LAUNCHER(launch_checkpoint, checkpoint_kernel)
+
+template <int MODE, typename RA>
+static hipError_t launch_checkpoint_fields_m(int walls, const LayoutArgs &a, hipStream_t st) {
+  const dim3 grid((a.lx + 127) / 128, a.ly), block(128);
+  if (walls) hipLaunchKernelGGL((checkpoint_fields_kernel<MODE, true, RA>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((checkpoint_fields_kernel<MODE, false, RA>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_checkpoint_fields(int mode, int walls, int fp64, const LayoutArgs &a, hipStream_t st) {
+  switch (mode) {
+    case MODE_F64:
+      return fp64 ? launch_checkpoint_fields_m<MODE_F64, double>(walls, a, st)
+                  : launch_checkpoint_fields_m<MODE_F64, float>(walls, a, st);
+    case MODE_F32:
+      return fp64 ? launch_checkpoint_fields_m<MODE_F32, double>(walls, a, st)
+                  : launch_checkpoint_fields_m<MODE_F32, float>(walls, a, st);
+    case MODE_BF16:
+      return fp64 ? launch_checkpoint_fields_m<MODE_BF16, double>(walls, a, st)
+                  : launch_checkpoint_fields_m<MODE_BF16, float>(walls, a, st);
+  }
+  return hipErrorInvalidValue;
+}
 
 #undef LB_LAYOUT_LAUNCHER
 
