@@ -169,6 +169,11 @@ def test_profile_stats_match_numpy():
     corr = (d * d[:, [k0]]).mean(axis=0) / (d[:, k0] ** 2).mean()
     np.testing.assert_allclose(st["corr"].cpu().numpy(), corr, rtol=1e-9, atol=1e-12)
     assert st["corr"][k0].item() == pytest.approx(1.0, rel=1e-12)
+    from paper_1402_6019_amd import LbError
+    with pytest.raises(LbError):
+        sim.profile_stats(samples, ly + 1)
+    with pytest.raises(ValueError):
+        sim.profile_stats(samples[:, :-1])
     sim.close()
 
 

@@ -41,6 +41,9 @@ def test_stress_field_matches_oracle(case, storage, tol):
     for tile in ((64, 3), (128, 13), (256, 40)):
         sim.set_tile(*tile)
         assert np.array_equal(sim.stress_field().cpu().numpy(), ref), tile
+    import torch
+    f32 = sim.stress_field(dtype=torch.float32).cpu().numpy()
+    assert np.array_equal(f32, ref.astype(np.float32))  # the same values, rounded once on output
     sim.close()
 
 
