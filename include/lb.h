@@ -134,9 +134,12 @@ int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const 
    (see lb_set_reduce_every) has already reported a bad density. */
 int lb_step(lb_ctx *ctx, int64_t n);
 
-/* Run the FP64 reductions (species mass, momentum, wall stress, flow rate, health) in the
-   epilogue of every k-th step (k = 0: never; default 0).  lb_wall_stress averages over the
-   steps that ran them.  Host call. */
+/* Every k-th step (k = 0: never; default 0) also accumulates, in its epilogue, the FP64 wall
+   momentum exchange (lb_wall_stress averages over the steps that did) and the count of
+   non-finite or non-positive densities (the health latch).  Each workgroup adds to its own row
+   of running sums; lb_step folds them once per call, in fixed order, and starts the
+   asynchronous health readback.  Masses, momentum and flow rate come from lb_totals.
+   Host call. */
 int lb_set_reduce_every(lb_ctx *ctx, int32_t k);
 
 /* Density and velocity of the current state: rho (device, [n_species][ly][lx]) and
