@@ -247,6 +247,44 @@ def couette_cell(steps, sample_every=100):
             "mean_wall_stress": [float(sig[0]), float(-sig[-1])]}
 
 
+def couette_study(u_wall=0.01, fraction=0.8, warm=200000, samples=1500, every=200):
+    """The fluidity profile of the Couette cell (emulsion section, eq. (predict)) at the
+    paper's 1040 x 1040 domain: confined emulsion (volume fraction `fraction`, seed 6), walls
+    sliding with -+u_wall, FP32, `warm` steps to forget the start, then a profile every `every`
+    steps; time-averaged velocity, stress and local fluidity, and the cooperative-length fit
+    (fluidity averaged over bins of 13 lines).  Not part of the default run."""
+    import numpy as np
+    import torch
+    import lbgen
+    from paper_1402_6019_amd import Sim, fit_cooperative_length
+    L = 1040
+    rho, info = lbgen.emulsion(L, L, fraction=fraction, seed=6, walls=True)
+    sim = Sim(L, L, rho, n_species=2, walls=True, storage="f32", g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2,
+              gab=lbgen.EMULSION_GAB, rho_wall=lbgen.EMULSION_POOR, rho0=lbgen.EMULSION_RHO0,
+              u_wall=(-u_wall, u_wall))
+    tile, _ = sim.autotune(10)
+    sim.set_graph(every)
+    t0 = time.perf_counter()
+    sim.step(warm)
+    smp = sim.sample_profiles(samples, every)
+    st = sim.profile_stats(smp)
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    u, sig, fl = (st[k].cpu().numpy() for k in ("u", "sigma", "fluidity"))
+    sim.close()
+    z = np.arange(1, L, dtype=float)
+    f = fl[1:-1]
+    nb = len(f) // 13 * 13
+    fit = fit_cooperative_length(z[:nb].reshape(-1, 13).mean(axis=1), f[:nb].reshape(-1, 13).mean(axis=1), float(L),
+                                 (1.0, 5.0 * L))
+    return {"workload": f"Couette cell {L}x{L}, confined emulsion, volume fraction {fraction}, seed 6, walls -+{u_wall}, "
+                        f"FP32, {warm} + {samples} x {every} steps", "mass_fraction": info["mass_fraction"],
+            "tile": list(tile), "seconds": seconds, "steps": warm + samples * every,
+            "mean_shear_rate": 2 * u_wall / L, "sigma_mean": float(sig.mean()), "sigma_spread": float(np.ptp(sig)),
+            "fluidity_at": {str(k): float(f[k - 1]) for k in (1, 5, 20, 50, 100, 200, 520)},
+            "apparent_fluidity": float(2 * u_wall / L / sig.mean()), "fit": fit}
+
+
 def film_sweep(radii=(16, 24, 32, 48, 64), steps=30000):
     """Disjoining pressure of the thin film between two gas bubbles pressed together
     (single component, G1 = -20.4, G2 = 16, FP64): for each bubble radius, the film thickness
@@ -486,6 +524,8 @@ def main():
     ap.add_argument("--tile", type=str, default=None, help="tx,sy launch shape")
     ap.add_argument("--core", action="store_true",
                     help="headline lattice and copy only (skip the channel, batched and adjoint legs)")
+    ap.add_argument("--couette-study", action="store_true",
+                    help="run only the Couette-cell fluidity study (half a million steps at 1040^2) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -493,6 +533,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.couette_study:
+        print(json.dumps(couette_study()), flush=True)
+        return
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
 
     rho, info, kw = workload()
