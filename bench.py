@@ -177,7 +177,7 @@ def auxiliary_passes(rho, kw, reps=200):
     from paper_1402_6019_amd import _binding as B
     out["moments_f32_ms"] = timed(lambda: sim._lib.lb_moments(sim._h, ctypes.c_void_p(rho_o.data_ptr()),
                                                                ctypes.c_void_p(u_o.data_ptr()), B.LB_OUT_F32))
-    prof = torch.empty(2 * LY + 1, dtype=torch.float64, device="cuda")
+    prof = torch.empty(4 * LY + 1, dtype=torch.float64, device="cuda")
     out["profile_ms"] = timed(lambda: sim.profile(prof))
     sig = torch.empty((3, LY, LX), dtype=torch.float32, device="cuda")
     out["stress_field_f32_ms"] = timed(lambda: sim._lib.lb_stress_field(sim._h, ctypes.c_void_p(sig.data_ptr()),
@@ -224,7 +224,7 @@ def couette_cell(steps, sample_every=100):
 
     ms_step = timed(lambda: sim.step(1), steps)
     nprof = 50
-    buf = torch.empty((nprof, 2 * ly + 1), dtype=torch.float64, device="cuda")
+    buf = torch.empty((nprof, 4 * ly + 1), dtype=torch.float64, device="cuda")
     it = iter(range(nprof))
     ms_prof = timed(lambda: sim.profile(buf[next(it)]), nprof)
     nsamp = max(2, steps // sample_every)

@@ -211,10 +211,10 @@ int lb_set_couplings(lb_ctx *ctx, const lb_couplings *cpl);
 
 /*
  * Stream-wise averaged profiles for the rheology of the confined flows (emulsion section:
- * the averaged velocity profile and stress of the pressure-driven channel and of the planar
- * Couette cell, from which the local fluidity f(z) = (du/dz) / sigma and the cooperative
- * length of eq. (fluidity) / eq. (predict) follow; and the stress correlator of eq.
- * (correlator)).
+ * the averaged velocity and density profiles and stress of the pressure-driven channel and of
+ * the planar Couette cell, from which the local fluidity f(z) = (du/dz) / sigma and the
+ * cooperative length of eq. (fluidity) / eq. (predict) follow; and the stress correlator of
+ * eq. (correlator)).
  *
  * lb_profile writes, for the current state at time t, out[0 .. ly-1] = ubar(y), the x-average
  * of the velocity u_x of lb_moments in row y, and out[ly .. 2 ly] = sigma(k), k = 0..ly, the
@@ -225,15 +225,17 @@ int lb_set_couplings(lb_ctx *ctx, const lb_couplings *cpl);
  * sigma(0) = W_bot(t) and sigma(ly) = -W_top(t) on channel lattices (the walls' momentum
  * exchange of lb_wall_stress); on periodic lattices sigma(ly) = sigma(0).  Exact lattice
  * momentum balance: the x-momentum of the rows between lines k1 < k2 changes in step t by
- * lx (sigma(k2) - sigma(k1)) + g_x times their mass.  out: device, 2 ly + 1 doubles.
+ * lx (sigma(k2) - sigma(k1)) + g_x times their mass.  out[2 ly + 1 .. 3 ly] and
+ * out[3 ly + 1 .. 4 ly] are the x-averaged densities of species A and B in row y (B zero for
+ * one component).  out: device, 4 ly + 1 doubles.
  * One read of the state (a step without the store) plus a small second pass; the state
  * is not changed.  Asynchronous.
  */
 int lb_profile(lb_ctx *ctx, double *out);
 
 /*
- * Time statistics of n >= 1 profiles samples (device, [n][2 ly + 1], as written by
- * lb_profile), written to out (device, 4 ly + 3 doubles):
+ * Time statistics of n >= 1 profile samples (device, [n][4 ly + 1], as written by
+ * lb_profile), written to out (device, 6 ly + 3 doubles):
  *   out[0 .. ly-1]             <ubar(y)>
  *   out[ly .. 2ly]             <sigma(k)>, k = 0..ly
  *   out[2ly+1 .. 3ly+1]        <f(k)>, the time average of the local fluidity
@@ -243,6 +245,8 @@ int lb_profile(lb_ctx *ctx, double *out);
  *   out[3ly+2 .. 4ly+2]        C_sigma(k, k0) of eq. (correlator): the covariance of sigma(k) and
  *                              sigma(k0) over the samples divided by the variance of sigma(k0)
  *                              (NaN if that variance is 0)
+ *   out[4ly+3 .. 5ly+2]        <rho_A(y)>
+ *   out[5ly+3 .. 6ly+2]        <rho_B(y)>
  * with 0 <= k0 <= ly.  Sums run over the samples in order, in FP64.  Asynchronous.
  */
 int lb_profile_stats(lb_ctx *ctx, const double *samples, int64_t n, int32_t k0, double *out);

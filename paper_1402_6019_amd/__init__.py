@@ -212,42 +212,42 @@ class Sim:
         return out
 
     def profile(self, out=None):
-        """Stream-wise averaged profiles of the current state (device FP64 tensor of 2 ly + 1):
-        [0:ly] the x-averaged velocity ubar(y), [ly:] the shear stress sigma(k) through the
-        lines k = 0..ly between rows k-1 and k (sigma(0) = W_bot, sigma(ly) = -W_top on a
-        channel)."""
+        """Stream-wise averaged profiles of the current state (device FP64 tensor of 4 ly + 1):
+        [0:ly] the x-averaged velocity ubar(y), [ly:2ly+1] the shear stress sigma(k) through
+        the lines k = 0..ly between rows k-1 and k (sigma(0) = W_bot, sigma(ly) = -W_top on a
+        channel), [2ly+1:3ly+1] and [3ly+1:] the x-averaged densities of species A and B."""
         torch = self.torch
         if out is None:
-            out = torch.empty(2 * self.ly + 1, dtype=torch.float64, device=self.device)
-        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != 2 * self.ly + 1:
-            raise ValueError("out must be a contiguous float64 tensor of 2 ly + 1 elements")
+            out = torch.empty(4 * self.ly + 1, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != 4 * self.ly + 1:
+            raise ValueError("out must be a contiguous float64 tensor of 4 ly + 1 elements")
         self._chk(self._lib.lb_profile(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
 
     def sample_profiles(self, n, every):
-        """n profiles, one after every `every` steps (advances n * every steps): [n, 2 ly + 1]."""
+        """n profiles, one after every `every` steps (advances n * every steps): [n, 4 ly + 1]."""
         torch = self.torch
-        out = torch.empty((int(n), 2 * self.ly + 1), dtype=torch.float64, device=self.device)
+        out = torch.empty((int(n), 4 * self.ly + 1), dtype=torch.float64, device=self.device)
         for i in range(int(n)):
             self.step(every)
             self.profile(out[i])
         return out
 
     def profile_stats(self, samples, k0=None):
-        """Time statistics of profile samples [n, 2 ly + 1]: dict of <ubar> [ly], <sigma> [ly+1],
-        the time-averaged local fluidity <f> [ly+1] and the stress correlator C_sigma(k, k0)
-        [ly+1] (k0 default: the centre line)."""
+        """Time statistics of profile samples [n, 4 ly + 1]: dict of <ubar> [ly], <sigma> [ly+1],
+        the time-averaged local fluidity <f> [ly+1], the stress correlator C_sigma(k, k0)
+        [ly+1] (k0 default: the centre line) and the species densities <rho_A>, <rho_B> [ly]."""
         torch = self.torch
         ly = self.ly
         samples = samples.to(dtype=torch.float64, device=self.device).contiguous()
-        if samples.dim() != 2 or samples.shape[1] != 2 * ly + 1:
-            raise ValueError("samples must have shape (n, 2 ly + 1)")
+        if samples.dim() != 2 or samples.shape[1] != 4 * ly + 1:
+            raise ValueError("samples must have shape (n, 4 ly + 1)")
         k0 = ly // 2 if k0 is None else int(k0)
-        out = torch.empty(4 * ly + 3, dtype=torch.float64, device=self.device)
+        out = torch.empty(6 * ly + 3, dtype=torch.float64, device=self.device)
         self._chk(self._lib.lb_profile_stats(self._h, ctypes.c_void_p(samples.data_ptr()), samples.shape[0], k0,
                                              ctypes.c_void_p(out.data_ptr())))
         return dict(u=out[:ly], sigma=out[ly:2 * ly + 1], fluidity=out[2 * ly + 1:3 * ly + 2],
-                    corr=out[3 * ly + 2:])
+                    corr=out[3 * ly + 2:4 * ly + 3], rho_a=out[4 * ly + 3:5 * ly + 3], rho_b=out[5 * ly + 3:])
 
     def checkpoint(self):
         """Canonical FP64 pre-collision populations f[ns, 9, ly, lx] (device tensor)."""

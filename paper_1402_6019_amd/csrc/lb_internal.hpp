@@ -28,7 +28,8 @@ enum AccSlot { ACC_WBOT = 0, ACC_WTOP, ACC_BAD, ACC_N };
 //   PROF_KDN sum_s (f*_8 - f*_7): x-momentum the populations with c_y = -1 carry down
 //   PROF_I1  x-force on the row's sites from partners at c_y >= 1 (pairs crossing line y + 1/2)
 //   PROF_I2  the part of PROF_I1 from partners at c_y = 2 (pairs also crossing line y + 3/2)
-enum ProfSlot { PROF_U = 0, PROF_KUP, PROF_KDN, PROF_I1, PROF_I2, PROF_N };
+//   PROF_RA, PROF_RB  sums of the species densities (B zero for one component)
+enum ProfSlot { PROF_U = 0, PROF_KUP, PROF_KDN, PROF_I1, PROF_I2, PROF_RA, PROF_RB, PROF_N };
 
 // Partial-sum slots written per workgroup (and totals after the second pass).
 enum RedSlot {
@@ -157,7 +158,8 @@ hipError_t launch_flush(double *rows, int nrows, double *acc, double count, doub
 hipError_t launch_batch_flush(double *rows, const ReduceJob *jobs, int njobs, double *acc, double count,
                               hipStream_t st);
 
-// Profile second pass: out[0..ly) = ubar, out[ly..2ly] = sigma (see lb_profile).  wb0, wt0:
+// Profile second pass: out[0..ly) = ubar, out[ly..2ly] = sigma, out[2ly+1..4ly+1) = the
+// species densities per row (see lb_profile).  wb0, wt0:
 // sum_s rho_w,s U / 3 of the bottom and top wall; rows: scratch of ly * PROF_N doubles.
 hipError_t launch_profile_finish(const double *prof, int ncb, int lx, int ly, int walls, double wb0, double wt0,
                                  double *rows, double *out, hipStream_t st);

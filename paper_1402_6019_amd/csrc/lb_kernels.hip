@@ -828,7 +828,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
         sr += rho[s];
         mx += jx[s] + R(0.5) * Fx[s];
       }
-      double pv[PROF_N] = {double(mx / sr), kup, kdn, i1, i2};
+      double pv[PROF_N] = {double(mx / sr), kup, kdn, i1, i2, double(rho[0]), NS == 2 ? double(rho[NS - 1]) : 0.0};
       const int lane = tid & 63, wv = tid >> 6;
       double *row = a.prof + ((size_t)(strip * (TX >> 6) + wv) * ly + y) * PROF_N;
 #pragma unroll
@@ -1382,7 +1382,11 @@ __global__ void profile_finish_kernel(const double *rows, int lx, int ly, int wa
   if (k > ly) return;
   auto row = [&](int y, int slot) { return rows[(size_t)y * PROF_N + slot]; };
   const double ilx = 1.0 / lx;
-  if (k < ly) out[k] = row(k, PROF_U) * ilx;
+  if (k < ly) {
+    out[k] = row(k, PROF_U) * ilx;
+    out[2 * ly + 1 + k] = row(k, PROF_RA) * ilx;
+    out[3 * ly + 1 + k] = row(k, PROF_RB) * ilx;
+  }
   double sig;
   if (walls && k == 0) {
     sig = 2.0 * row(0, PROF_KDN) * ilx - wb0;
@@ -1405,13 +1409,17 @@ __global__ void profile_stats_kernel(const double *smp, long long n, int ly, int
                                      double u_top, double *out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > ly) return;
-  const size_t len = 2 * (size_t)ly + 1;
+  const size_t len = 4 * (size_t)ly + 1;
   const double in = 1.0 / (double)n;
-  double su = 0.0, ss = 0.0, sf = 0.0, s0 = 0.0;
+  double su = 0.0, ss = 0.0, sf = 0.0, s0 = 0.0, sa = 0.0, sb = 0.0;
   for (long long t = 0; t < n; ++t) {
     const double *p = smp + (size_t)t * len;
     const double sig = p[ly + k];
-    if (k < ly) su += p[k];
+    if (k < ly) {
+      su += p[k];
+      sa += p[2 * ly + 1 + k];
+      sb += p[3 * ly + 1 + k];
+    }
     ss += sig;
     s0 += p[ly + k0];
     double du;
@@ -1431,7 +1439,11 @@ __global__ void profile_stats_kernel(const double *smp, long long n, int ly, int
     c00 += d0 * d0;
     ck0 += (p[ly + k] - mk) * d0;
   }
-  if (k < ly) out[k] = su * in;
+  if (k < ly) {
+    out[k] = su * in;
+    out[4 * ly + 3 + k] = sa * in;
+    out[5 * ly + 3 + k] = sb * in;
+  }
   out[ly + k] = mk;
   out[2 * ly + 1 + k] = sf * in;
   out[3 * ly + 2 + k] = c00 > 0.0 ? ck0 / c00 : NAN;

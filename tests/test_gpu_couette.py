@@ -82,7 +82,9 @@ def test_couette_closed_form_on_gpu():
     sim.set_graph(1000)
     sim.step(20000)
     prof = sim.profile().cpu().numpy()
-    ubar, sigma = prof[:ly], prof[ly:]
+    ubar, sigma = prof[:ly], prof[ly:2 * ly + 1]
+    np.testing.assert_allclose(prof[2 * ly + 1:3 * ly + 1], 1.0, rtol=1e-12)  # uniform density
+    assert np.all(prof[3 * ly + 1:] == 0.0)  # one component
     S = (ut - ub) / ly
     nu = (tau - 0.5) / 3
     y = np.arange(ly)
@@ -110,10 +112,13 @@ def test_profile_matches_oracle(storage, walls):
         prof = sim.profile().cpu().numpy()
         ubar, sigma = dg.shear_profile(orc)
         e_u = np.abs(prof[:c["ly"]] - ubar).max() / max(np.abs(ubar).max(), 1e-3)
-        e_s = np.abs(prof[c["ly"]:] - sigma).max() / np.abs(sigma).max()
-        print(f"{storage} walls={walls} t={t}: ubar {e_u:.2e} sigma {e_s:.2e} (max |sigma| {np.abs(sigma).max():.3e})",
-              flush=True)
-        assert e_u <= tol and e_s <= tol
+        ly = c["ly"]
+        e_s = np.abs(prof[ly:2 * ly + 1] - sigma).max() / np.abs(sigma).max()
+        rho_rows = orc.fields()["rho"].mean(axis=2)  # [ns, ly]
+        e_r = np.abs(prof[2 * ly + 1:].reshape(2, ly) - rho_rows).max() / np.abs(rho_rows).max()
+        print(f"{storage} walls={walls} t={t}: ubar {e_u:.2e} sigma {e_s:.2e} rho rows {e_r:.2e} "
+              f"(max |sigma| {np.abs(sigma).max():.3e})", flush=True)
+        assert e_u <= tol and e_s <= tol and e_r <= tol
     ref = sim.profile().cpu().numpy()
     for tile in ((64, 3), (128, 11), (256, 40)):
         sim.set_tile(*tile)
@@ -140,7 +145,7 @@ def test_profile_momentum_budget_on_gpu():
 
     for _ in range(3):
         p0, m0 = rows()
-        sigma = sim.profile().cpu().numpy()[c["ly"]:]
+        sigma = sim.profile().cpu().numpy()[c["ly"]:2 * c["ly"] + 1]
         sim.step(1)
         p1, _ = rows()
         pred = lx * (sigma[1:] - sigma[:-1]) + c["body"][0] * m0
@@ -157,7 +162,9 @@ def test_profile_stats_match_numpy():
     k0 = ly // 3
     st = sim.profile_stats(samples, k0)
     s = samples.cpu().numpy()
-    u, sig = s[:, :ly], s[:, ly:]
+    u, sig = s[:, :ly], s[:, ly:2 * ly + 1]
+    np.testing.assert_allclose(st["rho_a"].cpu().numpy(), s[:, 2 * ly + 1:3 * ly + 1].mean(axis=0), rtol=1e-12)
+    np.testing.assert_allclose(st["rho_b"].cpu().numpy(), s[:, 3 * ly + 1:].mean(axis=0), rtol=1e-12)
     np.testing.assert_allclose(st["u"].cpu().numpy(), u.mean(axis=0), rtol=1e-12, atol=1e-18)
     np.testing.assert_allclose(st["sigma"].cpu().numpy(), sig.mean(axis=0), rtol=1e-12, atol=1e-18)
     du = np.empty_like(sig)
