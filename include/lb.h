@@ -336,6 +336,15 @@ int lb_batch_autotune(lb_batch *b, int32_t trial_steps, int32_t out[3], double *
    [2][ly_i][lx_i]).  Asynchronous. */
 int lb_batch_moments(lb_batch *b, int32_t i, void *rho, void *u, int32_t dtype);
 
+/* Profiles of instance i, as lb_profile (device out, 4 ly_i + 1 doubles); time statistics of
+   its samples follow from lb_profile_stats on a context of the same lattice, or directly from
+   the samples.  Asynchronous. */
+int lb_batch_profile(lb_batch *b, int32_t i, double *out);
+
+/* Site pressure tensor of instance i, as lb_stress_field (device [3][ly_i][lx_i]).
+   Asynchronous. */
+int lb_batch_stress_field(lb_batch *b, int32_t i, void *sigma, int32_t dtype);
+
 /* FP64 totals of every instance (host out[n][5]: mass A, mass B, momentum x, momentum y,
    flow rate), as lb_totals.  Synchronises. */
 int lb_batch_totals(lb_batch *b, double *out);

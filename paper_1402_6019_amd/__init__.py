@@ -387,6 +387,24 @@ class Batch:
                                              ctypes.c_void_p(u.data_ptr()), code))
         return rho, u
 
+    def profile(self, i):
+        """Profiles of instance i (device FP64 [4 ly_i + 1]), as Sim.profile."""
+        torch = self.torch
+        lx, ly = self.shapes[i]
+        out = torch.empty(4 * ly + 1, dtype=torch.float64, device=self.device)
+        self._chk(self._lib.lb_batch_profile(self._h, int(i), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def stress_field(self, i, dtype=None):
+        """Site pressure tensor of instance i (device [3, ly_i, lx_i]), as Sim.stress_field."""
+        torch = self.torch
+        dtype = dtype or torch.float64
+        lx, ly = self.shapes[i]
+        out = torch.empty((3, ly, lx), dtype=dtype, device=self.device)
+        code = B.LB_OUT_F32 if dtype == torch.float32 else B.LB_OUT_F64
+        self._chk(self._lib.lb_batch_stress_field(self._h, int(i), ctypes.c_void_p(out.data_ptr()), code))
+        return out
+
     def totals(self):
         """[n, 5] FP64: mass A, mass B, momentum x, momentum y, flow rate."""
         out = np.zeros((self.n, 5))

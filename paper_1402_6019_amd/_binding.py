@@ -85,6 +85,8 @@ SIGNATURES = {
     "lb_batch_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "lb_batch_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), _dp]),
     "lb_batch_moments": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32]),
+    "lb_batch_profile": (ctypes.c_int, [_vp, _i32, _vp]),
+    "lb_batch_stress_field": (ctypes.c_int, [_vp, _i32, _vp, _i32]),
     "lb_batch_totals": (ctypes.c_int, [_vp, _dp]),
     "lb_batch_wall_stress": (ctypes.c_int, [_vp, _dp, _i32]),
     "lb_batch_checkpoint": (ctypes.c_int, [_vp, _i32, _vp]),

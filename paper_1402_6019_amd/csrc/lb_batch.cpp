@@ -48,6 +48,8 @@ struct lb_batch {
   ReduceJob *d_jobs = nullptr;
   double *d_partials = nullptr;  // [tiles][RED_N]
   double *d_accrows = nullptr;   // [tiles][ACC_N]: running sums of reducing steps (zero after a flush)
+  double *d_prof = nullptr;      // profile pass of one instance: block sums, then row sums
+  size_t prof_cap = 0;           // doubles
   int64_t acc_pending = 0;       // reducing launches since the last flush
   double *d_totals = nullptr;    // [n][RED_N]
   double *d_acc = nullptr;       // [n][4]: wall stress sums (bot, top), count, bad
@@ -473,6 +475,49 @@ int lb_batch_moments(lb_batch *b, int32_t i, void *rho, void *u, int32_t dtype) 
   return LB_OK;
 }
 
+int lb_batch_stress_field(lb_batch *b, int32_t i, void *sigma, int32_t dtype) {
+  if (!b) return bfail(nullptr, LB_EINVAL, "null context");
+  int rc = check_index(b, i);
+  if (rc) return rc;
+  if (!sigma) return bfail(b, LB_EINVAL, "null output");
+  if (dtype != LB_OUT_F64 && dtype != LB_OUT_F32) return bfail(b, LB_EINVAL, "dtype must be LB_OUT_F64 or LB_OUT_F32");
+  hipError_t e = launch_tiles(b, WHAT_STRESS, b->cur, b->tile0[i], b->ntile[i], b->stream, sigma, nullptr,
+                              dtype == LB_OUT_F32);
+  if (e != hipSuccess) return bhip(b, e, "stress launch");
+  return LB_OK;
+}
+
+int lb_batch_profile(lb_batch *b, int32_t i, double *out) {
+  if (!b) return bfail(nullptr, LB_EINVAL, "null context");
+  int rc = check_index(b, i);
+  if (rc) return rc;
+  if (!out) return bfail(b, LB_EINVAL, "null output");
+  const lb_lattice &L = b->lat[i];
+  const int ncb = ((L.lx + b->tx - 1) / b->tx) * (b->tx / 64);
+  const size_t need = ((size_t)ncb + 1) * L.ly * PROF_N;
+  if (need > b->prof_cap) {
+    (void)hipStreamSynchronize(b->stream);
+    if (b->d_prof) (void)hipFree(b->d_prof);
+    b->d_prof = nullptr;
+    b->prof_cap = 0;
+    hipError_t e = hipMalloc(&b->d_prof, need * sizeof(double));
+    if (e != hipSuccess) return bfail(b, LB_ENOMEM, std::string("profile buffer: ") + hipGetErrorString(e));
+    b->prof_cap = need;
+  }
+  hipError_t e = launch_tiles(b, WHAT_PROFILE, b->cur, b->tile0[i], b->ntile[i], b->stream, b->d_prof);
+  double wb0 = 0.0, wt0 = 0.0;
+  if (b->walls)
+    for (int s = 0; s < b->ns; ++s) {
+      wb0 += 2.0 * b->args[i].wall_mom[0][s];
+      wt0 += 2.0 * b->args[i].wall_mom[1][s];
+    }
+  if (e == hipSuccess)
+    e = launch_profile_finish(b->d_prof, ncb, L.lx, L.ly, b->walls, wb0, wt0, b->d_prof + (size_t)ncb * L.ly * PROF_N,
+                              out, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "profile launch");
+  return LB_OK;
+}
+
 int lb_batch_totals(lb_batch *b, double *out) {
   if (!b) return bfail(nullptr, LB_EINVAL, "null context");
   if (!out) return bfail(b, LB_EINVAL, "null output");
@@ -577,6 +622,7 @@ void lb_batch_destroy(lb_batch *b) {
   if (b->check_pending && b->ev) (void)hipEventSynchronize(b->ev);
   (void)hipStreamSynchronize(b->stream);
   for (void *p : {(void *)b->d_args, (void *)b->d_tiles, (void *)b->d_jobs, (void *)b->d_partials, (void *)b->d_accrows,
+                  (void *)b->d_prof,
                   (void *)b->d_totals, (void *)b->d_acc})
     if (p) (void)hipFree(p);
   if (b->h_acc) (void)hipHostFree(b->h_acc);

@@ -81,7 +81,8 @@ struct BatchArgs {
   const char *src;       // population buffers holding every instance at StepArgs::offset
   char *dst;
   double *partials;      // [tiles][RED_N]
-  void *out_rho, *out_u; // WHAT_MOMENTS (the launch then covers one instance)
+  void *out_rho, *out_u; // WHAT_MOMENTS (the launch then covers one instance); out_rho is the
+                         // output of WHAT_STRESS and WHAT_PROFILE too
   int out_f32;
   int stream_stores;     // non-temporal population stores (see StepArgs)
   double *accrows;       // WHAT_STEP_ACCUM: [tiles][ACC_N] running sums, row TileDesc::part

@@ -326,10 +326,12 @@ __device__ inline T wave_sum(T v) {
 
 // One tile: strip `strip` (tx = blockDim.x columns) and segment `seg` (a.sy rows) of the
 // lattice described by a, read from src and written to dst.  part: this tile's row of
-// reduction partials; out_*: moments output (WHAT_MOMENTS).
+// reduction partials; out0: the output of a pass that stores nothing (WHAT_MOMENTS: rho;
+// WHAT_STRESS: the pressure tensor; WHAT_PROFILE: the [64-column block][row][PROF_N] sums);
+// out_u: the WHAT_MOMENTS velocity.
 template <int MODE, int NS, bool WALLS, int WHAT, int STP>
 __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const src, void *const dst, const int strip,
-                                         const int seg, double *const part, void *const out_rho,
+                                         const int seg, double *const part, void *const out0,
                                          void *const out_u, const int out_f32) {
   using C = Codec<MODE>;
   using R = typename C::R;
@@ -661,11 +663,11 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       }
       const size_t site = (size_t)y * lx + xc;
       const size_t nsite = (size_t)lx * ly;
-      if (out_rho) {
+      if (out0) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          if (out_f32) static_cast<float *>(out_rho)[s * nsite + site] = float(rho[s]);
-          else static_cast<double *>(out_rho)[s * nsite + site] = double(rho[s]);
+          if (out_f32) static_cast<float *>(out0)[s * nsite + site] = float(rho[s]);
+          else static_cast<double *>(out0)[s * nsite + site] = double(rho[s]);
         }
       }
       if (out_u) {
@@ -746,13 +748,13 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       const size_t site = (size_t)y * lx + xc;
       const size_t nsite = (size_t)lx * ly;
       if (out_f32) {
-        static_cast<float *>(a.out_sigma)[site] = float(sxx);
-        static_cast<float *>(a.out_sigma)[nsite + site] = float(sxy);
-        static_cast<float *>(a.out_sigma)[2 * nsite + site] = float(syy);
+        static_cast<float *>(out0)[site] = float(sxx);
+        static_cast<float *>(out0)[nsite + site] = float(sxy);
+        static_cast<float *>(out0)[2 * nsite + site] = float(syy);
       } else {
-        static_cast<double *>(a.out_sigma)[site] = sxx;
-        static_cast<double *>(a.out_sigma)[nsite + site] = sxy;
-        static_cast<double *>(a.out_sigma)[2 * nsite + site] = syy;
+        static_cast<double *>(out0)[site] = sxx;
+        static_cast<double *>(out0)[nsite + site] = sxy;
+        static_cast<double *>(out0)[2 * nsite + site] = syy;
       }
     }
 
@@ -830,7 +832,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       }
       double pv[PROF_N] = {double(mx / sr), kup, kdn, i1, i2, double(rho[0]), NS == 2 ? double(rho[NS - 1]) : 0.0};
       const int lane = tid & 63, wv = tid >> 6;
-      double *row = a.prof + ((size_t)(strip * (TX >> 6) + wv) * ly + y) * PROF_N;
+      double *row = static_cast<double *>(out0) + ((size_t)(strip * (TX >> 6) + wv) * ly + y) * PROF_N;
 #pragma unroll
       for (int k = 0; k < PROF_N; ++k) {
         const double v = wave_sum(col_ok ? pv[k] : 0.0);
@@ -961,7 +963,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   const int strip = logical - seg * nstrip;
   double *const part = WHAT == WHAT_STEP_ACCUM ? a.accrows + (size_t)blockIdx.x * ACC_N
                                                : a.partials + (size_t)blockIdx.x * RED_N;
-  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, part, a.out_rho, a.out_u, a.out_f32);
+  void *const out0 =
+      WHAT == WHAT_STRESS ? a.out_sigma : (WHAT == WHAT_PROFILE ? static_cast<void *>(a.prof) : a.out_rho);
+  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, part, out0, a.out_u, a.out_f32);
 }
 
 // Many independent lattices in one persistent launch.  The host lists every tile of every
@@ -1292,6 +1296,12 @@ static hipError_t launch_batch_t(int what, int tx, int grid, const BatchArgs &b,
       break;
     case WHAT_OBSERVE:
       hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_OBSERVE>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    case WHAT_PROFILE:
+      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_PROFILE>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    case WHAT_STRESS:
+      hipLaunchKernelGGL((batch_step_kernel<MODE, NS, WALLS, WHAT_STRESS>), dim3(grid), dim3(tx), lds, st, b);
       break;
     default: return hipErrorInvalidValue;
   }

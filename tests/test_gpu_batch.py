@@ -35,7 +35,8 @@ def batch_cases(storage, walls=True):
 def make_batch(cases, storage):
     from paper_1402_6019_amd import Batch
     inst = [dict(lx=c["lx"], ly=c["ly"], rho_init=c["rho"], g1=c["g1"], g2=c["g2"], gab=c["gab"], body=c["body"],
-                 rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"], rho_ref=c["rho_ref"])
+                 rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"], rho_ref=c["rho_ref"],
+                 u_wall=c.get("u_wall", (0.0, 0.0)))
             for c in cases]
     return Batch(inst, n_species=2, walls=bool(cases[0]["walls"]), storage=storage)
 
@@ -92,6 +93,23 @@ def test_batch_totals_and_wall_stress_match_single_contexts():
         w = sim.wall_stress(reset=True)
         np.testing.assert_allclose(tot[i], [m0, m1, px, py, q], rtol=1e-12, atol=1e-15 * m0)
         np.testing.assert_allclose(ws[i], w, rtol=1e-12, atol=1e-18)
+        sim.close()
+    b.close()
+
+
+def test_batch_profiles_and_stress_fields_match_single_contexts():
+    """Per-instance profiles and pressure tensors of a batch equal those of the same lattices
+    in their own contexts, bit for bit (sliding walls on two instances)."""
+    cases = batch_cases("f64", True)
+    cases[1]["u_wall"] = (-0.01, 0.02)
+    cases[3]["u_wall"] = (0.015, -0.005)
+    b = make_batch(cases, "f64")
+    b.step(11)
+    for i, c in enumerate(cases):
+        sim = make_sim(c)
+        sim.step(11)
+        assert np.array_equal(b.profile(i).cpu().numpy(), sim.profile().cpu().numpy()), i
+        assert np.array_equal(b.stress_field(i).cpu().numpy(), sim.stress_field().cpu().numpy()), i
         sim.close()
     b.close()
 
