@@ -60,6 +60,31 @@ def test_channel_4096x512_full_size(storage):
     assert e_rho <= TOL[storage][0] and e_u <= TOL[storage][1]
 
 
+def test_couette_1040_full_size():
+    """The Couette cell at the paper's 1040 x 1040 domain in the launch shape bench.py times
+    (the autotuner's 128 x 10): FP32 fields and profile against the oracle after 6 steps."""
+    from oracle import Oracle, Params
+    from oracle import diagnostics as dg
+    from paper_1402_6019_amd import Sim
+    L = 1040
+    rho, _ = lbgen.emulsion(L, L, fraction=0.8, seed=6, walls=True)
+    kw = dict(g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB, rho_wall=lbgen.EMULSION_POOR,
+              rho0=lbgen.EMULSION_RHO0, u_wall=(-0.01, 0.01))
+    sim = Sim(L, L, rho, n_species=2, walls=True, storage="f32", tile=(128, 10), **kw)
+    orc = Oracle(Params(lx=L, ly=L, ns=2, walls=1, **kw), rho_init=rho)
+    sim.step(6)
+    orc.step(6)
+    r, u = sim.moments()
+    e_rho, e_u = rel_fields(r.cpu().numpy(), u.cpu().numpy(), orc.fields())
+    prof = sim.profile().cpu().numpy()
+    ubar, sigma = dg.shear_profile(orc)
+    e_ub = np.abs(prof[:L] - ubar).max() / np.abs(ubar).max()
+    e_s = np.abs(prof[L:2 * L + 1] - sigma).max() / np.abs(sigma).max()
+    print(f"couette 1040 f32: rho {e_rho:.2e} u {e_u:.2e} ubar {e_ub:.2e} sigma {e_s:.2e}", flush=True)
+    assert e_rho <= 1e-5 and e_u <= 1e-5 and e_ub <= 1e-5 and e_s <= 1e-4
+    sim.close()
+
+
 def test_batched_sweep_full_size():
     """The 64-instance uneven sweep (seed 4) in FP32 with the autotuned shape; the three
     smallest instances against the oracle after 5 steps."""
