@@ -67,6 +67,27 @@ def time_storage(storage, rho, kw, steps, warmup, tile=None, shape=(LX, LY)):
     return ms, wall, tile_used
 
 
+def channel_profiles(rho, kw, lx, ly, samples=20, every=100):
+    """The channel's time-averaged outputs (velocity and density profiles, wall stress) from
+    profile samples taken every `every` steps (FP32): a short average, to show the outputs
+    and the cost of the profile pass at this size, not a converged flow."""
+    import torch
+    from paper_1402_6019_amd import Sim
+    sim = Sim(lx, ly, rho, storage="f32", **kw)
+    sim.set_graph(every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp = sim.sample_profiles(samples, every)
+    st = sim.profile_stats(smp)
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    u, sig, ra, rb = (st[k].cpu().numpy() for k in ("u", "sigma", "rho_a", "rho_b"))
+    sim.close()
+    return {"steps": samples * every, "samples": samples, "seconds": seconds,
+            "wall_stress_bot_top": [float(sig[0]), float(-sig[-1])], "u_centre": float(u[ly // 2]),
+            "u_max": float(u.max()), "rho_a_centre": float(ra[ly // 2]), "rho_b_wall_rows": [float(rb[0]), float(rb[-1])]}
+
+
 def channel_beyond_cache(steps):
     """Confined emulsion channel 4096 x 512 (walls, wetting, g = 1e-6, volume fraction 0.85):
     its FP32 ping-pong footprint (302 MB) exceeds the 256 MB Infinity Cache, so this rate is
@@ -78,6 +99,7 @@ def channel_beyond_cache(steps):
               body=(1e-6, 0.0), rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0,
               rho_ref=(float(rho[0].mean()), float(rho[1].mean())))
     out = {"workload": f"confined emulsion channel {lx}x{ly}, walls + wetting, g = 1e-6, volume fraction 0.85, seed 3"}
+    out["profiles_f32"] = channel_profiles(rho, kw, lx, ly)
     for storage in ("f32", "bf16dev", "f64"):
         ms, wall, tile = time_storage(storage, rho, kw, steps, max(10, steps // 10), shape=(lx, ly))
         bpl = 2 * 9 * 2 * BYTES_PER_VALUE[storage]
