@@ -510,13 +510,21 @@ def cpu_baseline(rho, kw, budget_s=15.0):
     orc.step(n)
     dt = time.perf_counter() - t0
     refs[100 + n] = orc.fields()
+    # the same binary on one thread, for a few steps of the same lattice
+    threads = oracle.get_threads()
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    orc.step(3)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {
         "value": LX * LY * n / dt / 1e6,
         "unit": "MLUPS",
-        "cores": oracle.get_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"{n} steps (steps 100..{100 + n}) of the same 1024x1024 two-component lattice from the "
                   f"same initial state ({dt:.1f} s, FP64, OpenMP over rows)",
+        "one_thread_mlups": LX * LY * 3 / dt1 / 1e6,
     }, refs
 
 
