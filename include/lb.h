@@ -110,6 +110,12 @@ typedef struct {
                           stores plain populations. */
 } lb_psi_params;
 
+/* Streaming copy of `bytes` (a multiple of 16, 16-byte aligned device buffers) from src to
+   dst with 16-byte accesses, non-temporal if nontemporal != 0: the bandwidth reference the
+   benchmark compares the step against (a plain copy moves the same bytes with no stencil).
+   Asynchronous on hip_stream; errors are reported by lb_last_error(NULL). */
+int lb_stream_copy(void *dst, const void *src, size_t bytes, int32_t nontemporal, void *hip_stream);
+
 /* Fill *c with zero couplings and the default isotropic weights.  Pure host call. */
 int lb_default_couplings(lb_couplings *c);
 

@@ -49,6 +49,7 @@ _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c
 _dp = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "lb_default_couplings": (ctypes.c_int, [ctypes.POINTER(LbCouplings)]),
+    "lb_stream_copy": (ctypes.c_int, [_vp, _vp, _sz, _i32, _vp]),
     "lb_pop_bytes": (_sz, [ctypes.POINTER(LbLattice)]),
     "lb_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(LbLattice), ctypes.POINTER(LbCouplings), _dp,
                                ctypes.POINTER(LbPsiParams), _dp, _vp, _vp, _sz, _vp]),

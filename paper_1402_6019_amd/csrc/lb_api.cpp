@@ -225,6 +225,16 @@ void default_tile(lb_ctx *c) {
 
 extern "C" {
 
+int lb_stream_copy(void *dst, const void *src, size_t bytes, int32_t nontemporal, void *hip_stream) {
+  if (!dst || !src) return fail(nullptr, LB_EINVAL, "null buffer");
+  if (bytes % 16 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+    return fail(nullptr, LB_EINVAL, "copy size and addresses must be multiples of 16 bytes");
+  const hipError_t e = launch_stream_copy(dst, src, bytes / 16, nontemporal ? 1 : 0, 4 * device_cu_count(),
+                                          static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(nullptr, LB_EDEVICE, std::string("copy launch: ") + hipGetErrorString(e));
+  return LB_OK;
+}
+
 int lb_default_couplings(lb_couplings *c) {
   if (!c) return fail(nullptr, LB_EINVAL, "null argument");
   std::memset(c, 0, sizeof(*c));

@@ -152,6 +152,8 @@ hipError_t launch_checkpoint_fields(int mode, int walls, int fp64, const LayoutA
 hipError_t launch_restore(int mode, int walls, const LayoutArgs &a, hipStream_t st);
 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+// Grid-stride copy of n16 16-byte elements (blocks workgroups of 256), non-temporal if asked.
+hipError_t launch_stream_copy(void *dst, const void *src, size_t n16, int nontemporal, int blocks, hipStream_t st);
 // acc[0..1] += (column sums of rows' wall stress) * inv_lx, acc[2] += count, acc[3] += bad;
 // rows are cleared.
 hipError_t launch_flush(double *rows, int nrows, double *acc, double count, double inv_lx, hipStream_t st);

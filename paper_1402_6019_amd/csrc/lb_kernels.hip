@@ -1488,6 +1488,27 @@ hipError_t launch_batch_flush(double *rows, const ReduceJob *jobs, int njobs, do
   return hipGetLastError();
 }
 
+// Streaming copy (the benchmark's bandwidth reference): 16-byte accesses in a grid-stride
+// loop over n16 elements, non-temporal when NT.
+using u32x4v = unsigned int __attribute__((ext_vector_type(4)));
+template <int NT>
+__global__ void stream_copy_kernel(const u32x4v *__restrict__ src, u32x4v *__restrict__ dst, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+    if (NT) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    else dst[i] = src[i];
+  }
+}
+
+hipError_t launch_stream_copy(void *dst, const void *src, size_t n16, int nontemporal, int blocks, hipStream_t st) {
+  if (n16 == 0) return hipSuccess;
+  const auto *s = static_cast<const u32x4v *>(src);
+  auto *d = static_cast<u32x4v *>(dst);
+  if (nontemporal) hipLaunchKernelGGL(stream_copy_kernel<1>, dim3(blocks), dim3(256), 0, st, s, d, n16);
+  else hipLaunchKernelGGL(stream_copy_kernel<0>, dim3(blocks), dim3(256), 0, st, s, d, n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
