@@ -142,6 +142,9 @@ template <> struct Codec<MODE_F32> {
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
 };
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 // BF16: stored value = bf16(d_l), arithmetic in FP32.
 // BF16: the FIFO keeps the raw 16-bit values (two to a register), decoded where used.
 template <> struct Codec<MODE_BF16> {
@@ -150,13 +153,8 @@ template <> struct Codec<MODE_BF16> {
   using L = uint16_t;
   __device__ static R dec(L v) { return decode(v); }
   __device__ static R decode(uint32_t h) { return __uint_as_float(h << 16); }
-  __device__ static uint16_t encode(R v) {
-    const uint32_t b = __float_as_uint(v);
-    // round to nearest even; NaN stays NaN
-    const uint32_t r = (b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) ? (b | 0x00400000u)
-                                                                              : b + 0x7fffu + ((b >> 16) & 1u);
-    return uint16_t(r >> 16);
-  }
+  // the hardware conversion (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
+  __device__ static uint16_t encode(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
   __device__ static R load(const S *p, R wref) { return decode(*p) + wref; }
   __device__ static void store(S *p, R v, R wref) { *p = encode(v - wref); }
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
@@ -175,7 +173,10 @@ template <> struct Codec<MODE_BF16> {
   }
   template <int AUX>
   __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
-    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)encode(a) | ((uint32_t)encode(b) << 16), r, voff, soff, AUX);
+    // both values in one packed conversion
+    const f32x2 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2)), r, voff,
+                                          soff, AUX);
   }
 };
 
