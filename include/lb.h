@@ -69,6 +69,13 @@ enum lb_storage {
 /* Output type of lb_moments. */
 enum lb_dtype { LB_OUT_F64 = 0, LB_OUT_F32 = 1 };
 
+/* Population store policy of the plain and reducing step kernels (lb_set_store_policy). */
+enum lb_store_policy {
+  LB_STORES_AUTO = 0,          /* by footprint: streaming once both buffers exceed 256 MiB */
+  LB_STORES_WRITE_THROUGH = 1, /* stores written through L2 and kept by the Infinity Cache */
+  LB_STORES_STREAMING = 2      /* non-temporal stores, lead-row loads issued without a branch */
+};
+
 typedef struct {
   int32_t lx, ly;      /* lattice size: lx, ly >= 5, ly <= 65535, lx * ly <= 2^27, and one population
                           buffer (lb_pop_bytes) below 4 GiB */
@@ -195,6 +202,13 @@ int64_t lb_time(const lb_ctx *ctx);
    results.  Host call. */
 int lb_set_tile(lb_ctx *ctx, int32_t tx, int32_t sy);
 int lb_get_tile(const lb_ctx *ctx, int32_t *tx, int32_t *sy);
+
+/* Choose the step kernel's variant for the population traffic (enum lb_store_policy).  The
+   default, LB_STORES_AUTO, takes the streaming variant when both population buffers together
+   exceed the 256 MiB Infinity Cache and the write-through one otherwise; the other two values
+   force one.  All variants give bitwise identical results; only their speed differs.
+   Captured graphs are rebuilt.  Host call; LB_EINVAL for any other value. */
+int lb_set_store_policy(lb_ctx *ctx, int32_t policy);
 
 /* Replay plain steps from captured HIP graphs: with steps > 0 (even) and no reductions
    (lb_set_reduce_every k = 0), lb_step runs whole groups of `steps` launches as one graph

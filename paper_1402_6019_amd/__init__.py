@@ -136,6 +136,15 @@ class Sim:
     def set_tile(self, tx, sy):
         self._chk(self._lib.lb_set_tile(self._h, int(tx), int(sy)))
 
+    STORE_POLICIES = {"auto": 0, "write_through": 1, "streaming": 2}
+
+    def set_store_policy(self, policy):
+        """Step-kernel variant for the population traffic: "auto" (by footprint),
+        "write_through" or "streaming"; bitwise the same results, different speed."""
+        if policy not in self.STORE_POLICIES:
+            raise ValueError(f"policy must be one of {sorted(self.STORE_POLICIES)}")
+        self._chk(self._lib.lb_set_store_policy(self._h, self.STORE_POLICIES[policy]))
+
     def get_tile(self):
         tx, sy = ctypes.c_int32(), ctypes.c_int32()
         self._chk(self._lib.lb_get_tile(self._h, ctypes.byref(tx), ctypes.byref(sy)))

@@ -40,6 +40,7 @@ struct lb_ctx {
   int tx = 256, sy = 16;
   int n_cu = 256;  // compute units of the device the context runs on
   int reduce_every = 0;
+  int store_policy = LB_STORES_AUTO;
   int64_t t = 0;
   double *d_partials = nullptr;  // [partial_cap][RED_N], grown to the largest launch
   int partial_cap = 0;
@@ -91,7 +92,8 @@ int ensure_partials(lb_ctx *c, int nb) {
 
 void fill_step_args(const lb_ctx *c, StepArgs &a) {
   a = make_step_args(c->lat, c->cpl, c->psi, c->tau, c->pitch, c->plane, c->sy);
-  a.stream_stores = streaming_stores(lb_pop_bytes(&c->lat));
+  a.stream_stores = c->store_policy == LB_STORES_AUTO ? streaming_stores(lb_pop_bytes(&c->lat))
+                                                       : (c->store_policy == LB_STORES_STREAMING ? 1 : 0);
 }
 
 // One plain step launch (no reductions) from buffer `from` to the other one, on stream st.
@@ -499,6 +501,15 @@ int lb_set_tile(lb_ctx *c, int32_t tx, int32_t sy) {
   c->tx = tx;
   c->sy = std::min<int32_t>(sy, c->lat.ly);
   c->graph.clear();  // captured launches carry the old shape
+  return LB_OK;
+}
+
+int lb_set_store_policy(lb_ctx *c, int32_t policy) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (policy != LB_STORES_AUTO && policy != LB_STORES_WRITE_THROUGH && policy != LB_STORES_STREAMING)
+    return fail(c, LB_EINVAL, "policy must be LB_STORES_AUTO, LB_STORES_WRITE_THROUGH or LB_STORES_STREAMING");
+  c->store_policy = policy;
+  c->graph.clear();  // captured launches carry the old kernel variant
   return LB_OK;
 }
 

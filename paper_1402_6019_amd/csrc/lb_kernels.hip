@@ -449,8 +449,8 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
 
   // Stage 1, halo columns: load (one item per thread), stage into LDS buffer `buf`, and
   // finish (after a barrier) into ring slot `slot`.
-  auto halo_load = [&](const RowOffs &r, L (&hv)[2]) {
-    const Rsrc rs = make_rsrc(src, buf_b);
+  auto halo_load = [&](const RowOffs &r, L (&hv)[2], uint32_t nbytes) {
+    const Rsrc rs = make_rsrc(src, nbytes);
     if (NS == 2) C::bload2(rs, halo_offset(hitem, r), 0u, hv[0], hv[1]);
     else hv[0] = C::bload(rs, halo_offset(hitem, r), 0u);
   };
@@ -507,7 +507,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     auto load_row = [&](int r, L (&dstb)[NS][9], L (&hv)[2]) {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r, ly), ly, row_b);
       load_pull<C, NS>(src, buf_b, plane_b, pcc, pr, dstb);
-      halo_load(pr, hv);
+      halo_load(pr, hv, buf_b);
     };
     load_row(y0 - 2 * dir, B[D - 1], HP[0]);
     load_row(y0 - dir, B[D - 2], HP[1]);
@@ -546,13 +546,24 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     const int hbuf = (int)uni((uint32_t)hbuf_in);
     const uint32_t rb0 = (uint32_t)y * row_b;
     halo_stage(hbuf, hv);
-    // lead rows past the last one the segment needs are not loaded (uniform branch); their
-    // buffers then feed only ring rows that no output row reads
+    // Lead rows past the last one the segment needs are not fetched; their buffers then feed
+    // only ring rows that no output row reads.
     const int rl = y + dir * (D - 1);
-    if (dir > 0 ? rl <= ylast : rl >= ylast) {
+    const bool past = dir > 0 ? rl > ylast : rl < ylast;
+    if (STP == kStoreStreaming) {
+      // Footprint beyond the Infinity Cache: the loads are issued for every row, those of a
+      // row past the end through a zero-length buffer range (they return zeros and touch no
+      // memory).  With no branch around them the compiler counts outstanding loads exactly
+      // and no longer waits for the previous row's stores before the ring row, which pays
+      // once HBM serves the traffic; with cache-resident buffers the extra issue costs more.
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(past ? ylast : rl, ly), ly, row_b);
+      const uint32_t nb = past ? 0u : buf_b;
+      load_pull<C, NS>(src, nb, plane_b, pcc, pr, FL);
+      halo_load(pr, hv, nb);
+    } else if (!past) {  // uniform branch
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rl, ly), ly, row_b);
       load_pull<C, NS>(src, buf_b, plane_b, pcc, pr, FL);
-      halo_load(pr, hv);
+      halo_load(pr, hv, buf_b);
     }
 
     __syncthreads();
