@@ -73,7 +73,8 @@ template <int MODE> struct Codec;
 // displace the next step's reads from the Infinity Cache.  That pays when both population
 // buffers together exceed the Infinity Cache (the state cannot stay resident anyway) and
 // costs when they fit (the next step would have read them from it), so the host picks the
-// kernel instantiation per lattice from the footprint.
+// kernel instantiation per lattice from the footprint.  The streaming instantiation also
+// issues its tail rows' loads without a branch (see the lead-row loads in run_tile).
 constexpr int kStoreWriteThrough = 16;      // SC1
 constexpr int kStoreStreaming = 16 | 2;     // SC1 | NT
 
@@ -491,9 +492,9 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   // ring row y'+3 of output row y' = y+D-4) and are the stage-2 input of their own row D-1
   // iterations after loading: every population is loaded once per step, D-4 full
   // iterations before its first use.  The halo items of a lead row are held in registers
-  // for the same D-4 iterations (NHV sets).  D = 5: a deeper FIFO does not help, because a
-  // wave can have at most 63 memory instructions outstanding and one row issues 38 (loads
-  // and stores count alike), so loads two rows ahead cannot be waited for selectively.
+  // for the same D-4 iterations (NHV sets).  D = 5: six or eight rows (two or four
+  // iterations of lead, with D a multiple of NHV) measured no faster in any storage mode,
+  // FP64 included, where the extra rows cost no occupancy.
   constexpr int D = 5;
   constexpr int NHV = D - 4;
   L B[D][NS][9];
