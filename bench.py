@@ -330,8 +330,45 @@ def film_sweep(radii=(16, 24, 32, 48, 64), steps=30000):
         torch.cuda.synchronize()
         rows.append({"radius": R, "h": o["h"], "pi": o["pi_capillary"], "pn_film": o["pn_film"]})
         sim.close()
+    import numpy as np
+    theory = flat_film_theory()
+    th, tp = np.array(theory["h"]), np.array(theory["pi"])
+    order = np.argsort(th)
+    for r in rows:
+        r["pi_flat_film_theory"] = float(np.interp(r["h"], th[order], tp[order])) if r["h"] > 0 else None
     return {"workload": f"two facing half-disc bubbles, gap {gap}, G1 = -20.4, G2 = 16, FP64, {steps} steps each",
-            "points": rows, "seconds": time.perf_counter() - t0}
+            "points": rows, "theory": theory, "seconds": time.perf_counter() - t0}
+
+
+def flat_film_theory(thicknesses=(3.0, 3.5, 4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0, 8.0, 9.0, 10.0, 12.0, 16.0, 24.0, 40.0),
+                     steps=60000, lx=160, ly=5):
+    """The theoretical disjoining pressure of eq. (doppiasigma): flat films of several
+    thicknesses relaxed at the same couplings (FP64), their film tension gamma_f(h) from the
+    site pressure tensor, and Pi(h) = -int_h^inf gamma_f'/h' dh' (Pi = 0 at the thickest).
+    The film thickness is measured at the density half-way between the bulk liquid and gas
+    of the thickest film."""
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    from paper_1402_6019_amd.film import disjoining_from_tension, flat_film
+    t0 = time.perf_counter()
+    sims = []
+    for h0 in thicknesses:
+        sim = Sim(lx, ly, lbgen.flat_film(lx, ly, h0)[None], n_species=1, storage="f64",
+                  g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0))
+        sim.set_graph(1000)
+        sim.step(steps)
+        sims.append(sim)
+    thick = flat_film(sims[-1])
+    mid = 0.5 * (thick["rho_min"] + thick["rho_max"])
+    rows = [flat_film(s, mid=mid) for s in sims]
+    for s in sims:
+        s.close()
+    h = [r["h"] for r in rows]
+    g = [r["gamma_f"] for r in rows]
+    pi = disjoining_from_tension(h, g)
+    return {"workload": f"flat films {lx}x{ly}, initial thickness {thicknesses[0]}..{thicknesses[-1]}, {steps} steps each, FP64",
+            "h": h, "gamma_f": g, "pi": [float(p) for p in pi], "max_p_n_spread": max(r["p_n_spread"] for r in rows),
+            "two_gamma": g[-1], "seconds": time.perf_counter() - t0}
 
 
 def adjoint_channel(T=4000, prerelax=2000, check_fd=True):

@@ -59,6 +59,17 @@ def facing_bubbles(lx, ly, radius, gap, rho_in=0.28, rho_out=1.39, width=1.5):
     return rho_in + (rho_out - rho_in) * 0.5 * (1.0 + np.tanh(d / width))
 
 
+def flat_film(lx, ly, thickness, rho_gas=0.28, rho_liq=1.39, width=1.5):
+    """A flat liquid film (rho_liq) of `thickness` sites centred at x = lx/2, uniform in y, in
+    the gas (rho_gas): the flat counterpart of the film between two bubbles, whose film
+    tension gives the theoretical disjoining pressure.  tanh walls of width `width`.
+    Shape [ly, lx]."""
+    x = np.arange(lx, dtype=np.float64)
+    x1, x2 = lx / 2.0 - thickness / 2.0, lx / 2.0 + thickness / 2.0
+    prof = rho_gas + (rho_liq - rho_gas) * 0.5 * (np.tanh((x - x1) / width) - np.tanh((x - x2) / width))
+    return np.broadcast_to(prof, (ly, lx)).copy()
+
+
 def _expected_area(rmin, rmax):
     er2 = (rmax ** 3 - rmin ** 3) / (3.0 * (rmax - rmin))
     return math.pi * er2

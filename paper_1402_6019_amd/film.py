@@ -3,9 +3,14 @@ near-interfaces: emergence of the disjoining pressure"): two bubbles pressed aga
 other leave a liquid film between them; in mechanical equilibrium the disjoining pressure of
 that film equals the capillary pressure between the bulk inside a bubble and the bulk outside.
 
+The theoretical side follows eq. (doppiasigma): a flat film of thickness h has a film tension
+gamma_f(h), the integral of the mismatch between the normal and tangential components of the
+pressure tensor across it, and differentiating (doppiasigma) gives d gamma_f = h dPi, so
+Pi(h) = -int_h^inf gamma_f'(h') / h' dh' with Pi(inf) = 0 and gamma_f(inf) = 2 gamma.
+
 Every field comes from the GPU (lb_moments for the density along the axis through the film,
-lb_stress_field for the pressure tensor); the host only reads a few values and interpolates
-the two crossings that bound the film.
+lb_stress_field for the pressure tensor); the host only reads a few values, sums one row and
+interpolates the two crossings that bound the film.
 """
 
 import numpy as np
@@ -58,3 +63,58 @@ def film_observables(sim, axis_row, film_x, bubble_x, outer_xy):
     return dict(h=float(h), p_bubble=float(p_bubble), p_outer=float(p_outer),
                 pi_capillary=float(p_bubble - p_outer), pn_film=float(pick[0, 1] - p_outer),
                 rho_bubble=rho_b, rho_outer=rho_o)
+
+
+def film_thickness(line, centre, mid):
+    """Distance between the two crossings of the density level `mid` on either side of
+    `centre` on the periodic-free profile `line` (0 if line[centre] is below mid)."""
+    if line[centre] < mid:
+        return 0.0
+    left = _crossing(line, centre, -1, mid)
+    right = _crossing(line, centre, +1, mid)
+    return 0.0 if left is None or right is None else float(right - left)
+
+
+def flat_film(sim, row=None, mid=None):
+    """Film tension and normal stress of a flat liquid film along y (one component, the film
+    centred at lx/2): returns dict(h, gamma_f, p_n, p_n_spread, rho_min, rho_max).
+
+    The pressure tensor and the density are averaged over two consecutive steps (the state
+    alternates with period two at the last digits), which advances `sim` by two steps.
+    gamma_f = sum over the sites of the row of (sigma_xx - sigma_yy); p_n is the mean of
+    sigma_xx over the row and p_n_spread its max - min (zero at mechanical equilibrium).  h
+    is measured at the density level `mid` (default: half-way between the row's extremes)."""
+    row = sim.ly // 2 if row is None else row
+    acc_s, acc_r = 0.0, 0.0
+    for _ in range(2):
+        acc_s = acc_s + sim.stress_field()[:, row, :].cpu().numpy()
+        acc_r = acc_r + sim.moments()[0][:, row, :].sum(dim=0).cpu().numpy()
+        sim.step(1)
+    sig, line = 0.5 * acc_s, 0.5 * acc_r
+    lo, hi = float(line.min()), float(line.max())
+    level = 0.5 * (lo + hi) if mid is None else mid
+    return dict(h=film_thickness(line, sim.lx // 2, level), gamma_f=float((sig[0] - sig[2]).sum()),
+                p_n=float(sig[0].mean()), p_n_spread=float(np.ptp(sig[0])), rho_min=lo, rho_max=hi)
+
+
+def disjoining_from_tension(h, gamma_f):
+    """Pi at the thicknesses h (any order, distinct) from the film tensions gamma_f(h) of flat
+    films, by eq. (doppiasigma): dPi = dgamma_f / h, integrated from the thickest film, where
+    Pi is taken as 0; gamma_f is taken linear between neighbouring thicknesses and 1/h is
+    integrated exactly on each interval.  Returns Pi in the order of the input."""
+    h = np.asarray(h, dtype=np.float64)
+    g = np.asarray(gamma_f, dtype=np.float64)
+    if h.shape != g.shape or h.ndim != 1 or len(h) < 2:
+        raise ValueError("h and gamma_f must be 1-D of the same length >= 2")
+    order = np.argsort(h)
+    hs, gs = h[order], g[order]
+    if np.any(np.diff(hs) <= 0):
+        raise ValueError("thicknesses must be distinct")
+    pi = np.zeros_like(hs)
+    for i in range(len(hs) - 2, -1, -1):
+        # int_{h_i}^{h_i+1} gamma_f'(h)/h dh over a linear piece of gamma_f: slope * ln(h_i+1/h_i)
+        slope = (gs[i + 1] - gs[i]) / (hs[i + 1] - hs[i])
+        pi[i] = pi[i + 1] - slope * np.log(hs[i + 1] / hs[i])
+    out = np.empty_like(pi)
+    out[order] = pi
+    return out

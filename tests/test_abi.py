@@ -183,3 +183,27 @@ def test_cooperative_length_fit_recovers_the_prediction(B):
     zz = np.array([0.0, 1.0, 200.0])  # outside [0, H]
     assert lib.lb_fit_cooperative_length(zz.ctypes.data_as(dp), zz.ctypes.data_as(dp), 3, H, 1.0, 10.0, out) == B.LB_EINVAL
     assert lib.lb_fit_cooperative_length(z.ctypes.data_as(dp), f.ctypes.data_as(dp), 2, H, 1.0, 10.0, out) == B.LB_EINVAL
+
+
+def test_disjoining_pressure_from_film_tension():
+    """Eq. (doppiasigma) inverted on the host: for Pi(h) = A exp(-h / l), the film tension is
+    gamma_f(h) = 2 gamma + A (l + h) exp(-h / l) (from (doppiasigma) with Pi(inf) = 0), and the
+    routine recovers Pi from gamma_f sampled on a grid, in any order; a dropped 1/h weight or
+    a sign error fails."""
+    from paper_1402_6019_amd.film import disjoining_from_tension, film_thickness
+    A, lam, two_gamma = 1e-3, 2.0, 0.0175
+    h = np.linspace(2.0, 60.0, 581)
+    g = two_gamma + A * (lam + h) * np.exp(-h / lam)
+    exact = A * (np.exp(-h / lam) - np.exp(-h[-1] / lam))  # Pi taken 0 at the thickest film
+    pi = disjoining_from_tension(h, g)
+    assert np.abs(pi - exact).max() < 2e-3 * A
+    perm = np.random.default_rng(0).permutation(h.size)
+    assert np.array_equal(disjoining_from_tension(h[perm], g[perm]), pi[perm])
+    # a constant tension (two independent interfaces) carries no disjoining pressure
+    assert np.all(disjoining_from_tension(h, np.full_like(h, two_gamma)) == 0.0)
+    with pytest.raises(ValueError):
+        disjoining_from_tension([3.0, 3.0], [1.0, 2.0])
+    # thickness between the two crossings of a level, linearly interpolated
+    line = np.array([0.2, 0.2, 0.6, 1.4, 1.4, 1.0, 0.2, 0.2])
+    assert film_thickness(line, 3, 0.8) == pytest.approx((5 + 0.2 / 0.8) - (2 + 0.2 / 0.8))
+    assert film_thickness(line, 0, 0.8) == 0.0

@@ -85,3 +85,63 @@ def test_film_radius_sweep():
     pis = [o[2] for o in out]
     assert all(o[1] > 3.0 for o in out)
     assert all(a > b > 0 for a, b in zip(pis, pis[1:]))
+
+
+def test_flat_film_tension_parity_with_oracle():
+    """The film tension and normal stress of a flat film (eq. (doppiasigma)'s input) from the
+    GPU's pressure tensor against the same sums over the oracle's Appendix A tensor, FP64,
+    after 3000 steps and averaged over the next two."""
+    from oracle import Oracle, Params
+    from oracle import diagnostics as dg
+    from paper_1402_6019_amd import Sim
+    from paper_1402_6019_amd.film import film_thickness, flat_film
+    lx, ly = 64, 5
+    rho = lbgen.flat_film(lx, ly, 5.0)[None]
+    sim = Sim(lx, ly, rho, n_species=1, storage="f64", g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0))
+    orc = Oracle(Params(lx=lx, ly=ly, ns=1, g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0)), rho_init=rho)
+    sim.step(3000)
+    orc.step(3000)
+    got = flat_film(sim, mid=0.85)
+    sig, line = 0.0, 0.0
+    for _ in range(2):
+        sxx, _, syy = dg.stress_field(orc)
+        sig = sig + 0.5 * np.stack([sxx[ly // 2], syy[ly // 2]])
+        line = line + 0.5 * orc.fields()["rho"][0, ly // 2]
+        orc.step(1)
+    gamma_ref = float((sig[0] - sig[1]).sum())
+    print(f"flat film: gamma_f {got['gamma_f']:.12e} vs {gamma_ref:.12e}; p_n {got['p_n']:.12e}; h {got['h']:.4f}",
+          flush=True)
+    assert got["gamma_f"] == pytest.approx(gamma_ref, rel=1e-11)
+    assert got["p_n"] == pytest.approx(float(sig[0].mean()), rel=1e-12)
+    assert got["h"] == pytest.approx(film_thickness(line, lx // 2, 0.85), abs=1e-9)
+    sim.close()
+
+
+def test_flat_films_give_a_positive_decaying_disjoining_pressure():
+    """Flat films relaxed at the frustrated couplings reach mechanical equilibrium (uniform
+    normal stress to rounding), thick films carry the tension of two free interfaces, and
+    eq. (doppiasigma) turns the thin films' excess tension into a positive disjoining pressure
+    that decreases with the film thickness."""
+    from paper_1402_6019_amd import Sim
+    from paper_1402_6019_amd.film import disjoining_from_tension, flat_film
+    lx, ly = 160, 5
+    rows = []
+    for h0 in (3.0, 4.0, 5.0, 16.0, 40.0):
+        sim = Sim(lx, ly, lbgen.flat_film(lx, ly, h0)[None], n_species=1, storage="f64",
+                  g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0))
+        sim.set_graph(1000)
+        sim.step(60000)
+        rows.append(flat_film(sim, mid=0.8555))
+        sim.close()
+    for r in rows:
+        print(r, flush=True)
+        assert r["p_n_spread"] < 1e-7 * r["p_n"]
+    h = np.array([r["h"] for r in rows])
+    g = np.array([r["gamma_f"] for r in rows])
+    assert np.all(np.diff(h) > 0)
+    assert abs(g[3] - g[4]) < 1e-3 * g[4]  # thick films: 2 gamma
+    assert np.all(g[:3] > g[4])            # thin films: excess tension
+    pi = disjoining_from_tension(h, g)
+    print(f"h {h}\nPi {pi}", flush=True)
+    assert pi[0] > pi[1] > pi[2] > 0
+    assert 1e-4 < pi[0] < 1e-2
