@@ -267,6 +267,61 @@ def test_force_closed_form_y_sinusoid():
     assert np.abs(fl["force"][0, 0]).max() < 1e-14
 
 
+def test_wetting_force_closed_form():
+    """Wetting (the wall ghost rows carry psi(rho_w)): for a uniform fluid psi between walls
+    the force vanishes except on the two rows next to each wall, where only the links that
+    land in the wall rows contribute psi (psi_w - psi) K c_y; the first belt's A-B term acts on
+    the first row only.  A dropped wall row, a wrong sign or the wall's density used in
+    place of its psi fails."""
+    lx, ly = 6, 9
+    P = Params(lx=lx, ly=ly, ns=1, walls=1, rho_wall=(1.3, 0.0), **FILM)
+    rho = 0.7
+    o = Oracle(P, rho_init=np.full((1, ly, lx), rho))
+    fl = o.fields()
+    psi = 1.0 - np.exp(-rho)
+    dpsi = (1.0 - np.exp(-1.3)) - psi
+    K = P.shell_k(0)
+    k1 = K[0] + 2 * K[1] + 2 * K[3]  # links with c_y = -1 reaching row -1 from row 0
+    k2 = K[2] + 2 * K[3] + 2 * K[4]  # links with c_y = -2 reaching rows -1, -2
+    want = np.zeros(ly)
+    want[0], want[1] = psi * dpsi * (k1 + 2 * k2), psi * dpsi * 2 * k2
+    want[-1], want[-2] = -want[0], -want[1]
+    np.testing.assert_allclose(fl["force"][0, 1], np.broadcast_to(want[:, None], (ly, lx)), rtol=1e-13, atol=1e-15)
+    assert np.abs(fl["force"][0, 0]).max() < 1e-15
+
+    # two components: self terms as above per species, plus the A-B term over the first belt
+    P2 = Params(lx=lx, ly=ly, ns=2, walls=1, g1=(-9.0, -8.0), g2=(8.1, 7.1), gab=0.587, rho0=0.83,
+                rho_wall=(0.2, 1.2))
+    ra, rb = 0.9, 0.4
+    o2 = Oracle(P2, rho_init=np.stack([np.full((ly, lx), ra), np.full((ly, lx), rb)]))
+    fl2 = o2.fields()
+    pw = lambda r: 1.0 - np.exp(-r / 0.83)
+    T1, T2 = P2.t
+    for s, (r_s, r_o, rw_s, rw_o) in enumerate(((ra, rb, 0.2, 1.2), (rb, ra, 1.2, 0.2))):
+        K = P2.shell_k(s)
+        k1 = K[0] + 2 * K[1] + 2 * K[3]
+        k2 = K[2] + 2 * K[3] + 2 * K[4]
+        d = pw(rw_s) - pw(r_s)
+        want = np.zeros(ly)
+        want[0], want[1] = pw(r_s) * d * (k1 + 2 * k2), pw(r_s) * d * 2 * k2
+        want[0] += 0.587 * r_s * (T1 + 2 * T2) * (rw_o - r_o)
+        want[-1], want[-2] = -want[0], -want[1]
+        np.testing.assert_allclose(fl2["force"][s, 1][:, 0], want, rtol=1e-13, atol=1e-15)
+
+
+def test_wall_of_the_fluid_densities_leaves_a_uniform_state_at_rest():
+    """Walls whose ghost densities equal the fluid's are invisible to the force: a uniform
+    two-component state between them stays exactly at rest."""
+    lx, ly = 6, 9
+    P = Params(lx=lx, ly=ly, ns=2, walls=1, g1=(-9.0, -8.0), g2=(8.1, 7.1), gab=0.587, rho0=0.83,
+               rho_wall=(0.9, 0.4), tau=(0.8, 1.3))
+    o = Oracle(P, rho_init=np.stack([np.full((ly, lx), 0.9), np.full((ly, lx), 0.4)]))
+    f0 = o.get_f()
+    assert np.abs(o.fields()["force"]).max() < 1e-15
+    o.step(200)
+    np.testing.assert_allclose(o.get_f(), f0, rtol=1e-14, atol=0)
+
+
 def test_force_closed_form_diagonal_sinusoid():
     """psi = a + b sin(k (x + y)) exercises every shell with both orientations:
     F_x = F_y = -psi 2 b cos(k(x+y)) [ (K1 + K5) sin k + (K2 + 2 K4) sin 2k + 3 K5 sin 3k + 2 K8 sin 4k ]."""
