@@ -85,6 +85,8 @@ def emulsion(lx, ly, fraction=0.8, seed=2, walls=False, rmin=8.0, rmax=24.0, gap
     and at least gap/2 from the boundary of its power cell (and, with walls, at least gap/2
     from the wall rows); lam is set by bisection so that the A-rich volume fraction is
     `fraction`.  Dense packings turn into polygonal cells separated by films of width ~gap.
+    When the films leave less than `fraction` of the box (small droplets, wide gap) the result
+    is the densest packing the cells allow, and info['volume_fraction'] reports what it reached.
 
     Returns (rho[2, ly, lx], info) with info = {n_drops, volume_fraction, mass_fraction, lam}.
     """
