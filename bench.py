@@ -661,7 +661,9 @@ def main():
             "note": "footprint 2 x 75.5 MB fits in the 256 MB Infinity Cache"}
 
     out = {
-        "metric": "MLUPS, 2-component D2Q9 two-belt step (FP32 populations); FP64 and BF16-deviation beside it",
+        # value: FP32 MLUPS; % of HBM peak in roofline.frac; FP64 (and BF16) beside it; the
+        # errors against the FP64 oracle in error_vs_oracle
+        "metric": "MLUPS + % HBM peak, 2-component D2Q9 two-belt step, FP32 vs FP64 at stated err",
         "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
