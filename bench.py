@@ -625,6 +625,8 @@ def main():
     ap.add_argument("--tile", type=str, default=None, help="tx,sy launch shape")
     ap.add_argument("--core", action="store_true",
                     help="headline lattice and copy only (skip the channel, batched and adjoint legs)")
+    ap.add_argument("--channel-only", action="store_true",
+                    help="run only the 4096 x 512 channel leg (served by HBM) and print it")
     ap.add_argument("--couette-study", action="store_true",
                     help="run only the Couette-cell fluidity study (half a million steps at 1040^2) and print it")
     args = ap.parse_args()
@@ -636,6 +638,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.couette_study:
         print(json.dumps(couette_study()), flush=True)
+        return
+    if args.channel_only:
+        print(json.dumps(channel_beyond_cache(args.steps)), flush=True)
         return
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
 
