@@ -83,12 +83,12 @@ constexpr int kStoreStreaming = 16 | 2;     // SC1 | NT
 // step works on deviations directly (bload/bstore), which costs nothing and keeps the
 // rounding of each stored value relative to |d_l| instead of |f_l|.
 // L is the type a pulled population is held in between its load and its use (the register
-// FIFO of the step); dec() turns it into the arithmetic type.
+// FIFO of the step); dec(v, s) turns it into species s's value in the arithmetic type.
 template <> struct Codec<MODE_F64> {
   using S = double;
   using R = double;
   using L = double;
-  __device__ static R dec(L v) { return v; }
+  __device__ static R dec(L v, int) { return v; }
   __device__ static R load(const S *p, R wref) { return *p + wref; }
   __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
@@ -117,7 +117,7 @@ template <> struct Codec<MODE_F32> {
   using S = float;
   using R = float;
   using L = float;
-  __device__ static R dec(L v) { return v; }
+  __device__ static R dec(L v, int) { return v; }
   __device__ static R load(const S *p, R wref) { return *p + wref; }
   __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
@@ -147,12 +147,14 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // BF16: stored value = bf16(d_l), arithmetic in FP32.
-// BF16: the FIFO keeps the raw 16-bit values (two to a register), decoded where used.
+// BF16: the FIFO keeps the raw 32-bit word that holds both species of a site (one register
+// for the pair: bload2 hands the same word to both), decoded where used: species 0 is the low
+// half, species 1 the high half.
 template <> struct Codec<MODE_BF16> {
   using S = uint16_t;
   using R = float;
-  using L = uint16_t;
-  __device__ static R dec(L v) { return decode(v); }
+  using L = uint32_t;
+  __device__ static R dec(L v, int s) { return __uint_as_float(s == 0 ? v << 16 : v & 0xffff0000u); }
   __device__ static R decode(uint32_t h) { return __uint_as_float(h << 16); }
   // the hardware conversion (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
   __device__ static uint16_t encode(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
@@ -169,8 +171,8 @@ template <> struct Codec<MODE_BF16> {
   __device__ static R rcp(R v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
   __device__ static void bload2(Rsrc r, uint32_t voff, uint32_t soff, L &a, L &b) {
     const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-    a = uint16_t(v);
-    b = uint16_t(v >> 16);
+    a = v;
+    b = v;
   }
   template <int AUX>
   __device__ static void bstore2(Rsrc r, uint32_t voff, uint32_t soff, R a, R b) {
@@ -439,7 +441,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       for (int s = 0; s < NS; ++s) {
         R a9[9];
 #pragma unroll
-        for (int l = 0; l < 9; ++l) a9[l] = C::dec(A[s][l]);
+        for (int l = 0; l < 9; ++l) a9[l] = C::dec(A[s][l], s);
         rh.v[s] = rref[s] + sum9(a9);
         ps.v[s] = psi0 * (R(1) - C::expo(rh.v[s] * nirho0));
       }
@@ -458,7 +460,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   auto halo_stage = [&](int buf, const L (&hv)[2]) {
     if (tid < NI) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) hstage[(buf * NI + tid) * NS + s] = C::dec(hv[s]);
+      for (int s = 0; s < NS; ++s) hstage[(buf * NI + tid) * NS + s] = C::dec(hv[s], s);
     }
   };
   auto halo_finish = [&](int buf, int slot, int r) {
@@ -582,7 +584,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int l = 0; l < 9; ++l) f[s][l] = C::dec(fraw[s][l]);
+      for (int l = 0; l < 9; ++l) f[s][l] = C::dec(fraw[s][l], s);
     R drho[NS], rho[NS], jx[NS], jy[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
