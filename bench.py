@@ -644,8 +644,8 @@ def main():
                     help="run only the Couette-cell fluidity study (half a million steps at 1040^2) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
-              f"not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is "
+              f"described, not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
