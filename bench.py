@@ -123,6 +123,50 @@ def channel_beyond_cache(steps):
     return out
 
 
+def channel_long_run(steps=50000, average_last=25000, every=100):
+    """The confined channel 4096 x 512 run for `steps` steps in each storage mode from the same
+    initial state, with the velocity, density and shear-stress profiles averaged over the last
+    `average_last` steps (a profile every `every` steps); FP32 and BF16 are compared with FP64,
+    whose step matches the FP64 oracle to 1e-12.  The emulsion flow is chaotic, so the
+    differences are those of time averages over decorrelated trajectories."""
+    import numpy as np
+    import torch
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    lx, ly = 4096, 512
+    rho, info = lbgen.emulsion(lx, ly, fraction=0.85, seed=3, walls=True)
+    kw = dict(n_species=2, walls=True, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+              body=(1e-6, 0.0), rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0,
+              rho_ref=(float(rho[0].mean()), float(rho[1].mean())))
+    avg = {}
+    for storage in ("f64", "f32", "bf16dev"):
+        t0 = time.perf_counter()
+        sim = Sim(lx, ly, rho, storage=storage, **kw)
+        sim.set_graph(every)
+        sim.step(steps - average_last)
+        st = sim.profile_stats(sim.sample_profiles(average_last // every, every))
+        torch.cuda.synchronize()
+        u, sig, ra = (st[k].cpu().numpy() for k in ("u", "sigma", "rho_a"))
+        avg[storage] = {"u": u, "sigma": sig, "rho_a": ra, "seconds": time.perf_counter() - t0}
+        sim.close()
+    ref = avg["f64"]
+    out = {"workload": f"confined emulsion channel {lx}x{ly}, fraction 0.85, seed 3, g = 1e-6, {steps} steps, "
+                       f"profiles averaged over the last {average_last} (every {every})",
+           "f64": {"flow_rate": float(ref["u"].sum()), "u_max": float(ref["u"].max()),
+                   "wall_stress_bot_top": [float(ref["sigma"][0]), float(-ref["sigma"][-1])],
+                   "seconds": ref["seconds"]}}
+    for storage in ("f32", "bf16dev"):
+        a = avg[storage]
+        out[storage] = {
+            "u_rel_err": float(np.abs(a["u"] - ref["u"]).max() / np.abs(ref["u"]).max()),
+            "rho_a_rel_err": float(np.abs(a["rho_a"] - ref["rho_a"]).max() / np.abs(ref["rho_a"]).max()),
+            "flow_rate_rel_err": float(abs(a["u"].sum() - ref["u"].sum()) / abs(ref["u"].sum())),
+            "wall_stress_rel_err": [float(abs(a["sigma"][0] - ref["sigma"][0]) / abs(ref["sigma"][0])),
+                                    float(abs(a["sigma"][-1] - ref["sigma"][-1]) / abs(ref["sigma"][-1]))],
+            "seconds": a["seconds"]}
+    return out
+
+
 def batched_sweep(steps, n=64):
     """Uneven sweep of n independent confined emulsion channels (Ly ~ U{64..512},
     Lx ~ U{256..2048}, per-instance couplings and body force drawn from seed 4, volume
@@ -711,6 +755,7 @@ def main():
         "tiles": {k: v["tile"] for k, v in res.items()},
         "copy_reference": copy,
         "beyond_infinity_cache": None if args.core else channel_beyond_cache(max(50, args.steps // 4)),
+        "channel_50k_averages": None if args.core else channel_long_run(),
         "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
         "couette_cell": None if args.core else couette_cell(max(200, args.steps // 2)),
         "auxiliary_passes": None if args.core else auxiliary_passes(rho, kw),
