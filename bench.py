@@ -583,25 +583,27 @@ def emulsion_errors(rho, kw, ref_by_t):
     return out
 
 
-def channel_errors(steps=300, window=200):
-    """Confined emulsion in a 256 x 128 channel (walls, wetting, body force 1e-5): rho, u after
-    `steps` steps and the wall stress averaged over the last `window` steps, each GPU storage
-    mode against the oracle."""
-    import numpy as np
+CHANNEL_ERR = dict(lx=256, ly=128, steps=300, window=200)
+
+
+def channel_err_case():
+    """Confined emulsion in a 256 x 128 channel (walls, wetting, body force 1e-5)."""
     import lbgen
-    from oracle import Oracle, Params
-    from paper_1402_6019_amd import Sim
-    lx, ly = 256, 128
-    rho, _ = lbgen.emulsion(lx, ly, fraction=0.85, seed=4, walls=True, rmin=6, rmax=14)
+    rho, _ = lbgen.emulsion(CHANNEL_ERR["lx"], CHANNEL_ERR["ly"], fraction=0.85, seed=4, walls=True, rmin=6, rmax=14)
     kw = dict(n_species=2, walls=True, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
               body=(1e-5, 0.0), rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0)
-    P = Params(lx=lx, ly=ly, ns=2, walls=1, g1=kw["g1"], g2=kw["g2"], gab=kw["gab"], body=kw["body"],
-               rho_wall=kw["rho_wall"], tau=kw["tau"], psi0=kw["psi0"], rho0=kw["rho0"])
-    orc = Oracle(P, rho_init=rho)
-    orc.step(steps - window)
-    recs = orc.step(window, record=True)
-    ref = orc.fields()
-    ref_w = np.array([recs[:, 4].mean(), recs[:, 5].mean()])
+    return rho, kw
+
+
+def channel_errors(oracle_ref):
+    """The channel of channel_err_case: rho, u after `steps` steps and the wall stress averaged
+    over the last `window` steps, each GPU storage mode against the oracle's (computed in the
+    CPU baseline leg)."""
+    import numpy as np
+    from paper_1402_6019_amd import Sim
+    lx, ly, steps, window = (CHANNEL_ERR[k] for k in ("lx", "ly", "steps", "window"))
+    rho, kw = channel_err_case()
+    ref, ref_w = oracle_ref
     out = {"workload": f"confined emulsion {lx}x{ly}, walls + wetting, g = 1e-5, fraction 0.85, seed 4",
            "steps": steps, "stress_window": window}
     for storage in ("f64", "f32", "bf16dev"):
@@ -620,7 +622,10 @@ def channel_errors(steps=300, window=200):
 
 
 def cpu_baseline(rho, kw, budget_s=15.0):
-    """The FP64 CPU oracle, as it stands, on the same lattice for a bounded number of steps."""
+    """The FP64 CPU oracle, as it stands, on the same lattice for a bounded number of steps; its
+    fields at a few times, and the oracle's run of the small channel, are the references of the
+    GPU errors.  Every use of the oracle in this script is in this leg."""
+    import numpy as np
     import oracle
     from oracle import Oracle, Params
     P = Params(lx=LX, ly=LY, ns=2, walls=0, g1=kw["g1"], g2=kw["g2"], gab=kw["gab"], body=kw["body"],
@@ -645,6 +650,14 @@ def cpu_baseline(rho, kw, budget_s=15.0):
     orc.step(3)
     dt1 = time.perf_counter() - t1
     oracle.set_threads(threads)
+    # the small channel's reference
+    crho, ckw = channel_err_case()
+    cP = Params(lx=CHANNEL_ERR["lx"], ly=CHANNEL_ERR["ly"], ns=2, walls=1, g1=ckw["g1"], g2=ckw["g2"], gab=ckw["gab"],
+                body=ckw["body"], rho_wall=ckw["rho_wall"], tau=ckw["tau"], psi0=ckw["psi0"], rho0=ckw["rho0"])
+    corc = Oracle(cP, rho_init=crho)
+    corc.step(CHANNEL_ERR["steps"] - CHANNEL_ERR["window"])
+    recs = corc.step(CHANNEL_ERR["window"], record=True)
+    chan_ref = (corc.fields(), np.array([recs[:, 4].mean(), recs[:, 5].mean()]))
     return {
         "value": LX * LY * n / dt / 1e6,
         "unit": "MLUPS",
@@ -653,7 +666,7 @@ def cpu_baseline(rho, kw, budget_s=15.0):
         "sample": f"{n} steps (steps 100..{100 + n}) of the same 1024x1024 two-component lattice from the "
                   f"same initial state ({dt:.1f} s, FP64, OpenMP over rows)",
         "one_thread_mlups": LX * LY * 3 / dt1 / 1e6,
-    }, refs
+    }, refs, chan_ref
 
 
 def traffic_from_profile(kernel_hash, storage, tile):
@@ -764,10 +777,10 @@ def main():
         "kernel_source_hash": khash,
     }
     if not args.no_cpu:
-        base, refs = cpu_baseline(rho, kw)
+        base, refs, chan_ref = cpu_baseline(rho, kw)
         out["cpu_baseline"] = base
         out["error_vs_oracle"] = {"emulsion_1024_by_step": emulsion_errors(rho, kw, refs),
-                                  "channel_256x128": channel_errors()}
+                                  "channel_256x128": channel_errors(chan_ref)}
     print(json.dumps(out), flush=True)
 
 
