@@ -126,9 +126,10 @@ def channel_beyond_cache(steps):
 def channel_long_run(steps=50000, average_last=25000, every=100):
     """The confined channel 4096 x 512 run for `steps` steps in each storage mode from the same
     initial state, with the velocity, density and shear-stress profiles averaged over the last
-    `average_last` steps (a profile every `every` steps); FP32 and BF16 are compared with FP64,
-    whose step matches the FP64 oracle to 1e-12.  The emulsion flow is chaotic, so the
-    differences are those of time averages over decorrelated trajectories."""
+    `average_last` steps (a profile every `every` steps); FP32 and BF16 (rounded to nearest, and
+    stochastically) are compared with FP64, whose step matches the FP64 oracle to 1e-12.  The
+    emulsion flow is chaotic, so the differences are those of time averages over decorrelated
+    trajectories."""
     import numpy as np
     import torch
     import lbgen
@@ -139,15 +140,18 @@ def channel_long_run(steps=50000, average_last=25000, every=100):
               body=(1e-6, 0.0), rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0,
               rho_ref=(float(rho[0].mean()), float(rho[1].mean())))
     avg = {}
-    for storage in ("f64", "f32", "bf16dev"):
+    for name, storage, rounding in (("f64", "f64", None), ("f32", "f32", None), ("bf16dev", "bf16dev", None),
+                                    ("bf16dev_stochastic", "bf16dev", "stochastic")):
         t0 = time.perf_counter()
         sim = Sim(lx, ly, rho, storage=storage, **kw)
+        if rounding:
+            sim.set_rounding(rounding)
         sim.set_graph(every)
         sim.step(steps - average_last)
         st = sim.profile_stats(sim.sample_profiles(average_last // every, every))
         torch.cuda.synchronize()
         u, sig, ra = (st[k].cpu().numpy() for k in ("u", "sigma", "rho_a"))
-        avg[storage] = {"u": u, "sigma": sig, "rho_a": ra, "seconds": time.perf_counter() - t0}
+        avg[name] = {"u": u, "sigma": sig, "rho_a": ra, "seconds": time.perf_counter() - t0}
         sim.close()
     ref = avg["f64"]
     out = {"workload": f"confined emulsion channel {lx}x{ly}, fraction 0.85, seed 3, g = 1e-6, {steps} steps, "
@@ -155,9 +159,9 @@ def channel_long_run(steps=50000, average_last=25000, every=100):
            "f64": {"flow_rate": float(ref["u"].sum()), "u_max": float(ref["u"].max()),
                    "wall_stress_bot_top": [float(ref["sigma"][0]), float(-ref["sigma"][-1])],
                    "seconds": ref["seconds"]}}
-    for storage in ("f32", "bf16dev"):
-        a = avg[storage]
-        out[storage] = {
+    for name in ("f32", "bf16dev", "bf16dev_stochastic"):
+        a = avg[name]
+        out[name] = {
             "u_rel_err": float(np.abs(a["u"] - ref["u"]).max() / np.abs(ref["u"]).max()),
             "rho_a_rel_err": float(np.abs(a["rho_a"] - ref["rho_a"]).max() / np.abs(ref["rho_a"]).max()),
             "flow_rate_rel_err": float(abs(a["u"].sum() - ref["u"].sum()) / abs(ref["u"].sum())),

@@ -69,6 +69,12 @@ enum lb_storage {
 /* Output type of lb_moments. */
 enum lb_dtype { LB_OUT_F64 = 0, LB_OUT_F32 = 1 };
 
+/* Rounding of BF16 population stores (lb_set_rounding). */
+enum lb_rounding {
+  LB_ROUND_NEAREST = 0,   /* round to nearest even (default) */
+  LB_ROUND_STOCHASTIC = 1 /* unbiased random rounding, reproducible from (site, plane, step) */
+};
+
 /* Population store policy of the plain and reducing step kernels (lb_set_store_policy). */
 enum lb_store_policy {
   LB_STORES_AUTO = 0,          /* by footprint: streaming once both buffers exceed 256 MiB */
@@ -209,6 +215,16 @@ int lb_get_tile(const lb_ctx *ctx, int32_t *tx, int32_t *sy);
    force one.  All variants give bitwise identical results; only their speed differs.
    Captured graphs are rebuilt.  Host call; LB_EINVAL for any other value. */
 int lb_set_store_policy(lb_ctx *ctx, int32_t policy);
+
+/* Rounding of the population stores of a BF16-deviation context (enum lb_rounding).  With
+   LB_ROUND_NEAREST (default) every store rounds to nearest, and an increment below half a
+   BF16 step of the stored deviation (a weak body force) is lost at every step.  With
+   LB_ROUND_STOCHASTIC each store rounds away from zero with probability equal to the dropped
+   fraction, using bits hashed from the site, the plane and the time step: unbiased, and
+   bitwise reproducible for any launch shape and under graph replay.  Device memory for one
+   double is allocated on first use.  LB_EINVAL for other storage modes; lb_adjoint refuses
+   stochastically rounding contexts (it recomputes states).  Host call. */
+int lb_set_rounding(lb_ctx *ctx, int32_t mode);
 
 /* Replay plain steps from captured HIP graphs: with steps > 0 (even) and no reductions
    (lb_set_reduce_every k = 0), lb_step runs whole groups of `steps` launches as one graph

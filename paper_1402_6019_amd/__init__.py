@@ -136,6 +136,15 @@ class Sim:
     def set_tile(self, tx, sy):
         self._chk(self._lib.lb_set_tile(self._h, int(tx), int(sy)))
 
+    ROUNDINGS = {"nearest": 0, "stochastic": 1}
+
+    def set_rounding(self, mode):
+        """Rounding of the BF16 population stores: "nearest" (default) or "stochastic"
+        (unbiased, reproducible; keeps increments far below one BF16 step on average)."""
+        if mode not in self.ROUNDINGS:
+            raise ValueError(f"mode must be one of {sorted(self.ROUNDINGS)}")
+        self._chk(self._lib.lb_set_rounding(self._h, self.ROUNDINGS[mode]))
+
     STORE_POLICIES = {"auto": 0, "write_through": 1, "streaming": 2}
 
     def set_store_policy(self, policy):

@@ -63,6 +63,7 @@ SIGNATURES = {
     "lb_time": (_i64, [_vp]),
     "lb_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
     "lb_set_store_policy": (ctypes.c_int, [_vp, _i32]),
+    "lb_set_rounding": (ctypes.c_int, [_vp, _i32]),
     "lb_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "lb_set_graph": (ctypes.c_int, [_vp, _i32]),
     "lb_set_couplings": (ctypes.c_int, [_vp, ctypes.POINTER(LbCouplings)]),

@@ -41,6 +41,8 @@ struct lb_ctx {
   int n_cu = 256;  // compute units of the device the context runs on
   int reduce_every = 0;
   int store_policy = LB_STORES_AUTO;
+  int rounding = LB_ROUND_NEAREST;  // BF16 stores: nearest or stochastic
+  double *d_tbase = nullptr;        // step at which a graph replay starts (stochastic rounding)
   int64_t t = 0;
   double *d_partials = nullptr;  // [partial_cap][RED_N], grown to the largest launch
   int partial_cap = 0;
@@ -96,8 +98,14 @@ void fill_step_args(const lb_ctx *c, StepArgs &a) {
                                                        : (c->store_policy == LB_STORES_STREAMING ? 1 : 0);
 }
 
-// One plain step launch (no reductions) from buffer `from` to the other one, on stream st.
-hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st) {
+// Kernel variant of the passes that store populations.
+int step_mode(const lb_ctx *c) {
+  return c->lat.storage == LB_BF16DEV && c->rounding == LB_ROUND_STOCHASTIC ? MODE_BF16SR : c->lat.storage;
+}
+
+// One plain step launch (no reductions) from buffer `from` to the other one, on stream st,
+// as time step t_step (+ *t_base if t_base is set: a graph replay's first step).
+hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st, uint32_t t_step, const double *t_base) {
   int nseg = 0;
   const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
   StepArgs a;
@@ -105,7 +113,9 @@ hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st) {
   a.nseg = nseg;
   a.src = c->pop[from];
   a.dst = c->pop[from ^ 1];
-  return launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
+  a.t_step = t_step;
+  a.t_base = t_base;
+  return launch_step(step_mode(c), c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
 }
 
 // Canonical FP64 pre-collision populations of buffer `from` into dst, and the reverse step's
@@ -181,7 +191,8 @@ int run_step_kernel(lb_ctx *c, int what, void *out_rho, void *out_u, int out_f32
   a.out_rho = out_rho;
   a.out_u = out_u;
   a.out_f32 = out_f32;
-  hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, what, c->tx, nb, a, c->stream);
+  a.t_step = (uint32_t)c->t;
+  hipError_t e = launch_step(step_mode(c), c->lat.n_species, c->lat.walls, what, c->tx, nb, a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
   if (reduce) {
     e = launch_reduce(c->d_partials, nb, c->d_totals, c->d_acc, 0, 1.0 / c->lat.lx, c->stream);
@@ -342,7 +353,11 @@ int lb_step(lb_ctx *c, int64_t n) {
     while (n >= c->graph.steps) {
       hipGraphExec_t g = nullptr;
       const int from = c->cur;
-      hipError_t e = c->graph.get(from, [&](int k, hipStream_t st) { return launch_plain_step(c, from ^ (k & 1), st); }, &g);
+      const double *tb = c->rounding == LB_ROUND_STOCHASTIC ? c->d_tbase : nullptr;
+      hipError_t e = c->graph.get(
+          from, [&](int k, hipStream_t st) { return launch_plain_step(c, from ^ (k & 1), st, (uint32_t)k, tb); }, &g);
+      // the replay's steps are t + k: the base goes to device memory (a fill kernel, outside the graph)
+      if (e == hipSuccess && tb) e = launch_fill(c->d_tbase, (double)c->t, 1, c->stream);
       if (e == hipSuccess) e = hipGraphLaunch(g, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "step graph");
       c->t += c->graph.steps;
@@ -513,6 +528,21 @@ int lb_set_store_policy(lb_ctx *c, int32_t policy) {
   return LB_OK;
 }
 
+int lb_set_rounding(lb_ctx *c, int32_t mode) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (mode != LB_ROUND_NEAREST && mode != LB_ROUND_STOCHASTIC)
+    return fail(c, LB_EINVAL, "mode must be LB_ROUND_NEAREST or LB_ROUND_STOCHASTIC");
+  if (mode == LB_ROUND_STOCHASTIC && c->lat.storage != LB_BF16DEV)
+    return fail(c, LB_EINVAL, "stochastic rounding applies to BF16 storage only");
+  if (mode == LB_ROUND_STOCHASTIC && !c->d_tbase) {
+    hipError_t e = hipMalloc(&c->d_tbase, sizeof(double));
+    if (e != hipSuccess) return fail(c, LB_ENOMEM, std::string("step base: ") + hipGetErrorString(e));
+  }
+  c->rounding = mode;
+  c->graph.clear();  // captured launches carry the old kernel variant
+  return LB_OK;
+}
+
 int lb_set_couplings(lb_ctx *c, const lb_couplings *cpl) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (!cpl) return fail(c, LB_EINVAL, "null couplings");
@@ -597,7 +627,7 @@ int lb_autotune(lb_ctx *c, int32_t trial_steps, int32_t *tx_out, int32_t *sy_out
     if (sy > c->lat.ly || grid_blocks(c, tx, sy, nullptr) > kMaxBlocks) return LB_OK;
     c->tx = tx;
     c->sy = sy;
-    const double ms = time_launches(c->stream, 2, trial_steps, [&]() { return launch_plain_step(c, c->cur, c->stream); });
+    const double ms = time_launches(c->stream, 2, trial_steps, [&]() { return launch_plain_step(c, c->cur, c->stream, (uint32_t)c->t, nullptr); });
     if (ms < 0.0) return hip_fail(c, hipGetLastError(), "autotune trial");
     if (best < 0.0 || ms < best) {
       best = ms;
@@ -722,6 +752,8 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   if (!loss_weights || !grad) return fail(c, LB_EINVAL, "null argument");
   if (!workspace) return fail(c, LB_EINVAL, "null workspace");
   if (flags & ~LB_ADJ_FP64) return fail(c, LB_EINVAL, "unknown adjoint flags");
+  if (c->rounding != LB_ROUND_NEAREST)
+    return fail(c, LB_EINVAL, "the adjoint recomputes states and needs round-to-nearest storage");
   const AdjLayout L = adjoint_layout(c, T, every, flags);
   if (workspace_bytes < L.total) return fail(c, LB_ENOMEM, "workspace smaller than lb_adjoint_workspace_bytes()");
   int rc = poll_health(c, true);
@@ -766,7 +798,7 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
     for (int jj = 0; jj < len && er == hipSuccess; ++jj) {
       er = launch_checkpoint_fields_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.s64,
                                          ws + L.fields + (size_t)jj * L.fb, fp64, st);
-      if (er == hipSuccess && jj + 1 < len) er = launch_plain_step(c, from ^ (jj & 1), st);
+      if (er == hipSuccess && jj + 1 < len) er = launch_plain_step(c, from ^ (jj & 1), st, 0u, nullptr);
     }
     return er;
   };
@@ -835,6 +867,7 @@ void lb_destroy(lb_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->d_partials) (void)hipFree(c->d_partials);
   if (c->d_prof) (void)hipFree(c->d_prof);
+  if (c->d_tbase) (void)hipFree(c->d_tbase);
   if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->d_acc) (void)hipFree(c->d_acc);
   if (c->d_accrows) (void)hipFree(c->d_accrows);

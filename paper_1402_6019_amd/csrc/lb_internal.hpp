@@ -7,7 +7,9 @@
 
 namespace lb355 {
 
-enum StoreMode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
+// MODE_BF16SR: BF16 storage whose population stores round stochastically (the step kernels
+// only; every other kernel reads and writes it like MODE_BF16).
+enum StoreMode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2, MODE_BF16SR = 3 };
 
 // What one launch of the fused step kernel does.
 enum StepWhat {
@@ -61,6 +63,8 @@ struct StepArgs {
   int ncb;                    // profile: 64-column blocks per row in prof
   double *prof;               // profile: [ncb][ly][PROF_N]
   int stream_stores;          // both population buffers exceed the Infinity Cache: non-temporal stores
+  uint32_t t_step;            // MODE_BF16SR: time step of the launch, plus *t_base when t_base is set
+  const double *t_base;       // (graph replays: the step at which the replay starts)
   void *out_sigma;            // stress: [3][ly][lx] (xx, xy, yy)
   double *accrows;            // WHAT_STEP_ACCUM: [gridDim.x][ACC_N] running sums
 };

@@ -144,6 +144,17 @@ template <> struct Codec<MODE_F32> {
 };
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Integer hash for the stochastic rounding bits (a 32-bit xorshift-multiply mixer; any
+// well-mixed function of (site, plane, step) would do).
+__device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // BF16: stored value = bf16(d_l), arithmetic in FP32.
@@ -151,6 +162,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // for the pair: bload2 hands the same word to both), decoded where used: species 0 is the low
 // half, species 1 the high half.
 template <> struct Codec<MODE_BF16> {
+  static constexpr bool kStochastic = false;
   using S = uint16_t;
   using R = float;
   using L = uint32_t;
@@ -180,6 +192,28 @@ template <> struct Codec<MODE_BF16> {
     const f32x2 v = {a, b};
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2)), r, voff,
                                           soff, AUX);
+  }
+};
+
+// BF16 with stochastic rounding at the population stores: the 16 bits that BF16 drops are
+// compared with 16 random bits, so a value rounds away from zero with probability equal to
+// the dropped fraction.  The rounding is unbiased, so increments far below one BF16 step (a
+// weak body force) still accumulate on average.  Non-finite values take the nearest rounding.
+template <> struct Codec<MODE_BF16SR> : Codec<MODE_BF16> {
+  static constexpr bool kStochastic = true;
+  __device__ static uint32_t round_sr(float v, uint32_t r16) {
+    const uint32_t b = __float_as_uint(v);
+    if ((b & 0x7f800000u) == 0x7f800000u) return encode(v);
+    return (b + r16) >> 16;  // magnitude bits round up with probability (b & 0xffff) / 2^16
+  }
+  template <int AUX>
+  __device__ static void bstore_sr(Rsrc r, uint32_t voff, uint32_t soff, R v, uint32_t rnd) {
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)round_sr(v, rnd & 0xffffu), r, voff, soff, AUX);
+  }
+  template <int AUX>
+  __device__ static void bstore2_sr(Rsrc r, uint32_t voff, uint32_t soff, R a, R b, uint32_t rnd) {
+    __builtin_amdgcn_raw_buffer_store_b32(round_sr(a, rnd & 0xffffu) | (round_sr(b, rnd >> 16) << 16), r, voff, soff,
+                                          AUX);
   }
 };
 
@@ -373,6 +407,12 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   // last lead row the march needs (two beyond the segment's far end)
   const int ylast = dir > 0 ? yB + 1 : yA - 2;
   const int tid = threadIdx.x;
+  // stochastic rounding: a seed per time step
+  uint32_t tseed = 0;
+  if constexpr (MODE == MODE_BF16SR) {
+    const uint32_t t = a.t_step + (a.t_base ? (uint32_t)(long long)*a.t_base : 0u);
+    tseed = uni(mix32(t * 0x9e3779b9u + 0x632be5abu));
+  }
 
   // Per-species constants in the arithmetic type.
   R K1[NS], K2[NS], K4[NS], K5[NS], K8[NS], tau[NS], om[NS], rref[NS], psiw[NS], rhow[NS];
@@ -876,15 +916,22 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     }
     if (STORE) {
       const Rsrc rd = make_rsrc(dst, buf_b);
-      auto store_row = [&](auto policy) {
-        constexpr int AUX = decltype(policy)::value;
+      if constexpr (MODE == MODE_BF16SR) {
+        // random bits from (site, plane, step): the same for every launch shape
+        const uint32_t hs = mix32((uint32_t)(y * lx + (x0 + tid)) ^ tseed);
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
-          if (NS == 2) C::template bstore2<AUX>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
-          else C::template bstore<AUX>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
+          const uint32_t rnd = mix32(hs + (uint32_t)l * 0x9e3779b9u);
+          if (NS == 2) C::template bstore2_sr<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l], rnd);
+          else C::template bstore_sr<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], rnd);
         }
-      };
-      store_row(std::integral_constant<int, STP>{});
+      } else {
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+          if (NS == 2) C::template bstore2<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
+          else C::template bstore<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
+        }
+      }
     }
 
     if (ACCUM && col_ok) {
@@ -1370,11 +1417,42 @@ int step_blocks_per_cu(int mode, int ns, int walls, int tx) {
   return 1;
 }
 
+// The stochastically rounding BF16 variant exists for the passes that store populations.
+template <int NS, bool WALLS>
+static hipError_t launch_step_sr_t(int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
+  constexpr int M = MODE_BF16SR;
+  const size_t lds = step_lds_bytes(M, NS, tx);
+  switch (what) {
+    case WHAT_STEP:
+      if (a.stream_stores)
+        hipLaunchKernelGGL((step_kernel<M, NS, WALLS, WHAT_STEP, kStoreStreaming>), dim3(nb), dim3(tx), lds, st, a);
+      else
+        hipLaunchKernelGGL((step_kernel<M, NS, WALLS, WHAT_STEP>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_STEP_ACCUM:
+      if (a.stream_stores)
+        hipLaunchKernelGGL((step_kernel<M, NS, WALLS, WHAT_STEP_ACCUM, kStoreStreaming>), dim3(nb), dim3(tx), lds, st, a);
+      else
+        hipLaunchKernelGGL((step_kernel<M, NS, WALLS, WHAT_STEP_ACCUM>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_OBSERVE:
+      hipLaunchKernelGGL((step_kernel<M, NS, WALLS, WHAT_OBSERVE>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st) {
   switch (mode) {
     case MODE_F64: return launch_step_m<MODE_F64>(ns, walls, what, tx, nb, a, st);
     case MODE_F32: return launch_step_m<MODE_F32>(ns, walls, what, tx, nb, a, st);
     case MODE_BF16: return launch_step_m<MODE_BF16>(ns, walls, what, tx, nb, a, st);
+    case MODE_BF16SR:
+      if (what != WHAT_STEP && what != WHAT_STEP_ACCUM && what != WHAT_OBSERVE)
+        return launch_step_m<MODE_BF16>(ns, walls, what, tx, nb, a, st);
+      if (ns == 1) return walls ? launch_step_sr_t<1, true>(what, tx, nb, a, st) : launch_step_sr_t<1, false>(what, tx, nb, a, st);
+      return walls ? launch_step_sr_t<2, true>(what, tx, nb, a, st) : launch_step_sr_t<2, false>(what, tx, nb, a, st);
   }
   return hipErrorInvalidValue;
 }
