@@ -14,8 +14,8 @@
 // segment of sy rows, and marches through its rows, down for even segments and up for odd
 // ones.  The force at row y needs psi at rows y-2..y+2 and columns x-2..x+2, so the
 // workgroup keeps a six-row ring of psi_s (and rho_s for the A-B term) for its tx + 4
-// columns in LDS: each iteration computes the leading row of the ring (the pulled moments
-// of tx + 4 sites), synchronises once, then updates row y from the ring.  Interior columns
+// columns in LDS: each iteration synchronises once, computes the leading row of the ring
+// (the pulled moments of tx + 4 sites), then updates row y from the ring.  Interior columns
 // are computed once per row; only the two halo columns on each side and three rows beyond
 // each end of a segment are pulled again by the neighbours.  Six ring slots make one
 // barrier per row sufficient: the slot written in iteration r+1 is never among the five
@@ -354,13 +354,14 @@ __device__ inline T wave_sum(T v) {
 // Fused step
 // ---------------------------------------------------------------------------------------
 //
-// Software pipeline of one row iteration r (lead row r, output row y = r - 2):
-//   1. psi, rho of lead row r from populations already in registers  -> LDS ring slot
-//   2. issue the loads of output row y (stage 2 input)
-//   3. issue the loads of lead row r + 1 (next iteration's step 1)
-//   4. barrier
-//   5. force + collision of row y from the ring and the stage-2 registers, store
-// so the memory latency of both load batches overlaps the arithmetic of steps 1 and 5.
+// Software pipeline of one row iteration, output row y (rows named in march order):
+//   1. stage the halo items of lead row y+3 (loaded in the previous iteration) in LDS
+//   2. issue the loads of lead row y+4 (populations and halo items) into the register FIFO
+//   3. barrier
+//   4. psi, rho of lead row y+3 from the FIFO (and the staged halo items) -> LDS ring slot
+//   5. force + collision of row y from the ring and row y's populations in the FIFO, store
+// Every population is loaded once, an iteration before its first use in step 4, and stays in
+// the FIFO until its own row is updated, so the loads' latency overlaps steps 3 to 5.
 
 // One tile: strip `strip` (tx = blockDim.x columns) and segment `seg` (a.sy rows) of the
 // lattice described by a, read from src and written to dst.  part: this tile's row of
