@@ -355,6 +355,11 @@ int lb_batch_step(lb_batch *b, int64_t n);
 /* As lb_set_reduce_every, for every instance. */
 int lb_batch_set_reduce_every(lb_batch *b, int32_t k);
 
+/* lb_set_rounding for a batch: every instance's BF16 stores rounded to nearest or
+   stochastically; an instance's bits equal those of a single context of the same lattice
+   (the hash uses the instance's own site indices and the batch's step count). */
+int lb_batch_set_rounding(lb_batch *b, int32_t mode);
+
 /* As lb_set_graph: graphs of `steps` batch launches. */
 int lb_batch_set_graph(lb_batch *b, int32_t steps);
 

@@ -380,6 +380,12 @@ class Batch:
     def set_graph(self, steps):
         self._chk(self._lib.lb_batch_set_graph(self._h, int(steps)))
 
+    def set_rounding(self, mode):
+        """Rounding of every instance's BF16 population stores: "nearest" or "stochastic"."""
+        if mode not in Sim.ROUNDINGS:
+            raise ValueError(f"mode must be one of {sorted(Sim.ROUNDINGS)}")
+        self._chk(self._lib.lb_batch_set_rounding(self._h, Sim.ROUNDINGS[mode]))
+
     def set_tile(self, tx, sy, grid=0):
         self._chk(self._lib.lb_batch_set_tile(self._h, int(tx), int(sy), int(grid)))
 

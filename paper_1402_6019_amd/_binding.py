@@ -85,6 +85,7 @@ SIGNATURES = {
     "lb_batch_set_reduce_every": (ctypes.c_int, [_vp, _i32]),
     "lb_batch_set_graph": (ctypes.c_int, [_vp, _i32]),
     "lb_batch_set_tile": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
+    "lb_batch_set_rounding": (ctypes.c_int, [_vp, _i32]),
     "lb_batch_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "lb_batch_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), _dp]),
     "lb_batch_moments": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32]),

@@ -43,6 +43,8 @@ struct lb_batch {
   int n_cu = 256;
   int reduce_every = 0;
   int64_t t = 0;
+  int rounding = LB_ROUND_NEAREST;  // BF16 stores: nearest or stochastic
+  double *d_tbase = nullptr;        // step at which a graph replay starts (stochastic rounding)
   StepArgs *d_args = nullptr;
   TileDesc *d_tiles = nullptr;
   ReduceJob *d_jobs = nullptr;
@@ -169,7 +171,8 @@ int launch_grid(const lb_batch *b, int ntiles) {
 
 // One launch over tiles [first, first + count) from buffer `from` to the other one.
 hipError_t launch_tiles(const lb_batch *b, int what, int from, int first, int count, hipStream_t st,
-                        void *out_rho = nullptr, void *out_u = nullptr, int out_f32 = 0) {
+                        void *out_rho = nullptr, void *out_u = nullptr, int out_f32 = 0, uint32_t t_step = 0,
+                        const double *t_base = nullptr) {
   BatchArgs a;
   std::memset(&a, 0, sizeof(a));
   a.inst = b->d_args;
@@ -184,7 +187,10 @@ hipError_t launch_tiles(const lb_batch *b, int what, int from, int first, int co
   a.out_u = out_u;
   a.out_f32 = out_f32;
   a.stream_stores = streaming_stores(b->footprint);
-  return launch_batch_step(b->storage, b->ns, b->walls, what, b->tx, launch_grid(b, count), a, st);
+  a.t_step = t_step;
+  a.t_base = t_base;
+  const int mode = b->storage == LB_BF16DEV && b->rounding == LB_ROUND_STOCHASTIC ? MODE_BF16SR : b->storage;
+  return launch_batch_step(mode, b->ns, b->walls, what, b->tx, launch_grid(b, count), a, st);
 }
 
 int poll(lb_batch *b, bool wait) {
@@ -348,8 +354,15 @@ int lb_batch_step(lb_batch *b, int64_t n) {
     while (n >= b->graph.steps) {
       hipGraphExec_t g = nullptr;
       const int from = b->cur;
+      const double *tb = b->rounding == LB_ROUND_STOCHASTIC ? b->d_tbase : nullptr;
       hipError_t e = b->graph.get(
-          from, [&](int k, hipStream_t st) { return launch_tiles(b, WHAT_STEP, from ^ (k & 1), 0, nt, st); }, &g);
+          from,
+          [&](int k, hipStream_t st) {
+            return launch_tiles(b, WHAT_STEP, from ^ (k & 1), 0, nt, st, nullptr, nullptr, 0, (uint32_t)k, tb);
+          },
+          &g);
+      // the replay's steps are t + k: the base goes to device memory (a fill kernel, outside the graph)
+      if (e == hipSuccess && tb) e = launch_fill(b->d_tbase, (double)b->t, 1, b->stream);
       if (e == hipSuccess) e = hipGraphLaunch(g, b->stream);
       if (e != hipSuccess) return bhip(b, e, "step graph");
       b->t += b->graph.steps;
@@ -359,7 +372,8 @@ int lb_batch_step(lb_batch *b, int64_t n) {
   bool reduced = false;
   for (int64_t k = 0; k < n; ++k) {
     const bool red = b->reduce_every > 0 && (b->t % b->reduce_every) == 0;
-    hipError_t e = launch_tiles(b, red ? WHAT_STEP_ACCUM : WHAT_STEP, b->cur, 0, nt, b->stream);
+    hipError_t e = launch_tiles(b, red ? WHAT_STEP_ACCUM : WHAT_STEP, b->cur, 0, nt, b->stream, nullptr, nullptr, 0,
+                                (uint32_t)b->t);
     if (e != hipSuccess) return bhip(b, e, "batch step launch");
     reduced |= red;
     if (red) ++b->acc_pending;
@@ -382,6 +396,21 @@ int lb_batch_set_reduce_every(lb_batch *b, int32_t k) {
   if (!b) return bfail(nullptr, LB_EINVAL, "null context");
   if (k < 0) return bfail(b, LB_EINVAL, "k must be >= 0");
   b->reduce_every = k;
+  return LB_OK;
+}
+
+int lb_batch_set_rounding(lb_batch *b, int32_t mode) {
+  if (!b) return bfail(nullptr, LB_EINVAL, "null context");
+  if (mode != LB_ROUND_NEAREST && mode != LB_ROUND_STOCHASTIC)
+    return bfail(b, LB_EINVAL, "mode must be LB_ROUND_NEAREST or LB_ROUND_STOCHASTIC");
+  if (mode == LB_ROUND_STOCHASTIC && b->storage != LB_BF16DEV)
+    return bfail(b, LB_EINVAL, "stochastic rounding applies to BF16 storage only");
+  if (mode == LB_ROUND_STOCHASTIC && !b->d_tbase) {
+    hipError_t e = hipMalloc(&b->d_tbase, sizeof(double));
+    if (e != hipSuccess) return bfail(b, LB_ENOMEM, std::string("step base: ") + hipGetErrorString(e));
+  }
+  b->rounding = mode;
+  b->graph.clear();  // captured launches carry the old kernel variant
   return LB_OK;
 }
 
@@ -628,6 +657,7 @@ void lb_batch_destroy(lb_batch *b) {
   if (b->h_acc) (void)hipHostFree(b->h_acc);
   if (b->ev) (void)hipEventDestroy(b->ev);
   b->graph.destroy();
+  if (b->d_tbase) (void)hipFree(b->d_tbase);
   delete b;
 }
 

@@ -90,6 +90,8 @@ struct BatchArgs {
   int out_f32;
   int stream_stores;     // non-temporal population stores (see StepArgs)
   double *accrows;       // WHAT_STEP_ACCUM: [tiles][ACC_N] running sums, row TileDesc::part
+  uint32_t t_step;       // MODE_BF16SR: time step of the launch (see StepArgs)
+  const double *t_base;
 };
 
 // Second reduction pass of one batch instance: partial rows [p0, p0 + n).

@@ -371,7 +371,7 @@ __device__ inline T wave_sum(T v) {
 template <int MODE, int NS, bool WALLS, int WHAT, int STP>
 __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const src, void *const dst, const int strip,
                                          const int seg, double *const part, void *const out0,
-                                         void *const out_u, const int out_f32) {
+                                         void *const out_u, const int out_f32, const uint32_t tstep) {
   using C = Codec<MODE>;
   using R = typename C::R;
   using S = typename C::S;
@@ -410,10 +410,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   const int tid = threadIdx.x;
   // stochastic rounding: a seed per time step
   uint32_t tseed = 0;
-  if constexpr (MODE == MODE_BF16SR) {
-    const uint32_t t = a.t_step + (a.t_base ? (uint32_t)(long long)*a.t_base : 0u);
-    tseed = uni(mix32(t * 0x9e3779b9u + 0x632be5abu));
-  }
+  if constexpr (MODE == MODE_BF16SR) tseed = uni(mix32(tstep * 0x9e3779b9u + 0x632be5abu));
 
   // Per-species constants in the arithmetic type.
   R K1[NS], K2[NS], K4[NS], K5[NS], K8[NS], tau[NS], om[NS], rref[NS], psiw[NS], rhow[NS];
@@ -1017,6 +1014,14 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   }
 }
 
+// Time step of a launch (read only by the stochastically rounding variant): t_step, plus the
+// step a graph replay starts at when t_base is set.
+template <int MODE>
+__device__ inline uint32_t launch_step_index(uint32_t t_step, const double *t_base) {
+  if constexpr (MODE != MODE_BF16SR) return 0u;
+  return t_step + (t_base ? (uint32_t)(long long)*t_base : 0u);
+}
+
 // One lattice: one workgroup per tile, tiles in band-major order spread over the XCDs.
 template <int MODE, int NS, bool WALLS, int WHAT, int STP = kStoreWriteThrough>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step_kernel(StepArgs a) {
@@ -1028,7 +1033,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
                                                : a.partials + (size_t)blockIdx.x * RED_N;
   void *const out0 =
       WHAT == WHAT_STRESS ? a.out_sigma : (WHAT == WHAT_PROFILE ? static_cast<void *>(a.prof) : a.out_rho);
-  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, part, out0, a.out_u, a.out_f32);
+  run_tile<MODE, NS, WALLS, WHAT, STP>(a, a.src, a.dst, strip, seg, part, out0, a.out_u, a.out_f32,
+                                       launch_step_index<MODE>(a.t_step, a.t_base));
 }
 
 // Many independent lattices in one persistent launch.  The host lists every tile of every
@@ -1040,6 +1046,7 @@ template <int MODE, int NS, bool WALLS, int WHAT, int STP = kStoreWriteThrough>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void batch_step_kernel(BatchArgs b) {
   const int G = (int)gridDim.x;
   const int mine = xcd_remap(blockIdx.x, G);
+  const uint32_t tstep = launch_step_index<MODE>(b.t_step, b.t_base);
   for (int base = 0; base < b.ntiles; base += G) {
     const int t = base + mine;
     if (t >= b.ntiles) break;  // later rounds are shorter still
@@ -1050,7 +1057,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
     double *const part = WHAT == WHAT_STEP_ACCUM ? b.accrows + (size_t)td.part * ACC_N
                                                  : b.partials + (size_t)td.part * RED_N;
     run_tile<MODE, NS, WALLS, WHAT, STP>(a, b.src + a.offset, b.dst + a.offset, td.strip, td.seg, part, b.out_rho,
-                                         b.out_u, b.out_f32);
+                                         b.out_u, b.out_f32, tstep);
   }
 }
 
@@ -1377,12 +1384,39 @@ static hipError_t launch_batch_m(int ns, int walls, int what, int tx, int grid, 
   return walls ? launch_batch_t<MODE, 2, true>(what, tx, grid, b, st) : launch_batch_t<MODE, 2, false>(what, tx, grid, b, st);
 }
 
+template <int NS, bool WALLS>
+static hipError_t launch_batch_sr_t(int what, int tx, int grid, const BatchArgs &b, hipStream_t st) {
+  constexpr int M = MODE_BF16SR;
+  const size_t lds = step_lds_bytes(M, NS, tx);
+  switch (what) {
+    case WHAT_STEP:
+      if (b.stream_stores)
+        hipLaunchKernelGGL((batch_step_kernel<M, NS, WALLS, WHAT_STEP, kStoreStreaming>), dim3(grid), dim3(tx), lds, st, b);
+      else
+        hipLaunchKernelGGL((batch_step_kernel<M, NS, WALLS, WHAT_STEP>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    case WHAT_STEP_ACCUM:
+      if (b.stream_stores)
+        hipLaunchKernelGGL((batch_step_kernel<M, NS, WALLS, WHAT_STEP_ACCUM, kStoreStreaming>), dim3(grid), dim3(tx), lds,
+                           st, b);
+      else
+        hipLaunchKernelGGL((batch_step_kernel<M, NS, WALLS, WHAT_STEP_ACCUM>), dim3(grid), dim3(tx), lds, st, b);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_step(int mode, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
                              hipStream_t st) {
   switch (mode) {
     case MODE_F64: return launch_batch_m<MODE_F64>(ns, walls, what, tx, grid, b, st);
     case MODE_F32: return launch_batch_m<MODE_F32>(ns, walls, what, tx, grid, b, st);
     case MODE_BF16: return launch_batch_m<MODE_BF16>(ns, walls, what, tx, grid, b, st);
+    case MODE_BF16SR:
+      if (what != WHAT_STEP && what != WHAT_STEP_ACCUM) return launch_batch_m<MODE_BF16>(ns, walls, what, tx, grid, b, st);
+      if (ns == 1) return walls ? launch_batch_sr_t<1, true>(what, tx, grid, b, st) : launch_batch_sr_t<1, false>(what, tx, grid, b, st);
+      return walls ? launch_batch_sr_t<2, true>(what, tx, grid, b, st) : launch_batch_sr_t<2, false>(what, tx, grid, b, st);
   }
   return hipErrorInvalidValue;
 }

@@ -85,3 +85,32 @@ def test_rounding_arguments():
         sim.adjoint(10, (1.0, 0.0), every=5)  # the adjoint recomputes states
     sim.set_rounding("nearest")
     sim.close()
+
+
+def test_batch_stochastic_rounding_matches_single_contexts():
+    """A batch's instance rounds with the same bits as a single context of that lattice, over
+    graph-replayed and individual steps."""
+    from paper_1402_6019_amd import Batch, Sim
+    cases = [channel(130, 45, seed=5), channel(96, 33, seed=6)]
+    dims = [(130, 45), (96, 33)]
+    inst = []
+    for (rho, kw), (lx, ly) in zip(cases, dims):
+        inst.append(dict(lx=lx, ly=ly, rho_init=rho, g1=kw["g1"], g2=kw["g2"], gab=kw["gab"], body=kw["body"],
+                         rho_wall=kw["rho_wall"], tau=kw["tau"], psi0=kw["psi0"], rho0=kw["rho0"],
+                         rho_ref=kw["rho_ref"]))
+    b = Batch(inst, n_species=2, walls=True, storage="bf16dev")
+    b.set_rounding("stochastic")
+    b.set_graph(10)
+    b.step(23)
+    for i, ((rho, kw), (lx, ly)) in enumerate(zip(cases, dims)):
+        sim = Sim(lx, ly, rho, storage="bf16dev", **kw)
+        sim.set_rounding("stochastic")
+        sim.step(23)
+        assert np.array_equal(b.checkpoint(i).cpu().numpy(), sim.checkpoint().cpu().numpy()), i
+        sim.close()
+    b.close()
+    b = Batch(inst, n_species=2, walls=True, storage="f32")
+    from paper_1402_6019_amd import LbError
+    with pytest.raises(LbError):
+        b.set_rounding("stochastic")
+    b.close()
