@@ -44,12 +44,14 @@ def workload():
     return rho, info, kw
 
 
-def time_storage(storage, rho, kw, steps, warmup, tile=None, shape=(LX, LY)):
+def time_storage(storage, rho, kw, steps, warmup, tile=None, shape=(LX, LY), rounding=None):
     """Average duration of one step (= one fused-kernel launch) over `steps` launches, timed
     with HIP events recorded on the stream the kernels run on."""
     import torch
     from paper_1402_6019_amd import Sim
     sim = Sim(shape[0], shape[1], rho, storage=storage, tile=tile, **kw)
+    if rounding:
+        sim.set_rounding(rounding)
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = sim.stream
@@ -728,6 +730,10 @@ def main():
         res[storage] = {"ms_per_step": ms, "mlups": nsite / (ms * 1e-3) / 1e6, "gbs": algo / (ms * 1e-3) / 1e9,
                         "algo_bytes_per_launch": algo, "wall_s": wall, "tile": list(tile_used)}
 
+    ms_sr, _, tile_sr = time_storage("bf16dev", rho, kw, args.steps, args.warmup, tile, rounding="stochastic")
+    bf16_sr = {"mlups": nsite / (ms_sr * 1e-3) / 1e6, "ms_per_step": ms_sr, "tile": list(tile_sr),
+               "note": "BF16 deviations with stochastic rounding of the stores (unbiased; see channel_50k_averages)"}
+
     khash = kernel_source_hash()
     head = res["f32"]
     copy = copy_reference(head["algo_bytes_per_launch"] // 2, min(args.steps, 500))
@@ -767,6 +773,7 @@ def main():
                     "roofline": {"bound": "hbm", "achieved": res["bf16dev"]["gbs"], "peak": HBM_PEAK_GBS,
                                  "unit": "GB/s", "frac": res["bf16dev"]["gbs"] / HBM_PEAK_GBS, "bytes_per_lu": 72,
                                  "traffic": traffic_from_profile(khash, "bf16dev", res["bf16dev"]["tile"])}},
+        "bf16dev_stochastic": bf16_sr,
         "speedup_vs_fp64": {"f32": res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"],
                             "bf16dev": res["f64"]["ms_per_step"] / res["bf16dev"]["ms_per_step"]},
         "tiles": {k: v["tile"] for k, v in res.items()},
