@@ -99,7 +99,7 @@ void fill_step_args(const lb_ctx *c, StepArgs &a) {
 }
 
 // Kernel variant of the passes that store populations.
-int step_mode(const lb_ctx *c) {
+static int step_mode(const lb_ctx *c) {
   return c->lat.storage == LB_BF16DEV && c->rounding == LB_ROUND_STOCHASTIC ? MODE_BF16SR : c->lat.storage;
 }
 
