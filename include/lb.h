@@ -161,8 +161,14 @@ int lb_step(lb_ctx *ctx, int64_t n);
    Host call. */
 int lb_set_reduce_every(lb_ctx *ctx, int32_t k);
 
-/* Density and velocity of the current state: rho (device, [n_species][ly][lx]) and
-   u (device, [2][ly][lx]) with u = (sum_s j_s + F_s / 2) / sum_s rho_s.  dtype: lb_dtype.
+/* Density and velocity of the current state (section "Lattice Kinetic Theory for non-ideal
+   fluids": the density and momentum are the zeroth and first moments of the populations,
+   rho = sum_l f_l, rho u = sum_l c_l f_l; for the mixture the densities of the emulsion
+   section's two species and their common flow): rho (device, [n_species][ly][lx]) and
+   u (device, [2][ly][lx]) with u = (sum_s j_s + F_s / 2) / sum_s rho_s, the momentum counted
+   half-way through the forcing of the step (the paper does not fix which velocity is reported;
+   this one is consistent with the (tau - 1/2)^2 forcing term of the lattice stress).  F_s is
+   the force of eq. (FORCE) plus the A-B repulsion and the body force.  dtype: lb_dtype.
    Either pointer may be NULL.  Asynchronous. */
 int lb_moments(lb_ctx *ctx, void *rho, void *u, int32_t dtype);
 
@@ -188,20 +194,35 @@ int lb_stress_field(lb_ctx *ctx, void *sigma, int32_t dtype);
 int lb_wall_stress(lb_ctx *ctx, double out[2], int32_t reset);
 
 /* FP64 totals of the current state (host outputs): species masses mass[s] and total
-   momentum (sum_s j_s); also the flow rate (1/lx) sum u_x if flow != NULL.  Launches one
+   momentum (sum_s j_s), the quantities the collision of eq. (LB) conserves (section "Lattice
+   Kinetic Theory for non-ideal fluids"; the emulsion section keeps each species' mass fixed by
+   its initial condition); also the flow rate (1/lx) sum u_x of the confined flows (section
+   "Numerical simulations of confined pressure-driven flows", u as in lb_moments) if
+   flow != NULL.  Sums are FP64 in a fixed order whatever the storage mode.  Launches one
    reduction pass.  Synchronises; returns LB_EUNSTABLE on a bad density. */
 int lb_totals(lb_ctx *ctx, double mass[2], double momentum[2], double *flow);
 
 /* Write the current pre-collision populations f(t) in the canonical FP64 layout to dst
-   (device, n_species*9*ly*lx doubles).  Asynchronous. */
+   (device, n_species*9*ly*lx doubles): the state of eq. (LB) at time t, the populations f_l(x, t)
+   before the collision of step t (section "Lattice Kinetic Theory for non-ideal fluids"), in the
+   D2Q9 order of the conventions above, species by species.  Storage modes that keep deviations
+   add W_l rho_ref[s] back.  Asynchronous. */
 int lb_checkpoint(lb_ctx *ctx, void *dst_f64);
 
-/* Replace the state by canonical FP64 pre-collision populations src (device).  Clears a
-   latched LB_EUNSTABLE.  Asynchronous. */
+/* Replace the state by canonical FP64 pre-collision populations src (device; the layout of
+   lb_checkpoint: f_l(x, t) of eq. (LB) before the collision of step t), converted to the
+   storage mode (rounded for LB_F32 / LB_BF16DEV).  The step count is kept (lb_set_time sets
+   it).  Clears a latched LB_EUNSTABLE.  Asynchronous. */
 int lb_restore(lb_ctx *ctx, const void *src_f64);
 
 /* Number of completed time steps. */
 int64_t lb_time(const lb_ctx *ctx);
+
+/* Set the step count t >= 0 (host call).  The count picks the reducing steps
+   (lb_set_reduce_every) and seeds the stochastic rounding bits of step t, so a run resumed
+   in a new context from lb_checkpoint data continues bit for bit as the uninterrupted run
+   when its count is set to the checkpoint's lb_time before stepping.  LB_EINVAL for t < 0. */
+int lb_set_time(lb_ctx *ctx, int64_t t);
 
 /* Launch shape of the step kernel: strip width tx in {64, 128, 256} columns (one workgroup
    thread per column) and sy >= 1 rows per workgroup.  Any shape gives bitwise identical
@@ -400,6 +421,8 @@ int lb_batch_checkpoint(lb_batch *b, int32_t i, void *dst_f64);
 int lb_batch_restore(lb_batch *b, int32_t i, const void *src_f64);
 
 int64_t lb_batch_time(const lb_batch *b);
+/* As lb_set_time, for the batch's common step count. */
+int lb_batch_set_time(lb_batch *b, int64_t t);
 const char *lb_batch_last_error(const lb_batch *b);
 void lb_batch_destroy(lb_batch *b);
 

@@ -127,6 +127,10 @@ class Sim:
     def time(self):
         return self._lib.lb_time(self._h)
 
+    def set_time(self, t):
+        """Set the step count (resuming a checkpointed run in a new context)."""
+        self._chk(self._lib.lb_set_time(self._h, int(t)))
+
     def step(self, n=1):
         self._chk(self._lib.lb_step(self._h, int(n)))
 
@@ -370,6 +374,10 @@ class Batch:
     @property
     def time(self):
         return self._lib.lb_batch_time(self._h)
+
+    def set_time(self, t):
+        """Set the common step count (resuming checkpointed instances in a new batch)."""
+        self._chk(self._lib.lb_batch_set_time(self._h, int(t)))
 
     def step(self, n=1):
         self._chk(self._lib.lb_batch_step(self._h, int(n)))

@@ -61,6 +61,7 @@ SIGNATURES = {
     "lb_checkpoint": (ctypes.c_int, [_vp, _vp]),
     "lb_restore": (ctypes.c_int, [_vp, _vp]),
     "lb_time": (_i64, [_vp]),
+    "lb_set_time": (ctypes.c_int, [_vp, _i64]),
     "lb_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
     "lb_set_store_policy": (ctypes.c_int, [_vp, _i32]),
     "lb_set_rounding": (ctypes.c_int, [_vp, _i32]),
@@ -96,6 +97,7 @@ SIGNATURES = {
     "lb_batch_checkpoint": (ctypes.c_int, [_vp, _i32, _vp]),
     "lb_batch_restore": (ctypes.c_int, [_vp, _i32, _vp]),
     "lb_batch_time": (_i64, [_vp]),
+    "lb_batch_set_time": (ctypes.c_int, [_vp, _i64]),
     "lb_batch_last_error": (ctypes.c_char_p, [_vp]),
     "lb_batch_destroy": (None, [_vp]),
 }

@@ -508,6 +508,13 @@ int lb_restore(lb_ctx *c, const void *src) {
 
 int64_t lb_time(const lb_ctx *c) { return c ? c->t : -1; }
 
+int lb_set_time(lb_ctx *c, int64_t t) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (t < 0) return fail(c, LB_EINVAL, "time must be >= 0");
+  c->t = t;
+  return LB_OK;
+}
+
 int lb_set_tile(lb_ctx *c, int32_t tx, int32_t sy) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (tx != 64 && tx != 128 && tx != 256) return fail(c, LB_EINVAL, "tx must be 64, 128 or 256");

@@ -644,6 +644,13 @@ int lb_batch_restore(lb_batch *b, int32_t i, const void *src) {
 
 int64_t lb_batch_time(const lb_batch *b) { return b ? b->t : -1; }
 
+int lb_batch_set_time(lb_batch *b, int64_t t) {
+  if (!b) return bfail(nullptr, LB_EINVAL, "null context");
+  if (t < 0) return bfail(b, LB_EINVAL, "time must be >= 0");
+  b->t = t;
+  return LB_OK;
+}
+
 const char *lb_batch_last_error(const lb_batch *b) { return b ? b->err.c_str() : g_batch_init_error.c_str(); }
 
 void lb_batch_destroy(lb_batch *b) {

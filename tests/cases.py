@@ -28,7 +28,7 @@ def oracle_params(c):
     from oracle import Params
     return Params(lx=c["lx"], ly=c["ly"], ns=c["ns"], walls=c["walls"], g1=c["g1"], g2=c["g2"], gab=c["gab"],
                   body=c["body"], rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"],
-                  u_wall=c.get("u_wall", (0.0, 0.0)))
+                  u_wall=c.get("u_wall", (0.0, 0.0)), cross_psi=1 if c.get("cross_psi") else 0)
 
 
 def make_oracle(c):
@@ -41,7 +41,24 @@ def make_sim(c, tile=None, storage=None):
     return Sim(c["lx"], c["ly"], c["rho"], n_species=c["ns"], walls=bool(c["walls"]),
                storage=storage or c["storage"], g1=c["g1"], g2=c["g2"], gab=c["gab"], body=c["body"],
                rho_wall=c["rho_wall"], tau=c["tau"], psi0=c["psi0"], rho0=c["rho0"], rho_ref=c["rho_ref"],
-               tile=tile, u_wall=c.get("u_wall", (0.0, 0.0)))
+               tile=tile, u_wall=c.get("u_wall", (0.0, 0.0)), cross_psi=bool(c.get("cross_psi", False)))
+
+
+def counterflow(c, seed, u_amp=0.04):
+    """Canonical FP64 pre-collision populations [ns][9][ly][lx] of the case's densities with the
+    species drifting against each other: W_l rho_s (1 + 3 c_l . u_s), u_B = -u_A, u_A random per
+    site with amplitude u_amp (a seeded input; both sides start from it)."""
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])[:, None, None]
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])[:, None, None]
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    rng = np.random.default_rng(seed)
+    u = u_amp * rng.uniform(-1.0, 1.0, (2, c["ly"], c["lx"]))
+    rho = c["rho"]
+    f = np.empty((c["ns"], 9, c["ly"], c["lx"]))
+    for s in range(c["ns"]):
+        sign = 1.0 if s == 0 else -1.0
+        f[s] = w * rho[s] * (1.0 + 3.0 * sign * (cx * u[0] + cy * u[1]))
+    return f
 
 
 def rel_err(a, b):

@@ -16,7 +16,7 @@ Sizes span several workgroup strips and segments with ragged tails in x and y.
 import numpy as np
 import pytest
 
-from cases import emulsion_case, film_case, make_oracle, make_sim, rel_err
+from cases import counterflow, emulsion_case, film_case, make_oracle, make_sim, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -75,6 +75,30 @@ def test_emulsion_fp64_parity(walls):
         sim.step(t_target - sim.time)
         orc.step(t_target - orc.time)
         compare(sim, orc, tol)
+
+
+@pytest.mark.parametrize("cross_psi", [False, True])
+@pytest.mark.parametrize("walls", [False, True])
+def test_unequal_tau_counterflow_fp64_parity(walls, cross_psi):
+    """tau = (0.8, 1.3) from a state whose species drift against each other, so the common
+    velocity u' = sum_s (j_s / tau_s) / sum_s (rho_s / tau_s) and the shift tau_s F_s / rho_s
+    both matter; the A-B repulsion between densities or, with cross_psi, between
+    pseudopotentials.  Ragged lattice, walls with wetting and a body force, or periodic."""
+    c = emulsion_case(100, 77, walls=walls, fraction=0.7, seed=15, rmin=5, rmax=10, g=1e-5)
+    c["tau"] = (0.8, 1.3)
+    c["cross_psi"] = cross_psi
+    f0 = counterflow(c, seed=15)
+    orc = make_oracle(c)
+    orc.set_f(f0)
+    sim = make_sim(c, tile=(64, 16))
+    sim.restore(f0)
+    compare(sim, orc, 1e-13)  # t = 0: the restored counterflow state
+    for t_target, tol in ((1, 1e-13), (10, 1e-13), (60, 1e-11)):
+        sim.step(t_target - sim.time)
+        orc.step(t_target - orc.time)
+        e_rho, e_u = compare(sim, orc, tol)
+        print(f"tau (0.8, 1.3) walls={walls} cross_psi={cross_psi} t={t_target}: rho {e_rho:.2e} u {e_u:.2e}")
+    sim.close()
 
 
 def test_channel_observables_fp64():
@@ -260,10 +284,13 @@ def _bulk(rho):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_steady_flat_interface(storage):
-    """Flat liquid slab at the film couplings relaxed to equilibrium (quasi one-dimensional).
-    FP64: pointwise, 2e-10 (4e4 steps of a slowly relaxing mode accumulate rounding).
-    FP32: a periodic slab has a neutral translation mode that rounding noise random-walks, so
-    the comparison is on translation-invariant quantities: both bulk densities and the mass."""
+    """Flat liquid slab at the film couplings relaxed to equilibrium (quasi one-dimensional),
+    70,000 steps as in the oracle's own pin.  A periodic slab has a neutral translation mode:
+    rounding differences shift both interfaces by a fraction of a site that nothing restores
+    (the oracle's own response to a 1e-15 perturbation of the initial state grows to ~1e-11
+    pointwise over these steps), so the converged state is compared on translation-invariant
+    quantities: both bulk densities and the mass, 1e-11 in FP64 and 1e-5 in FP32.  FP64 is
+    also compared pointwise, to the stated bound of the neutral mode's walk."""
     lx, ly = 128, 5
     x = np.arange(lx)
     prof = 0.28 + 1.11 * 0.5 * (np.tanh((x - 31.5) / 3.0) - np.tanh((x - 95.5) / 3.0))
@@ -271,12 +298,19 @@ def test_steady_flat_interface(storage):
     c["rho"] = np.broadcast_to(prof, (1, ly, lx)).copy()
     sim = make_sim(c, storage=storage)
     orc = make_oracle(c)
-    sim.step(40000)
-    orc.step(40000)
+    sim.step(70000)
+    orc.step(70000)
     rho, u = gpu_fields(sim)
     fl = orc.fields()
     if storage == "f64":
-        assert rel_err(rho, fl["rho"]) <= 2e-10
+        (gl, gg), (ol, og) = _bulk(rho), _bulk(fl["rho"])
+        e_pt = rel_err(rho, fl["rho"])
+        drift = abs(rho.sum() - fl["rho"].sum()) / fl["rho"].sum()
+        print(f"flat interface f64 at 7e4 steps: liquid {abs(gl - ol) / ol:.2e}, gas {abs(gg - og) / og:.2e}, "
+              f"mass {drift:.2e}, pointwise {e_pt:.2e}")
+        assert abs(gl - ol) / ol <= 1e-11 and abs(gg - og) / og <= 1e-11
+        assert drift <= 1e-13
+        assert e_pt <= 1e-8
     else:
         (gl, gg), (ol, og) = _bulk(rho), _bulk(fl["rho"])
         print(f"flat interface f32: liquid {gl:.8f} vs {ol:.8f}, gas {gg:.8f} vs {og:.8f}")
@@ -305,13 +339,15 @@ def test_steady_droplet(storage):
     rho, _ = gpu_fields(sim)
     ref = orc.fields()["rho"]
     if storage == "f64":
+        # pointwise: the droplet's two neutral translation modes walk as the slab's does
         assert rel_err(rho, ref) <= 1e-10
     (gl, gg), (ol, og) = _bulk(rho), _bulk(ref)
     rg = dg.droplet_radius(rho[0], gl, gg)
     ro = dg.droplet_radius(ref[0], ol, og)
-    print(f"droplet {storage}: R {rg:.7f} vs {ro:.7f}, in {gl:.8f} vs {ol:.8f}, out {gg:.8f} vs {og:.8f}")
-    assert abs(gl - ol) / ol <= 1e-5 and abs(gg - og) / og <= 1e-5
-    assert abs(rg - ro) / ro <= 1e-5
+    print(f"droplet {storage}: R {rg:.12f} vs {ro:.12f}, in {gl:.14f} vs {ol:.14f}, out {gg:.14f} vs {og:.14f}")
+    tol = 1e-11 if storage == "f64" else 1e-5
+    assert abs(gl - ol) / ol <= tol and abs(gg - og) / og <= tol
+    assert abs(rg - ro) / ro <= tol
 
 
 def test_bf16dev_error_bound():

@@ -114,3 +114,32 @@ def test_batch_stochastic_rounding_matches_single_contexts():
     with pytest.raises(LbError):
         b.set_rounding("stochastic")
     b.close()
+
+
+def test_stochastic_rounding_resumes_bitwise_in_a_new_context():
+    """A run checkpointed at step 7 and resumed in a new context with lb_set_time(7) continues
+    bit for bit as the first context does after restoring the same checkpoint (the rounding bits
+    of step t are seeded by t); without the step count the resumed run rounds differently."""
+    from paper_1402_6019_amd import Sim
+    rho, kw = channel(130, 45)
+    first = Sim(130, 45, rho, storage="bf16dev", tile=(64, 7), **kw)
+    first.set_rounding("stochastic")
+    first.step(7)
+    ck = first.checkpoint().clone()
+    first.restore(ck)  # the same canonical round trip the resumed context takes
+    first.step(9)
+    ref = first.checkpoint().cpu().numpy()
+    assert first.time == 16
+    first.close()
+    for set_time in (True, False):
+        sim = Sim(130, 45, rho, storage="bf16dev", **kw)
+        sim.set_rounding("stochastic")
+        sim.restore(ck)
+        if set_time:
+            sim.set_time(7)
+        sim.step(9)
+        f = sim.checkpoint().cpu().numpy()
+        assert np.array_equal(f, ref) == set_time, set_time
+        sim.close()
+    with pytest.raises(Exception):
+        Sim(130, 45, rho, storage="bf16dev", **kw).set_time(-1)

@@ -359,9 +359,12 @@ def test_cross_force_closed_form_and_body_force():
     np.testing.assert_allclose(F[0, 1], 0.7 * g[1], rtol=0, atol=1e-15)
 
 
-def test_pair_forces_cancel_newton_third_law():
-    """Sum over a periodic lattice of all pair forces (own and cross species) vanishes."""
-    P = Params(lx=16, ly=12, ns=2, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB, rho0=0.83)
+@pytest.mark.parametrize("cross_psi", [0, 1])
+def test_pair_forces_cancel_newton_third_law(cross_psi):
+    """Sum over a periodic lattice of all pair forces (own and cross species, the A-B term
+    between densities or between pseudopotentials) vanishes."""
+    P = Params(lx=16, ly=12, ns=2, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB, rho0=0.83,
+               cross_psi=cross_psi)
     rng = np.random.default_rng(11)
     rho = 0.2 + rng.random((2, 12, 16))
     o = Oracle(P, rho_init=rho)
@@ -413,6 +416,110 @@ def test_momentum_balance_channel_with_body_force():
     assert np.abs(dP - pred).max() < 1e-13 * M
     for s in range(2):
         assert np.abs(rec[:, s] - rec[0, s]).max() / rec[0, s] < 1e-12
+
+
+def _counterflow(P, rho, seed, u_amp=0.04):
+    """Pre-collision populations of a two-species state whose species drift against each
+    other: W_l rho_s (1 + 3 c_l . u_s) with a random site velocity u_A and u_B = -u_A, so the
+    two species carry opposite momenta and the common velocity of the collision matters."""
+    rng = np.random.default_rng(seed)
+    u = u_amp * rng.uniform(-1.0, 1.0, (2, P.ly, P.lx))
+    f = np.empty((2, 9, P.ly, P.lx))
+    for s, sign in ((0, 1.0), (1, -1.0)):
+        cu = sign * (CX[:, None, None] * u[0] + CY[:, None, None] * u[1])
+        f[s] = WL[:, None, None] * rho[s] * (1.0 + 3.0 * cu)
+    return f
+
+
+def _collision_momentum_change(fl, tau, weight):
+    """Total momentum that one collision adds, sum_x sum_s (rho_s u^eq_s - j_s) / tau_s, when the
+    common velocity weights species s by weight[s]: u' = sum_s w_s j_s / sum_s w_s rho_s and
+    u^eq_s = u' + tau_s F_s / rho_s (computed from the oracle's moments and forces)."""
+    rho, j, F = fl["rho"], fl["j"], fl["force"]
+    tau = np.asarray(tau)[:, None, None]
+    w = np.asarray(weight)[:, None, None]
+    out = []
+    for k in range(2):
+        up = (w * j[:, k]).sum(0) / (w * rho).sum(0)
+        ueq = up[None] + tau * F[:, k] / rho
+        out.append(float(((rho * ueq - j[:, k]) / tau).sum()))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("cross_psi", [0, 1])
+def test_unequal_tau_counterflow_conserves_momentum(cross_psi):
+    """tau_A != tau_B with the species drifting against each other (periodic, no body force).
+    A collision changes the momentum of species s by (rho_s u^eq_s - j_s) / tau_s; summed over
+    species this is sum_s F_s only if the common velocity weights j_s and rho_s by 1/tau_s (Q8)
+    and the shift is tau_s F_s / rho_s, and the pair forces (own and A-B, with densities or
+    pseudopotentials) sum to zero over a periodic lattice.  So the total momentum is constant
+    to roundoff; a tau_s weighting, or a shift without tau_s, is not (checked on the same
+    state, so the pin is sensitive to both)."""
+    lx, ly = 40, 32
+    tau = (0.8, 1.3)
+    P = Params(lx=lx, ly=ly, ns=2, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+               rho0=lbgen.EMULSION_RHO0, tau=tau, cross_psi=cross_psi)
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.6, seed=12, rmin=5, rmax=9)
+    o = Oracle(P, f=_counterflow(P, rho, seed=12))
+    scale = float(np.abs(o.fields()["j"]).sum())  # momentum each species carries, summed over sites
+    assert scale > 1.0
+    rec = o.step(300, record=True)
+    assert np.abs(rec[:, 2:4] - rec[0, 2:4]).max() < 1e-13 * scale
+    for s in range(2):
+        assert np.abs(rec[:, s] - rec[0, s]).max() / rec[0, s] < 1e-13
+    # on the evolved state (the generator's complementary densities make the A-B force of
+    # each species sum to zero on its own at t = 0, which hides a missing tau_s in the shift)
+    # the right weighting conserves momentum and the wrong ones do not
+    fl = o.fields()
+    assert np.abs(_collision_momentum_change(fl, tau, 1.0 / np.array(tau))).max() < 1e-13 * scale
+    assert np.abs(_collision_momentum_change(fl, tau, np.array(tau))).max() > 1e-5 * scale
+    no_tau_shift = dict(fl, force=fl["force"] / np.array(tau)[:, None, None, None])
+    assert np.abs(_collision_momentum_change(no_tau_shift, tau, 1.0 / np.array(tau))).max() > 1e-6 * scale
+
+
+def test_unequal_tau_body_force_momentum_grows_by_gM():
+    """With a body force g on a periodic lattice, tau = (0.8, 1.3), the total momentum grows
+    by exactly g M per step (M the total mass): the forcing enters every species' collision
+    as rho_s g and nothing else changes the total."""
+    lx, ly = 36, 30
+    g = (2e-5, -1e-5)
+    P = Params(lx=lx, ly=ly, ns=2, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+               rho0=lbgen.EMULSION_RHO0, tau=(0.8, 1.3), body=g)
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.6, seed=14, rmin=5, rmax=8)
+    o = Oracle(P, f=_counterflow(P, rho, seed=14))
+    rec = o.step(200, record=True)
+    M = rec[0, 0] + rec[0, 1]
+    k = np.arange(200)
+    for c in range(2):
+        pred = rec[0, 2 + c] + k * g[c] * M
+        assert np.abs(rec[:, 2 + c] - pred).max() < 1e-13 * M
+
+
+def test_cross_force_closed_form_psi_coupling():
+    """A-B repulsion between pseudopotentials (the Q6 flag cross_psi): with uniform rho_A and
+    psi_B = a + b sin(k x), F_A,x = -G_AB psi_A 2 b cos(kx) (t1 + 2 t2) sin k, plus rho_A g;
+    F_A,y = rho_A g_y (no own-species couplings here)."""
+    lx, ly = 20, 5
+    gab = 0.587
+    g = (2e-4, -1e-4)
+    P = Params(lx=lx, ly=ly, ns=2, gab=gab, rho0=0.83, body=g, cross_psi=1)
+    kap = 2 * np.pi / lx
+    x = np.arange(lx)
+    a, b = 0.45, 0.15
+    psi_b = a + b * np.sin(kap * x)
+    rb = np.broadcast_to(-0.83 * np.log(1.0 - psi_b), (ly, lx))
+    ra = np.full((ly, lx), 0.7)
+    o = Oracle(P, rho_init=np.stack([ra, rb]))
+    fl = o.fields()
+    np.testing.assert_allclose(fl["psi"][1], np.broadcast_to(psi_b, (ly, lx)), rtol=1e-14)
+    psi_a = 1.0 - np.exp(-0.7 / 0.83)
+    t1, t2 = P.t
+    ref = -gab * psi_a * 2 * b * np.cos(kap * x) * (t1 + 2 * t2) * np.sin(kap) + 0.7 * g[0]
+    np.testing.assert_allclose(fl["force"][0, 0], np.broadcast_to(ref, (ly, lx)), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(fl["force"][0, 1], 0.7 * g[1], rtol=0, atol=1e-15)
+    # the density coupling on the same state gives a different force: the flag is live
+    o2 = Oracle(Params(lx=lx, ly=ly, ns=2, gab=gab, rho0=0.83, body=g, cross_psi=0), rho_init=np.stack([ra, rb]))
+    assert np.abs(o2.fields()["force"][0, 0] - fl["force"][0, 0]).max() > 1e-3
 
 
 # ----------------------------------------------------------------------------------------
