@@ -305,11 +305,15 @@ def test_steady_flat_interface(storage):
     if storage == "f64":
         (gl, gg), (ol, og) = _bulk(rho), _bulk(fl["rho"])
         e_pt = rel_err(rho, fl["rho"])
-        drift = abs(rho.sum() - fl["rho"].sum()) / fl["rho"].sum()
+        # mass against the initial mass: the kernel closes each collision's mass balance
+        # through the rest population, the oracle relaxes all nine populations as eq. (LB)
+        # writes it, so its rounding lets its own mass drift by ~1e-12 over these steps
+        m0 = c["rho"].sum()
+        drift, drift_orc = abs(rho.sum() - m0) / m0, abs(fl["rho"].sum() - m0) / m0
         print(f"flat interface f64 at 7e4 steps: liquid {abs(gl - ol) / ol:.2e}, gas {abs(gg - og) / og:.2e}, "
-              f"mass {drift:.2e}, pointwise {e_pt:.2e}")
+              f"mass drift {drift:.2e} (oracle {drift_orc:.2e}), pointwise {e_pt:.2e}")
         assert abs(gl - ol) / ol <= 1e-11 and abs(gg - og) / og <= 1e-11
-        assert drift <= 1e-13
+        assert drift <= 1e-13 and drift_orc <= 1e-11
         assert e_pt <= 1e-8
     else:
         (gl, gg), (ol, og) = _bulk(rho), _bulk(fl["rho"])
