@@ -291,6 +291,20 @@ int lb_set_couplings(lb_ctx *ctx, const lb_couplings *cpl);
 int lb_profile(lb_ctx *ctx, double *out);
 
 /*
+ * lb_profile without allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight sampling loops, hosts that forbid hipMalloc): the same passes and
+ * the same output as lb_profile, bit for bit, but the block sums and row sums go to a static
+ * scratch array of 2^19 doubles (4 MiB) in the library's code object on each device, whose
+ * address lb_init looks up once per device.  The call allocates nothing.  It needs
+ * ((lx + tx - 1) / tx * (tx / 64) + 1) * ly * 7 doubles of scratch (tx: the strip width of
+ * lb_set_tile); larger lattices are refused with LB_EINVAL (use lb_profile, or a narrower
+ * strip).  Every call on a device shares that device's scratch: calls on one device whose
+ * work overlaps (contexts on different streams) race, so order them on one stream or
+ * synchronise between them.  Asynchronous.
+ */
+int lb_profile_noalloc(lb_ctx *ctx, double *out);
+
+/*
  * Time statistics of n >= 1 profile samples (device, [n][4 ly + 1], as written by
  * lb_profile), written to out (device, 6 ly + 3 doubles):
  *   out[0 .. ly-1]             <ubar(y)>

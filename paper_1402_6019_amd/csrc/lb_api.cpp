@@ -39,6 +39,7 @@ struct lb_ctx {
   long long plane = 0;
   int tx = 256, sy = 16;
   int n_cu = 256;  // compute units of the device the context runs on
+  int device = 0;  // device current at lb_init
   int reduce_every = 0;
   int store_policy = LB_STORES_AUTO;
   int rounding = LB_ROUND_NEAREST;  // BF16 stores: nearest or stochastic
@@ -304,6 +305,11 @@ int lb_init(lb_ctx **out, const lb_lattice *lat, const lb_couplings *cpl, const 
   default_tile(c);
 
   hipError_t e;
+  if ((e = hipGetDevice(&c->device)) != hipSuccess || (e = static_scratch_setup(c->device)) != hipSuccess) {
+    g_init_error = std::string("device scratch lookup: ") + hipGetErrorString(e);
+    lb_destroy(c);
+    return LB_EDEVICE;
+  }
   if ((e = hipMalloc(&c->d_totals, RED_N * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->d_acc, 4 * sizeof(double))) != hipSuccess ||
       (e = hipHostMalloc(&c->h_acc, 4 * sizeof(double), hipHostMallocDefault)) != hipSuccess ||
@@ -562,6 +568,35 @@ int lb_set_couplings(lb_ctx *c, const lb_couplings *cpl) {
   return LB_OK;
 }
 
+namespace {
+
+// The profile pass and its second pass, with `buf` holding the block sums and then the row
+// sums ((ncb + 1) * ly * PROF_N doubles).
+int profile_into(lb_ctx *c, int nb, int nseg, int ncb, double *buf, double *out) {
+  StepArgs a;
+  fill_step_args(c, a);
+  a.nseg = nseg;
+  a.src = c->pop[c->cur];
+  a.dst = c->pop[c->cur ^ 1];  // not written
+  a.prof = buf;
+  a.ncb = ncb;
+  hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_PROFILE, c->tx, nb, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "profile kernel launch");
+  // the walls' share of their momentum exchange: sum_s rho_w,s U / 3 per unit length
+  double wb0 = 0.0, wt0 = 0.0;
+  if (c->lat.walls)
+    for (int s = 0; s < c->lat.n_species; ++s) {
+      wb0 += 2.0 * a.wall_mom[0][s];
+      wt0 += 2.0 * a.wall_mom[1][s];
+    }
+  e = launch_profile_finish(buf, ncb, c->lat.lx, c->lat.ly, c->lat.walls, wb0, wt0,
+                            buf + (size_t)ncb * c->lat.ly * PROF_N, out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "profile finish launch");
+  return LB_OK;
+}
+
+}  // namespace
+
 int lb_profile(lb_ctx *c, double *out) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (!out) return fail(c, LB_EINVAL, "null output");
@@ -577,26 +612,23 @@ int lb_profile(lb_ctx *c, double *out) {
     if (e != hipSuccess) return fail(c, LB_ENOMEM, std::string("profile buffer: ") + hipGetErrorString(e));
     c->prof_cap = need;
   }
-  StepArgs a;
-  fill_step_args(c, a);
-  a.nseg = nseg;
-  a.src = c->pop[c->cur];
-  a.dst = c->pop[c->cur ^ 1];  // not written
-  a.prof = c->d_prof;
-  a.ncb = ncb;
-  hipError_t e = launch_step(c->lat.storage, c->lat.n_species, c->lat.walls, WHAT_PROFILE, c->tx, nb, a, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "profile kernel launch");
-  // the walls' share of their momentum exchange: sum_s rho_w,s U / 3 per unit length
-  double wb0 = 0.0, wt0 = 0.0;
-  if (c->lat.walls)
-    for (int s = 0; s < c->lat.n_species; ++s) {
-      wb0 += 2.0 * a.wall_mom[0][s];
-      wt0 += 2.0 * a.wall_mom[1][s];
-    }
-  e = launch_profile_finish(c->d_prof, ncb, c->lat.lx, c->lat.ly, c->lat.walls, wb0, wt0,
-                            c->d_prof + (size_t)ncb * c->lat.ly * PROF_N, out, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "profile finish launch");
-  return LB_OK;
+  return profile_into(c, nb, nseg, ncb, c->d_prof, out);
+}
+
+int lb_profile_noalloc(lb_ctx *c, double *out) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!out) return fail(c, LB_EINVAL, "null output");
+  int nseg = 0;
+  const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
+  const int ncb = ((c->lat.lx + c->tx - 1) / c->tx) * (c->tx / 64);
+  const size_t need = ((size_t)ncb + 1) * c->lat.ly * PROF_N;
+  if (need > kStaticScratchDoubles)
+    return fail(c, LB_EINVAL, "lb_profile_noalloc: this lattice and strip width need " + std::to_string(need) +
+                                  " doubles of scratch, the static scratch holds " +
+                                  std::to_string(kStaticScratchDoubles) + " (use lb_profile)");
+  double *buf = static_scratch(c->device);
+  if (!buf) return fail(c, LB_EDEVICE, "lb_profile_noalloc: no static scratch address for this device");
+  return profile_into(c, nb, nseg, ncb, buf, out);
 }
 
 int lb_profile_stats(lb_ctx *c, const double *samples, int64_t n, int32_t k0, double *out) {

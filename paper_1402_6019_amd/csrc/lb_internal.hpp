@@ -181,6 +181,27 @@ hipError_t launch_batch_reduce(const double *partials, const ReduceJob *jobs, in
                                int accumulate, hipStream_t st);
 
 size_t step_lds_bytes(int mode, int ns, int tx);
+
+// Static device scratch of the entry points that allocate nothing (lb_static.hip), in doubles.
+constexpr size_t kStaticScratchDoubles = (size_t)1 << 19;
+// Looks up the scratch array's address on `device` once (makes it current for the lookup).
+hipError_t static_scratch_setup(int device);
+// That address (nullptr before static_scratch_setup succeeded on the device).
+double *static_scratch(int device);
+
+// Per storage mode (lb_step_f64.hip, lb_step_f32.hip, lb_step_bf16.hip): the launchers that
+// launch_step / launch_batch_step / step_blocks_per_cu dispatch to.
+hipError_t launch_step_f64(int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st);
+hipError_t launch_step_f32(int ns, int walls, int what, int tx, int nb, const StepArgs &a, hipStream_t st);
+hipError_t launch_step_bf16(bool stochastic, int ns, int walls, int what, int tx, int nb, const StepArgs &a,
+                            hipStream_t st);
+hipError_t launch_batch_f64(int ns, int walls, int what, int tx, int grid, const BatchArgs &b, hipStream_t st);
+hipError_t launch_batch_f32(int ns, int walls, int what, int tx, int grid, const BatchArgs &b, hipStream_t st);
+hipError_t launch_batch_bf16(bool stochastic, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
+                             hipStream_t st);
+int blocks_per_cu_f64(int ns, int walls, int tx);
+int blocks_per_cu_f32(int ns, int walls, int tx);
+int blocks_per_cu_bf16(int ns, int walls, int tx);
 // Workgroups of tx threads of the plain step kernel that one compute unit holds at once.
 int step_blocks_per_cu(int mode, int ns, int walls, int tx);
 
