@@ -154,6 +154,66 @@ def emulsion(lx, ly, fraction=0.8, seed=2, walls=False, rmin=8.0, rmax=24.0, gap
     return rho, info
 
 
+def emulsion3d(lx, ly, lz, fraction=0.5, seed=2, walls=False, rmin=4.0, rmax=8.0, gap=2.0,
+               rich=EMULSION_RICH, poor=EMULSION_POOR):
+    """Polydisperse packed emulsion in a box of lx x ly x lz sites, the 3-D counterpart of
+    emulsion(): round(fraction * V / E[4/3 pi r^3]) centres uniform in the box with radii
+    U(rmin, rmax); every site belongs to the centre of smallest power distance (periodic in x
+    and z, and in y unless walls); it is A-rich when within lam * r_i of that centre and at least
+    gap/2 from its power cell's boundary (and from the wall rows); lam is set by bisection to
+    reach the volume fraction.  Returns (rho[2, lz, ly, lx], info)."""
+    from scipy.spatial import cKDTree
+
+    g = rng(seed)
+    er3 = (rmax ** 4 - rmin ** 4) / (4.0 * (rmax - rmin))
+    n = max(1, int(round(fraction * lx * ly * lz / (4.0 / 3.0 * math.pi * er3))))
+    cen = np.stack([g.uniform(0.0, lx, n), g.uniform(0.0, ly, n), g.uniform(0.0, lz, n)], axis=1)
+    rad = g.uniform(rmin, rmax, n)
+    lift = np.sqrt(rmax * rmax - rad * rad)
+    pts, owner = [], []
+    for sx in (-lx, 0, lx):
+        for sy in ((0,) if walls else (-ly, 0, ly)):
+            for sz in (-lz, 0, lz):
+                pts.append(np.concatenate([cen + np.array([sx, sy, sz]), lift[:, None]], axis=1))
+                owner.append(np.arange(n))
+    pts = np.concatenate(pts)
+    owner = np.concatenate(owner)
+    tree = cKDTree(pts)
+    zz, yy, xx = np.mgrid[0:lz, 0:ly, 0:lx]
+    q = np.stack([xx.ravel(), yy.ravel(), zz.ravel(), np.zeros(xx.size)], axis=1).astype(np.float64)
+    k = 4
+    d, idx = tree.query(q, k=k)
+    pd = d * d
+    c0 = pts[idx[:, 0]]
+    dist_c = np.sqrt(((q[:, :3] - c0[:, :3]) ** 2).sum(axis=1))
+    r0 = rad[owner[idx[:, 0]]]
+    bdist = np.full(q.shape[0], np.inf)
+    for j in range(1, k):
+        cj = pts[idx[:, j]]
+        sep = np.sqrt(((c0[:, :3] - cj[:, :3]) ** 2).sum(axis=1))
+        same = owner[idx[:, j]] == owner[idx[:, 0]]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            bj = np.where(same | (sep == 0), np.inf, (pd[:, j] - pd[:, 0]) / (2.0 * sep))
+        bdist = np.minimum(bdist, bj)
+    ok = bdist >= gap / 2.0
+    if walls:
+        ok &= (q[:, 1] >= gap / 2.0) & (q[:, 1] <= ly - 1 - gap / 2.0)
+    ratio = dist_c / r0
+    lo, hi = 0.0, 8.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if np.count_nonzero(ok & (ratio < mid)) / q.shape[0] < fraction:
+            lo = mid
+        else:
+            hi = mid
+    a_rich = (ok & (ratio < hi)).reshape(lz, ly, lx)
+    rho = np.empty((2, lz, ly, lx))
+    rho[0] = np.where(a_rich, rich[0], poor[0])
+    rho[1] = np.where(a_rich, rich[1], poor[1])
+    ma, mb = rho[0].sum(), rho[1].sum()
+    return rho, dict(n_drops=n, volume_fraction=float(a_rich.mean()), mass_fraction=float(ma / (ma + mb)), lam=hi)
+
+
 # Emulsion couplings of the confined-flow simulations (emulsion section of the paper).
 EMULSION_G1 = (-9.0, -8.0)
 EMULSION_G2 = (8.1, 7.1)

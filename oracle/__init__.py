@@ -19,6 +19,8 @@ from . import weights as _weights
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lb_oracle.cpp")
 _LIB = os.path.join(_HERE, "liblb_oracle.so")
+_SRC3 = os.path.join(_HERE, "lb_oracle3d.cpp")
+_LIB3 = os.path.join(_HERE, "liblb_oracle3d.so")
 # Plain FP64: no contraction of a*b+c into fma, no fast-math reassociation.
 _CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
 
@@ -26,11 +28,13 @@ _lib = None
 
 
 def build(force=True):
-    """Compile the oracle shared library with g++ (called by the build entry point)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["g++", *_CXXFLAGS, _SRC, "-o", tmp], check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle shared libraries (2-D and 3-D) with g++ (called by the build entry
+    point)."""
+    for src, lib in ((_SRC, _LIB), (_SRC3, _LIB3)):
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            subprocess.run(["g++", *_CXXFLAGS, src, "-o", tmp], check=True)
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -216,3 +220,167 @@ def cs_grad(params: Params, f0, nsteps, loss_weights, param, h=1e-30):
 CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
 CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 WL = np.array([4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36])
+
+
+# ----------------------------------------------------------------------------------------
+# Three dimensions (D3Q19; lb_oracle3d.cpp)
+# ----------------------------------------------------------------------------------------
+
+_lib3 = None
+
+
+def _load3():
+    global _lib3
+    if _lib3 is not None:
+        return _lib3
+    if not os.path.exists(_LIB3) or os.path.getmtime(_LIB3) < os.path.getmtime(_SRC3):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB3)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    lib.orc3_create.restype = vp
+    lib.orc3_create.argtypes = [ctypes.POINTER(Orc3Config)]
+    lib.orc3_destroy.argtypes = [vp]
+    lib.orc3_init_rest.argtypes = [vp, dp]
+    lib.orc3_set_f.argtypes = [vp, dp]
+    lib.orc3_get_f.argtypes = [vp, dp]
+    lib.orc3_time.argtypes = [vp]
+    lib.orc3_time.restype = ctypes.c_int64
+    lib.orc3_nlinks.argtypes = [vp]
+    lib.orc3_nlinks.restype = ip
+    lib.orc3_step.argtypes = [vp, ip, dp]
+    lib.orc3_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+    _lib3 = lib
+    return lib
+
+
+class Orc3Config(ctypes.Structure):
+    _fields_ = [
+        ("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("lz", ctypes.c_int32), ("ns", ctypes.c_int32),
+        ("walls", ctypes.c_int32), ("cross_psi", ctypes.c_int32),
+        ("g1", ctypes.c_double * 2), ("g2", ctypes.c_double * 2), ("gab", ctypes.c_double),
+        ("w", ctypes.c_double * 7), ("p", ctypes.c_double * 7), ("t", ctypes.c_double * 2),
+        ("body", ctypes.c_double * 3), ("rho_wall", ctypes.c_double * 2), ("tau", ctypes.c_double * 2),
+        ("psi0", ctypes.c_double), ("rho0", ctypes.c_double),
+    ]
+
+
+def default_w3():
+    return _weights.as_float_list3(_weights.weights3_w())
+
+
+def default_p3():
+    return _weights.as_float_list3(_weights.weights3_p())
+
+
+def default_t3():
+    t = _weights.weights3_t()
+    return [float(t[1]), float(t[2])]
+
+
+@dataclass
+class Params3:
+    """Parameters of one 3-D simulation (lattice units); walls bound y as in two dimensions."""
+    lx: int
+    ly: int
+    lz: int
+    ns: int = 1
+    walls: int = 0
+    g1: Sequence[float] = (0.0, 0.0)
+    g2: Sequence[float] = (0.0, 0.0)
+    gab: float = 0.0
+    body: Sequence[float] = (0.0, 0.0, 0.0)
+    rho_wall: Sequence[float] = (0.0, 0.0)
+    tau: Sequence[float] = (1.0, 1.0)
+    psi0: float = 1.0
+    rho0: float = 1.0
+    w: Sequence[float] = field(default_factory=default_w3)
+    p: Sequence[float] = field(default_factory=default_p3)
+    t: Sequence[float] = field(default_factory=default_t3)
+    cross_psi: int = 0
+
+    def to_c(self):
+        c = Orc3Config()
+        c.lx, c.ly, c.lz, c.ns, c.walls, c.cross_psi = self.lx, self.ly, self.lz, self.ns, self.walls, self.cross_psi
+        for k in range(2):
+            c.g1[k], c.g2[k] = self.g1[k], self.g2[k]
+            c.rho_wall[k], c.tau[k] = self.rho_wall[k], self.tau[k]
+        for k in range(3):
+            c.body[k] = self.body[k]
+        c.gab = self.gab
+        for q in range(7):
+            c.w[q], c.p[q] = self.w[q], self.p[q]
+        c.t[0], c.t[1] = self.t[0], self.t[1]
+        c.psi0, c.rho0 = self.psi0, self.rho0
+        return c
+
+    def shell_k(self, s=0):
+        """K(q) = G1 w(q) + G2 p(q) for species s, q in (1, 2, 3, 4, 5, 6, 8)."""
+        return [self.g1[s] * self.w[q] + self.g2[s] * self.p[q] for q in range(7)]
+
+
+class Oracle3:
+    """One 3-D simulation on the CPU; state = pre-collision populations f[s][l][z][y][x]."""
+
+    def __init__(self, params: Params3, rho_init=None, f=None):
+        self.params = params
+        self._lib = _load3()
+        self._cfg = params.to_c()
+        self._h = self._lib.orc3_create(ctypes.byref(self._cfg))
+        self.shape = (params.ns, 19, params.lz, params.ly, params.lx)
+        if f is not None:
+            self.set_f(f)
+        elif rho_init is not None:
+            r = np.ascontiguousarray(np.broadcast_to(rho_init, (params.ns, params.lz, params.ly, params.lx)),
+                                     dtype=np.float64)
+            self._lib.orc3_init_rest(self._h, _dp(r))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc3_destroy(h)
+            self._h = None
+
+    @property
+    def time(self):
+        return self._lib.orc3_time(self._h)
+
+    @property
+    def nlinks(self):
+        return self._lib.orc3_nlinks(self._h)
+
+    def set_f(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.shape)
+        self._lib.orc3_set_f(self._h, _dp(f))
+
+    def get_f(self):
+        out = np.empty(self.shape, dtype=np.float64)
+        self._lib.orc3_get_f(self._h, _dp(out))
+        return out
+
+    def step(self, n=1, record=False):
+        """Advance n steps; with record=True return the (n, 8) per-step observables
+        [mass_0, mass_1, P_x, P_y, P_z, W_bot, W_top, Q]."""
+        if record:
+            rec = np.zeros((n, 8), dtype=np.float64)
+            self._lib.orc3_step(self._h, int(n), _dp(rec))
+            return rec
+        self._lib.orc3_step(self._h, int(n), None)
+        return None
+
+    def fields(self):
+        """rho, psi [ns,lz,ly,lx]; force, j [ns,3,lz,ly,lx]; u [3,lz,ly,lx]."""
+        P = self.params
+        rho = np.empty((P.ns, P.lz, P.ly, P.lx))
+        psi = np.empty_like(rho)
+        force = np.empty((P.ns, 3, P.lz, P.ly, P.lx))
+        u = np.empty((3, P.lz, P.ly, P.lx))
+        j = np.empty_like(force)
+        self._lib.orc3_fields(self._h, _dp(rho), _dp(psi), _dp(force), _dp(u), _dp(j))
+        return dict(rho=rho, psi=psi, force=force, u=u, j=j)
+
+
+# D3Q19 tables of the 3-D oracle (same values and order as in lb_oracle3d.cpp).
+CX3 = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0])
+CY3 = np.array([0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1])
+CZ3 = np.array([0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1])
+WL3 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)

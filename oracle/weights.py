@@ -130,3 +130,70 @@ def e6(W):
 
 def as_float_list(W):
     return [float(W.get(q, 0)) for q in SHELLS]
+
+
+# ----------------------------------------------------------------------------------------
+# Three dimensions (the extension of Sec. "Competing interactions"; the paper gives no 3-D
+# weights).  The same two belts over the integer vectors of the 5x5x5 cube: the attractive belt
+# |c|^2 <= 4 (shells 1, 2, 3, 4) and the repulsive belt |c|^2 <= 8 (shells 1, 2, 3, 4, 5, 6, 8),
+# with E2 = 1/3 and isotropy of E^(2n) in three dimensions: sum W cx^(2a) cy^(2b) cz^(2c) equals
+# e_2n (2a-1)!! (2b-1)!! (2c-1)!! for every a + b + c = n.  Sixth order fixes w on four shells
+# and eighth order fixes p on seven; the A-B weights t are the D3Q19 weights.
+# ----------------------------------------------------------------------------------------
+
+SHELLS3 = (1, 2, 3, 4, 5, 6, 8)
+
+
+def shell_links3(q):
+    """All integer vectors c with |c|^2 == q inside the 5x5x5 neighbourhood."""
+    return [c for c in product(range(-2, 3), repeat=3) if sum(v * v for v in c) == q]
+
+
+def moment3(q, a, b, c):
+    """sum over the links of shell q of cx^a cy^b cz^c (an integer)."""
+    return sum(x ** a * y ** b * z ** c for x, y, z in shell_links3(q))
+
+
+def isotropy_rows3(shells, order):
+    """Linear conditions for isotropy of the 3-D tensors E^(4) .. E^(order): one row per
+    partition a >= b >= c of n other than (n, 0, 0), against the (n, 0, 0) moment."""
+    rows = []
+    for n in range(2, order // 2 + 1):
+        for a in range(n, -1, -1):
+            for b in range(min(a, n - a), -1, -1):
+                c = n - a - b
+                if c > b or (a, b, c) == (n, 0, 0):
+                    continue
+                rows.append([Fraction(moment3(q, 2 * a, 2 * b, 2 * c) * _dfact(2 * n - 1)
+                                      - moment3(q, 2 * n, 0, 0) * _dfact(2 * a - 1) * _dfact(2 * b - 1)
+                                      * _dfact(2 * c - 1)) for q in shells])
+    return rows
+
+
+def isotropic_weights3(shells, order, e2=Fraction(1, 3)):
+    rows = [[Fraction(moment3(q, 2, 0, 0)) for q in shells]]
+    rhs = [Fraction(e2)]
+    for r in isotropy_rows3(shells, order):
+        rows.append(r)
+        rhs.append(Fraction(0))
+    return dict(zip(shells, _solve(rows, rhs)))
+
+
+def weights3_w():
+    """3-D attractive weights w(q), sixth-order isotropic on shells {1, 2, 3, 4}; zero beyond."""
+    w = isotropic_weights3((1, 2, 3, 4), 6)
+    return {q: w.get(q, Fraction(0)) for q in SHELLS3}
+
+
+def weights3_p():
+    """3-D repulsive weights p(q), eighth-order isotropic on shells {1, 2, 3, 4, 5, 6, 8}."""
+    return isotropic_weights3(SHELLS3, 8)
+
+
+def weights3_t():
+    """3-D A-B cross weights on shells {1, 2} (the D3Q19 weights)."""
+    return isotropic_weights3((1, 2), 4)
+
+
+def as_float_list3(W):
+    return [float(W.get(q, 0)) for q in SHELLS3]
