@@ -462,3 +462,118 @@ class Batch:
             raise ValueError("populations must have shape (n_species, 9, ly, lx)")
         self._keep = f
         self._chk(self._lib.lb_batch_restore(self._h, int(i), ctypes.c_void_p(f.data_ptr())))
+
+
+class Sim3:
+    """One 3-D lattice (D3Q19, include/lb3.h) on one GPU: the two-belt force over the 5x5x5
+    cube, one or two species, periodic or bounded in y by bounce-back walls.  rho_init:
+    [n_species, lz, ly, lx] host array; the state starts at rest.  Storage "f64" or "f32"."""
+
+    def __init__(self, lx, ly, lz, rho_init, n_species=1, walls=False, storage="f64", g1=(0.0, 0.0),
+                 g2=(0.0, 0.0), gab=0.0, body=(0.0, 0.0, 0.0), rho_wall=(0.0, 0.0), tau=(1.0, 1.0), psi0=1.0,
+                 rho0=1.0, rho_ref=None, w=None, p=None, t=None, cross_psi=False, device="cuda", tile=None):
+        import torch
+        self._lib = B.load()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.lx, self.ly, self.lz, self.ns = int(lx), int(ly), int(lz), int(n_species)
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.lat = B.Lb3Lattice(self.lx, self.ly, self.lz, self.ns, 1 if walls else 0, self.storage)
+        c = B.Lb3Couplings()
+        B.check3(self._lib.lb3_default_couplings(ctypes.byref(c)))
+        g1, g2, rw = _pair(g1), _pair(g2), _pair(rho_wall)
+        for k in range(2):
+            c.g1[k], c.g2[k], c.rho_wall[k] = g1[k], g2[k], rw[k]
+        c.g_ab = float(gab)
+        for k in range(3):
+            c.body_force[k] = float(body[k])
+        if w is not None:
+            for q in range(7):
+                c.w[q] = float(w[q])
+        if p is not None:
+            for q in range(7):
+                c.p[q] = float(p[q])
+        if t is not None:
+            c.t[0], c.t[1] = float(t[0]), float(t[1])
+        c.cross_uses_psi = 1 if cross_psi else 0
+        self.cpl = c
+        self.tau = (ctypes.c_double * 2)(*_pair(tau))
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho_init, dtype=np.float64),
+                                                   (self.ns, self.lz, self.ly, self.lx)))
+        ref = rho_ref if rho_ref is not None else tuple(float(rho[s].mean()) for s in range(self.ns))
+        self.psi = B.LbPsiParams(float(psi0), float(rho0), (ctypes.c_double * 2)(*_pair(ref)))
+        nbytes = self._lib.lb3_pop_bytes(ctypes.byref(self.lat))
+        if nbytes == 0:
+            raise LbError(B.LB_EINVAL, "invalid 3-D lattice")
+        self.pop_bytes = nbytes
+        self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self._lib.lb3_init(ctypes.byref(h), ctypes.byref(self.lat), ctypes.byref(c), self.tau,
+                                ctypes.byref(self.psi), rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                ctypes.c_void_p(self.pop_a.data_ptr()), ctypes.c_void_p(self.pop_b.data_ptr()),
+                                nbytes, ctypes.c_void_p(self.stream.cuda_stream))
+        B.check3(rc, None)
+        self._h = h
+        if tile is not None:
+            self.set_tile(*tile)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lb3_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        return B.check3(rc, self._h)
+
+    @property
+    def time(self):
+        return self._lib.lb3_time(self._h)
+
+    def step(self, n=1):
+        self._chk(self._lib.lb3_step(self._h, int(n)))
+
+    def set_tile(self, ty, sz):
+        self._chk(self._lib.lb3_set_tile(self._h, int(ty), int(sz)))
+
+    def get_tile(self):
+        ty, sz = ctypes.c_int32(), ctypes.c_int32()
+        self._chk(self._lib.lb3_get_tile(self._h, ctypes.byref(ty), ctypes.byref(sz)))
+        return ty.value, sz.value
+
+    def moments(self, dtype=None):
+        """(rho [ns, lz, ly, lx], u [3, lz, ly, lx]) device tensors of the current state."""
+        torch = self.torch
+        dtype = dtype or torch.float64
+        rho = torch.empty((self.ns, self.lz, self.ly, self.lx), dtype=dtype, device=self.device)
+        u = torch.empty((3, self.lz, self.ly, self.lx), dtype=dtype, device=self.device)
+        code = B.LB_OUT_F32 if dtype == torch.float32 else B.LB_OUT_F64
+        self._chk(self._lib.lb3_moments(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr()), code))
+        return rho, u
+
+    def totals(self):
+        """(mass[2], momentum[3], flow) of the current state (FP64; synchronises)."""
+        m, p, q = (ctypes.c_double * 2)(), (ctypes.c_double * 3)(), ctypes.c_double()
+        self._chk(self._lib.lb3_totals(self._h, m, p, ctypes.byref(q)))
+        return list(m), list(p), q.value
+
+    def checkpoint(self):
+        """Canonical FP64 pre-collision populations f[ns, 19, lz, ly, lx] (device tensor)."""
+        f = self.torch.empty((self.ns, 19, self.lz, self.ly, self.lx), dtype=self.torch.float64, device=self.device)
+        self._chk(self._lib.lb3_checkpoint(self._h, ctypes.c_void_p(f.data_ptr())))
+        return f
+
+    def restore(self, f):
+        f = self.torch.as_tensor(f, dtype=self.torch.float64, device=self.device).contiguous()
+        if tuple(f.shape) != (self.ns, 19, self.lz, self.ly, self.lx):
+            raise ValueError("populations must have shape (n_species, 19, lz, ly, lx)")
+        self._keep = f
+        self._chk(self._lib.lb3_restore(self._h, ctypes.c_void_p(f.data_ptr())))

@@ -36,6 +36,18 @@ class LbPsiParams(ctypes.Structure):
     _fields_ = [("psi0", ctypes.c_double), ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double * 2)]
 
 
+class Lb3Lattice(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("lz", ctypes.c_int32),
+                ("n_species", ctypes.c_int32), ("walls", ctypes.c_int32), ("storage", ctypes.c_int32)]
+
+
+class Lb3Couplings(ctypes.Structure):
+    _fields_ = [("g1", ctypes.c_double * 2), ("g2", ctypes.c_double * 2), ("g_ab", ctypes.c_double),
+                ("w", ctypes.c_double * 7), ("p", ctypes.c_double * 7), ("t", ctypes.c_double * 2),
+                ("body_force", ctypes.c_double * 3), ("rho_wall", ctypes.c_double * 2),
+                ("cross_uses_psi", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
 class LbError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -101,6 +113,21 @@ SIGNATURES = {
     "lb_batch_set_time": (ctypes.c_int, [_vp, _i64]),
     "lb_batch_last_error": (ctypes.c_char_p, [_vp]),
     "lb_batch_destroy": (None, [_vp]),
+    # 3-D extension (include/lb3.h)
+    "lb3_default_couplings": (ctypes.c_int, [ctypes.POINTER(Lb3Couplings)]),
+    "lb3_pop_bytes": (_sz, [ctypes.POINTER(Lb3Lattice)]),
+    "lb3_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Lb3Lattice), ctypes.POINTER(Lb3Couplings), _dp,
+                                ctypes.POINTER(LbPsiParams), _dp, _vp, _vp, _sz, _vp]),
+    "lb3_step": (ctypes.c_int, [_vp, _i64]),
+    "lb3_moments": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "lb3_totals": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "lb3_checkpoint": (ctypes.c_int, [_vp, _vp]),
+    "lb3_restore": (ctypes.c_int, [_vp, _vp]),
+    "lb3_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
+    "lb3_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "lb3_time": (_i64, [_vp]),
+    "lb3_last_error": (ctypes.c_char_p, [_vp]),
+    "lb3_destroy": (None, [_vp]),
 }
 
 
@@ -146,3 +173,10 @@ def default_couplings():
 
 def pop_bytes(lattice):
     return load().lb_pop_bytes(ctypes.byref(lattice))
+
+
+def check3(rc, ctx=None):
+    if rc != LB_OK:
+        msg = load().lb3_last_error(ctx)
+        raise LbError(rc, msg.decode() if msg else "")
+    return rc

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblb355.so")
-SOURCES = ["lb_step_f64.hip", "lb_step_f32.hip", "lb_step_bf16.hip", "lb_kernels.hip", "lb_adjoint.hip", "lb_static.hip",
-           "lb_api.cpp", "lb_batch.cpp", "lb_rheology.cpp"]
+SOURCES = ["lb_step_f64.hip", "lb_step_f32.hip", "lb_step_bf16.hip", "lb_kernels.hip", "lb_adjoint.hip", "lb_static.hip", "lb3_kernels.hip",
+           "lb_api.cpp", "lb_batch.cpp", "lb_rheology.cpp", "lb3_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

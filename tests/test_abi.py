@@ -47,6 +47,44 @@ def test_default_weights_match_oracle_derivation(B):
     np.testing.assert_array_equal(list(c.t), [float(t[1]), float(t[2])])
 
 
+def test_3d_default_weights_match_oracle_derivation(B):
+    """The 3-D library's default weights equal the oracle's sets, derived from the 3-D isotropy
+    conditions by exact rational elimination (w sixth order, p eighth order, t the D3Q19 set)."""
+    from oracle import weights as wt
+    c = B.Lb3Couplings()
+    assert B.load().lb3_default_couplings(ctypes.byref(c)) == 0
+    np.testing.assert_array_equal(list(c.w), wt.as_float_list3(wt.weights3_w()))
+    np.testing.assert_array_equal(list(c.p), wt.as_float_list3(wt.weights3_p()))
+    t = wt.weights3_t()
+    np.testing.assert_array_equal(list(c.t), [float(t[1]), float(t[2])])
+
+
+def test_3d_pop_bytes_and_host_validation(B):
+    lib = B.load()
+    for lx, ly, lz, ns, st, es in ((5, 5, 5, 1, 0, 8), (70, 21, 13, 2, 1, 4), (256, 256, 256, 2, 0, 8)):
+        lat = B.Lb3Lattice(lx, ly, lz, ns, 0, st)
+        pitch = (lx + 63) // 64 * 64
+        assert lib.lb3_pop_bytes(ctypes.byref(lat)) == lz * ly * 19 * pitch * ns * es
+    assert lib.lb3_pop_bytes(ctypes.byref(B.Lb3Lattice(5, 5, 4, 1, 0, 0))) == 0
+    assert lib.lb3_pop_bytes(ctypes.byref(B.Lb3Lattice(8, 8, 8, 1, 0, 2))) == 0  # no BF16 in 3-D
+    cpl = B.Lb3Couplings()
+    lib.lb3_default_couplings(ctypes.byref(cpl))
+    pp = B.LbPsiParams(1.0, 1.0, (ctypes.c_double * 2)(0.0, 0.0))
+    rho = np.ones((1, 8, 8, 8))
+    h = ctypes.c_void_p()
+    bad_tau = (ctypes.c_double * 2)(0.5, 1.0)
+    rc = lib.lb3_init(ctypes.byref(h), ctypes.byref(B.Lb3Lattice(8, 8, 8, 1, 0, 0)), ctypes.byref(cpl), bad_tau,
+                      ctypes.byref(pp), rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(16),
+                      ctypes.c_void_p(32), 1 << 40, None)
+    assert rc == B.LB_EINVAL and b"tau" in lib.lb3_last_error(None)
+    rho[0, 3, 3, 3] = -1.0
+    rc = lib.lb3_init(ctypes.byref(h), ctypes.byref(B.Lb3Lattice(8, 8, 8, 1, 0, 0)), ctypes.byref(cpl),
+                      (ctypes.c_double * 2)(1.0, 1.0), ctypes.byref(pp),
+                      rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                      1 << 40, None)
+    assert rc == B.LB_EINVAL and b"rho_init" in lib.lb3_last_error(None)
+
+
 @pytest.mark.parametrize("storage,es", [(0, 8), (1, 4), (2, 2)])
 def test_pop_bytes(B, storage, es):
     for lx, ly, ns in ((5, 5, 1), (64, 7, 2), (1000, 33, 2)):
