@@ -199,3 +199,41 @@ def test_adjoint_full_horizon_fp32_forward():
     e_f32 = np.abs(out[("f32", False)] - ref) / np.abs(ref)
     print(f"T=4000: FP32 forward + FP64 reverse rel err {e_mixed}; all-FP32 {e_f32}", flush=True)
     assert e_mixed.max() < 1e-4
+
+
+def test_adjoint_full_horizon_against_oracle_gradient():
+    """The adjoint benchmark at its full horizon against the FP64 oracle's gradient: 512 x 256
+    channel, the oracle's own 2000-step pre-relaxation (recomputed here on the host cores and
+    checked against the fixture's digest), restored into the GPU context, T = 4000.  The
+    fixture tests/golden/adjoint_channel_512x256_T4000.json holds the oracle's complex-step
+    gradient, written by make_adjoint_channel_4000.py beside it from the oracle alone.  FP64
+    adjoint within 1e-8; FP32 forward with the FP64 reverse sweep within 1e-4."""
+    import importlib.util
+    import json
+    import os
+    import oracle
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_adj", os.path.join(here, "make_adjoint_channel_4000.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    fix = json.load(open(os.path.join(here, "adjoint_channel_512x256_T4000.json")))
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    f0 = mk.prerelaxed_state()
+    assert mk.state_digest(f0) == fix["prerelaxed_state_sha256_16"]
+    d_o = np.array(fix["grad"])
+    rho, _ = lbgen.emulsion(mk.LX, mk.LY, fraction=0.8, seed=5, walls=True)
+    P = mk.params()
+    c = dict(lx=mk.LX, ly=mk.LY, ns=2, walls=1, g1=P.g1, g2=P.g2, gab=P.gab, body=P.body, rho_wall=P.rho_wall,
+             tau=P.tau, psi0=P.psi0, rho0=P.rho0, rho=rho, storage="f64", rho_ref=(0.0, 0.0))
+    res = {}
+    for storage, tol in (("f64", 1e-8), ("f32", 1e-4)):
+        sim = make_sim(dict(c, storage=storage, rho_ref=(0.0, 0.0) if storage == "f64" else
+                            (float(rho[0].mean()), float(rho[1].mean()))))
+        sim.restore(f0)
+        loss, g7 = sim.adjoint(fix["T"], tuple(fix["loss_weights"]), fp64_reverse=True)
+        sim.close()
+        e = np.abs(to4(g7) - d_o) / np.abs(d_o)
+        res[storage] = e
+        print(f"T=4000 {storage} forward, FP64 reverse: loss {loss:.12e} vs {fix['loss']:.12e}; "
+              f"rel err vs oracle {e}", flush=True)
+        assert e.max() < tol, (storage, e)
