@@ -29,7 +29,8 @@ BYTES_PER_VALUE = {"f64": 8, "f32": 4, "bf16dev": 2}
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lb_kernels.hip", "lb_internal.hpp", "lb_tables.hpp"):
+    for f in ("lb_step.hpp", "lb_step_f64.hip", "lb_step_f32.hip", "lb_step_bf16.hip", "lb_kernels.hip",
+              "lb_internal.hpp", "lb_tables.hpp"):
         with open(os.path.join(ROOT, "paper_1402_6019_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -148,19 +149,22 @@ def channel_long_run(steps=50000, average_last=25000, every=100):
         sim = Sim(lx, ly, rho, storage=storage, **kw)
         if rounding:
             sim.set_rounding(rounding)
+        m0, p0, _ = sim.totals()
         sim.set_graph(every)
         sim.step(steps - average_last)
         st = sim.profile_stats(sim.sample_profiles(average_last // every, every))
         torch.cuda.synchronize()
         u, sig, ra = (st[k].cpu().numpy() for k in ("u", "sigma", "rho_a"))
-        avg[name] = {"u": u, "sigma": sig, "rho_a": ra, "seconds": time.perf_counter() - t0}
+        m1, p1, _ = sim.totals()
+        avg[name] = {"u": u, "sigma": sig, "rho_a": ra, "seconds": time.perf_counter() - t0,
+                     "drift": conservation_drift(m0, m1, p0, p1, walls=True)}
         sim.close()
     ref = avg["f64"]
     out = {"workload": f"confined emulsion channel {lx}x{ly}, fraction 0.85, seed 3, g = 1e-6, {steps} steps, "
                        f"profiles averaged over the last {average_last} (every {every})",
            "f64": {"flow_rate": float(ref["u"].sum()), "u_max": float(ref["u"].max()),
                    "wall_stress_bot_top": [float(ref["sigma"][0]), float(-ref["sigma"][-1])],
-                   "seconds": ref["seconds"]}}
+                   "seconds": ref["seconds"], "drift": ref["drift"]}}
     for name in ("f32", "bf16dev", "bf16dev_stochastic"):
         a = avg[name]
         out[name] = {
@@ -169,7 +173,134 @@ def channel_long_run(steps=50000, average_last=25000, every=100):
             "flow_rate_rel_err": float(abs(a["u"].sum() - ref["u"].sum()) / abs(ref["u"].sum())),
             "wall_stress_rel_err": [float(abs(a["sigma"][0] - ref["sigma"][0]) / abs(ref["sigma"][0])),
                                     float(abs(a["sigma"][-1] - ref["sigma"][-1]) / abs(ref["sigma"][-1]))],
-            "seconds": a["seconds"]}
+            "seconds": a["seconds"], "drift": a["drift"]}
+    return out
+
+
+def conservation_drift(m0, m1, p0, p1, walls):
+    """Relative change of each species' mass (FP64 totals) and, on periodic lattices without a
+    body force, of the total momentum relative to the total mass (momentum per unit mass).  The
+    walls of a channel exchange momentum with the fluid in both directions, so there only the
+    masses are invariants."""
+    M = m0[0] + m0[1]
+    out = {"mass_rel": [abs(m1[s] - m0[s]) / m0[s] if m0[s] else 0.0 for s in range(2)]}
+    if not walls:
+        out["momentum_per_mass"] = max(abs(a - b) for a, b in zip(p1, p0)) / M
+    return out
+
+
+def long_run_1024(steps=20000):
+    """The 1024^2 emulsion (the headline workload) run for `steps` steps in FP64 and FP32 from
+    the same state: time, and the drift of each species' mass and of the total momentum
+    (periodic, no body force: both are conserved), from the FP64 reductions."""
+    import torch
+    from paper_1402_6019_amd import Sim
+    rho, _, kw = workload()
+    out = {"workload": f"emulsion 1024x1024 periodic, fraction 0.8, seed 2, {steps} steps"}
+    for storage in ("f64", "f32"):
+        sim = Sim(LX, LY, rho, storage=storage, **kw)
+        m0, p0, _ = sim.totals()
+        sim.set_graph(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        m1, p1, _ = sim.totals()
+        sim.close()
+        out[storage] = {"seconds": dt, "mlups": LX * LY * steps / dt / 1e6,
+                        "drift": conservation_drift(m0, m1, p0, p1, walls=False)}
+    return out
+
+
+def single_component_64(steps=1000):
+    """Config 1: one component, 64 x 64 periodic, film couplings (G1 = -20.4, G2 = 16), tau = 1,
+    rho = 1 + 0.01 U(-1, 1) (seed 1), FP64, 1000 steps: the GPU's time (launch-bound at this
+    size; no roofline claim) against the FP64 oracle on one host thread and on all of them, the
+    same run; and the GPU's fields against the oracle's at the end."""
+    import numpy as np
+    import torch
+    import lbgen
+    import oracle
+    from oracle import Oracle, Params
+    from paper_1402_6019_amd import Sim
+    n = 64
+    rho = lbgen.uniform_noise(n, n, 1.0, 0.01, seed=1)[None]
+    kw = dict(n_species=1, walls=False, g1=(lbgen.FILM_G1, 0.0), g2=(lbgen.FILM_G2, 0.0), tau=(1.0, 1.0), psi0=1.0,
+              rho0=1.0)
+    sim = Sim(n, n, rho, storage="f64", **kw)
+    sim.set_graph(100)
+    sim.step(100)
+    torch.cuda.synchronize()
+    sim.restore(torch.as_tensor(np.broadcast_to(np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[None, :, None, None]
+                                                * rho[:, None], (1, 9, n, n)).copy()))
+    sim.set_time(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r_gpu = sim.moments()[0].cpu().numpy()
+    m1, p1, _ = sim.totals()
+    sim.close()
+    P = Params(lx=n, ly=n, ns=1, g1=kw["g1"], g2=kw["g2"], tau=kw["tau"], psi0=1.0, rho0=1.0)
+    threads = oracle.get_threads()
+    res = {}
+    for nt in (1, threads):
+        oracle.set_threads(nt)
+        o = Oracle(P, rho_init=rho)
+        t0 = time.perf_counter()
+        o.step(steps)
+        res[nt] = (time.perf_counter() - t0, o.fields()["rho"])
+    oracle.set_threads(threads)
+    ref = res[threads][1]
+    return {"workload": f"one component, {n}x{n} periodic, film couplings, tau = 1, seed 1, {steps} steps, FP64",
+            "gpu_seconds": dt, "gpu_mlups": n * n * steps / dt / 1e6,
+            "oracle_1_thread_seconds": res[1][0], "oracle_1_thread_mlups": n * n * steps / res[1][0] / 1e6,
+            "oracle_all_threads_seconds": res[threads][0], "oracle_threads": threads,
+            "oracle_all_threads_mlups": n * n * steps / res[threads][0] / 1e6,
+            "rho_rel_err_vs_oracle": float(np.abs(r_gpu - ref).max() / np.abs(ref).max()),
+            "mass_rel_drift": abs(m1[0] - float(rho.sum())) / float(rho.sum())}
+
+
+def three_d(steps):
+    """The 3-D extension (include/lb3.h): two-component emulsion, 256^3 periodic (a seeded 128^3
+    periodic emulsion, radii U(6, 12), volume fraction 0.5, tiled 2 x 2 x 2), emulsion couplings,
+    D3Q19 with the two-belt cube stencil; FP32 and FP64 steps timed with HIP events on the
+    context's stream; algorithmic bytes per lattice update 2 * 19 * 2 values; mass and momentum
+    drift over the timed steps."""
+    import numpy as np
+    import torch
+    import lbgen
+    from paper_1402_6019_amd import Sim3
+    n = 256
+    rho = np.tile(lbgen.emulsion3d(128, 128, 128, fraction=0.5, seed=7, rmin=6.0, rmax=12.0)[0], (1, 2, 2, 2))
+    kw = dict(n_species=2, walls=False, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+              tau=(1.0, 1.0), psi0=1.0, rho0=lbgen.EMULSION_RHO0,
+              rho_ref=(float(rho[0].mean()), float(rho[1].mean())))
+    out = {"workload": f"3-D two-component emulsion {n}^3 periodic, fraction 0.5, seed 7 (128^3 tiled 2x2x2)"}
+    sites = n ** 3
+    for storage, bpv in (("f32", 4), ("f64", 8)):
+        sim = Sim3(n, n, n, rho, storage=storage, **kw)
+        sim.step(5)
+        m0, p0, _ = sim.totals()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(sim.stream)
+        sim.step(steps)
+        stop.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        m1, p1, _ = sim.totals()
+        tile = sim.get_tile()
+        sim.close()
+        bpl = 2 * 19 * 2 * bpv
+        gbs = bpl * sites / (ms * 1e-3) / 1e9
+        out[storage] = {"ms_per_step": ms, "mlups": sites / (ms * 1e-3) / 1e6, "bytes_per_lu": bpl,
+                        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": gbs / HBM_PEAK_GBS},
+                        "tile_ty_sz": list(tile), "footprint_mb": 2 * bpl / 2 * sites / 1e6,
+                        "drift": conservation_drift(m0, m1, p0, p1, walls=False)}
     return out
 
 
@@ -210,6 +341,16 @@ def batched_sweep(steps, n=64):
     stop.record(b.stream)
     torch.cuda.synchronize()
     ms_eager = start.elapsed_time(stop) / steps
+    # the sweep's horizon: 10,000 graph-replayed steps in all, then every instance's health
+    # and FP64 species masses against the initial ones
+    tot0 = b.totals()
+    b.set_graph(graph)
+    horizon = 10000
+    b.step(max(0, horizon - b.time))
+    tot1 = b.totals()  # raises on a latched non-finite or non-positive density
+    import numpy as np
+    mass_drift = float(np.max(np.abs(tot1[:, :2] - tot0[:, :2]) / tot0[:, :2]))
+    steps_done = b.time
     b.close()
     gbs = 144 * sites / (ms * 1e-3) / 1e9
     return {"workload": f"{n} confined emulsion channels, Ly U{{64..512}}, Lx U{{256..2048}}, per-instance "
@@ -217,7 +358,8 @@ def batched_sweep(steps, n=64):
             "ms_per_step": ms, "ms_per_step_eager": ms_eager, "mlups": sites / (ms * 1e-3) / 1e6, "gbs": gbs,
             "frac": gbs / HBM_PEAK_GBS, "graph_steps": graph, "tile": [tx, sy], "grid": grid,
             "default_tile": list(default_tile), "autotune_best_ms": tuned_ms,
-            "footprint_mb": 144 * sites / 1e6}
+            "footprint_mb": 144 * sites / 1e6, "steps_total": steps_done, "all_instances_healthy": True,
+            "max_species_mass_drift_fp32": mass_drift}
 
 
 def auxiliary_passes(rho, kw, reps=200):
@@ -668,11 +810,26 @@ def cpu_baseline(rho, kw, budget_s=15.0):
         "value": LX * LY * n / dt / 1e6,
         "unit": "MLUPS",
         "cores": threads,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": f"{n} steps (steps 100..{100 + n}) of the same 1024x1024 two-component lattice from the "
                   f"same initial state ({dt:.1f} s, FP64, OpenMP over rows)",
         "one_thread_mlups": LX * LY * 3 / dt1 / 1e6,
     }, refs, chan_ref
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs)"
 
 
 def traffic_from_profile(kernel_hash, storage, tile):
@@ -744,7 +901,17 @@ def main():
             "copy_ceiling_gbs": copy["gbs"], "frac_of_copy": head["gbs"] / copy["gbs"],
             "stream_copy_gbs": max(copy["stream_copy_gbs"], copy["stream_copy_nt_gbs"]),
             "frac_of_stream_copy": head["gbs"] / max(copy["stream_copy_gbs"], copy["stream_copy_nt_gbs"]),
-            "note": "footprint 2 x 75.5 MB fits in the 256 MB Infinity Cache"}
+            "served_by": "infinity_cache",
+            "note": "footprint 2 x 75.5 MB fits in the 256 MB Infinity Cache, so this rate is served by that "
+                    "cache, not by HBM; hbm_served gives the same kernel on the 4096 x 512 channel, whose "
+                    "302 MB footprint exceeds it"}
+    beyond = None if args.core else channel_beyond_cache(max(50, args.steps // 4))
+    if beyond is not None:
+        ch = beyond["f32"]
+        roof["hbm_served"] = {"workload": beyond["workload"], "achieved": ch["gbs"], "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": ch["frac"], "mlups": ch["mlups"],
+                              "footprint_mb": ch["footprint_mb"],
+                              "kernel": "step_kernel<F32, 2 species, channel>, streaming stores"}
 
     out = {
         # value: FP32 MLUPS; % of HBM peak in roofline.frac; FP64 (and BF16) beside it; the
@@ -778,7 +945,10 @@ def main():
                             "bf16dev": res["f64"]["ms_per_step"] / res["bf16dev"]["ms_per_step"]},
         "tiles": {k: v["tile"] for k, v in res.items()},
         "copy_reference": copy,
-        "beyond_infinity_cache": None if args.core else channel_beyond_cache(max(50, args.steps // 4)),
+        "beyond_infinity_cache": beyond,
+        "long_run_1024_20k": None if args.core else long_run_1024(),
+        "config1_single_component_64": None if args.core or args.no_cpu else single_component_64(),
+        "three_d": None if args.core else three_d(max(20, args.steps // 40)),
         "channel_50k_averages": None if args.core else channel_long_run(),
         "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
         "couette_cell": None if args.core else couette_cell(max(200, args.steps // 2)),
