@@ -247,6 +247,16 @@ int lb_set_store_policy(lb_ctx *ctx, int32_t policy);
    stochastically rounding contexts (it recomputes states).  Host call. */
 int lb_set_rounding(lb_ctx *ctx, int32_t mode);
 
+/* Temporal blocking (FP32 and BF16 storage): with enable = 1, lb_step advances plain steps
+   (no reductions, lb_set_reduce_every k = 0) two at a time, one launch per pair, keeping the
+   intermediate post-collision populations on chip, so the populations cross HBM once per two
+   steps.  Each wave updates a strip of 54 columns from a 64-column window and a segment of
+   `rows` rows (0: the default, sized so the whole grid is resident), recomputing the overlaps.
+   The per-site arithmetic and the rounding of the intermediate to the storage format are those
+   of two single steps: results are bitwise identical to enable = 0 (also with stochastic BF16
+   rounding and under graph replay).  LB_EINVAL for FP64 storage or rows < 0.  Host call. */
+int lb_set_two_step(lb_ctx *ctx, int32_t enable, int32_t rows);
+
 /* Replay plain steps from captured HIP graphs: with steps > 0 (even) and no reductions
    (lb_set_reduce_every k = 0), lb_step runs whole groups of `steps` launches as one graph
    launch on the context's stream and the remainder one by one.  Graphs are captured on first

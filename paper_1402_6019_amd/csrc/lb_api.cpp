@@ -42,6 +42,8 @@ struct lb_ctx {
   int device = 0;  // device current at lb_init
   int reduce_every = 0;
   int store_policy = LB_STORES_AUTO;
+  int two_step = 0;  // plain steps in pairs, two time steps per launch (FP32 / BF16)
+  int sy2 = 0;       // rows per segment of the two-step kernel (0: the resident-grid default)
   int rounding = LB_ROUND_NEAREST;  // BF16 stores: nearest or stochastic
   double *d_tbase = nullptr;        // step at which a graph replay starts (stochastic rounding)
   int64_t t = 0;
@@ -117,6 +119,39 @@ hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st, uint32_t
   a.t_step = t_step;
   a.t_base = t_base;
   return launch_step(step_mode(c), c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
+}
+
+// Segments of the two-step kernel: rows per segment (the context's choice, or the default that
+// makes the whole grid resident at once) and the grid size.
+int grid2(const lb_ctx *c, int *sy_out, int *nseg_out) {
+  const int nstrip = (c->lat.lx + 53) / 54;
+  int sy = c->sy2;
+  if (sy <= 0) {
+    const int resident = std::max(1, blocks2_per_cu_f32(c->lat.n_species, c->lat.walls)) * c->n_cu;
+    const int nseg = std::max(1, resident / nstrip);
+    sy = std::max(1, (c->lat.ly + nseg - 1) / nseg);
+  }
+  sy = std::min(sy, c->lat.ly);
+  const int nseg = (c->lat.ly + sy - 1) / sy;
+  if (sy_out) *sy_out = sy;
+  if (nseg_out) *nseg_out = nseg;
+  return nstrip * nseg;
+}
+
+// Two plain steps in one launch (time steps t_step and t_step + 1) from buffer `from` to the
+// other one.
+hipError_t launch_two_steps(const lb_ctx *c, int from, hipStream_t st, uint32_t t_step, const double *t_base) {
+  int sy = 0, nseg = 0;
+  const int nb = grid2(c, &sy, &nseg);
+  StepArgs a;
+  fill_step_args(c, a);
+  a.sy = sy;
+  a.nseg = nseg;
+  a.src = c->pop[from];
+  a.dst = c->pop[from ^ 1];
+  a.t_step = t_step;
+  a.t_base = t_base;
+  return launch_step2(step_mode(c), c->lat.n_species, c->lat.walls, nb, a, st);
 }
 
 // Canonical FP64 pre-collision populations of buffer `from` into dst, and the reverse step's
@@ -360,14 +395,30 @@ int lb_step(lb_ctx *c, int64_t n) {
       hipGraphExec_t g = nullptr;
       const int from = c->cur;
       const double *tb = c->rounding == LB_ROUND_STOCHASTIC ? c->d_tbase : nullptr;
+      const bool pairs = c->two_step != 0;
       hipError_t e = c->graph.get(
-          from, [&](int k, hipStream_t st) { return launch_plain_step(c, from ^ (k & 1), st, (uint32_t)k, tb); }, &g);
+          from,
+          [&](int k, hipStream_t st) {
+            if (!pairs) return launch_plain_step(c, from ^ (k & 1), st, (uint32_t)k, tb);
+            // two steps per launch: one launch for each even k, the buffers swap once per launch
+            return (k & 1) ? hipSuccess : launch_two_steps(c, from ^ ((k >> 1) & 1), st, (uint32_t)k, tb);
+          },
+          &g);
       // the replay's steps are t + k: the base goes to device memory (a fill kernel, outside the graph)
       if (e == hipSuccess && tb) e = launch_fill(c->d_tbase, (double)c->t, 1, c->stream);
       if (e == hipSuccess) e = hipGraphLaunch(g, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "step graph");
       c->t += c->graph.steps;
+      if (pairs) c->cur ^= (c->graph.steps >> 1) & 1;
       n -= c->graph.steps;
+    }
+  }
+  if (c->two_step && c->reduce_every == 0) {
+    for (; n >= 2; n -= 2) {
+      hipError_t e = launch_two_steps(c, c->cur, c->stream, (uint32_t)c->t, nullptr);
+      if (e != hipSuccess) return hip_fail(c, e, "two-step kernel launch");
+      c->cur ^= 1;
+      c->t += 2;
     }
   }
   for (int64_t k = 0; k < n; ++k) {
@@ -513,6 +564,17 @@ int lb_restore(lb_ctx *c, const void *src) {
 }
 
 int64_t lb_time(const lb_ctx *c) { return c ? c->t : -1; }
+
+int lb_set_two_step(lb_ctx *c, int32_t enable, int32_t rows) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (enable != 0 && enable != 1) return fail(c, LB_EINVAL, "enable must be 0 or 1");
+  if (enable && c->lat.storage == LB_F64) return fail(c, LB_EINVAL, "two steps per launch: FP32 and BF16 storage only");
+  if (rows < 0) return fail(c, LB_EINVAL, "rows must be >= 0");
+  c->two_step = enable;
+  c->sy2 = rows;
+  c->graph.clear();  // captured launches change
+  return LB_OK;
+}
 
 int lb_set_time(lb_ctx *c, int64_t t) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");

@@ -147,6 +147,7 @@ hipError_t launch_adjoint_reduce(const double *partials, int lx, int ly, double 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 
 // Host-side launchers (lb_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_step2(int mode, int ns, int walls, int nblocks, const StepArgs &a, hipStream_t st);
 hipError_t launch_step(int mode, int ns, int walls, int what, int tx, int nblocks, const StepArgs &a,
                        hipStream_t st);
 hipError_t launch_reduce(const double *partials, int nblocks, double *totals, double *acc, int accumulate,
@@ -200,6 +201,11 @@ hipError_t launch_batch_f32(int ns, int walls, int what, int tx, int grid, const
 hipError_t launch_batch_bf16(bool stochastic, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
                              hipStream_t st);
 int blocks_per_cu_f64(int ns, int walls, int tx);
+// Two time steps per launch (lb_step2.hpp; FP32 and BF16 storage): one wave per workgroup,
+// strips of 54 columns, nb = strips x segments workgroups, a.sy rows per segment.
+hipError_t launch_step2_f32(int ns, int walls, int nb, const StepArgs &a, hipStream_t st);
+hipError_t launch_step2_bf16(bool stochastic, int ns, int walls, int nb, const StepArgs &a, hipStream_t st);
+int blocks2_per_cu_f32(int ns, int walls);
 int blocks_per_cu_f32(int ns, int walls, int tx);
 int blocks_per_cu_bf16(int ns, int walls, int tx);
 // Workgroups of tx threads of the plain step kernel that one compute unit holds at once.

@@ -5,6 +5,7 @@
 // pass reads BF16 like the nearest-rounding variant.
 
 #include "lb_step.hpp"
+#include "lb_step2.hpp"
 
 namespace lb355 {
 
@@ -25,5 +26,23 @@ hipError_t launch_batch_bf16(bool stochastic, int ns, int walls, int what, int t
 }
 
 int blocks_per_cu_bf16(int ns, int walls, int tx) { return blocks_per_cu_m<MODE_BF16>(ns, walls, tx); }
+
+template <int MODE, int NS, bool WALLS>
+static hipError_t launch2_t(int streaming, int nb, const StepArgs &a, hipStream_t st) {
+  const size_t lds = step2_lds_bytes(MODE, NS);
+  if (streaming) hipLaunchKernelGGL((step2_kernel<MODE, NS, WALLS, kStoreStreaming>), dim3(nb), dim3(64), lds, st, a);
+  else hipLaunchKernelGGL((step2_kernel<MODE, NS, WALLS, kStoreWriteThrough>), dim3(nb), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch2_m(int ns, int walls, int nb, const StepArgs &a, hipStream_t st) {
+  if (ns == 1) return walls ? launch2_t<MODE, 1, true>(a.stream_stores, nb, a, st) : launch2_t<MODE, 1, false>(a.stream_stores, nb, a, st);
+  return walls ? launch2_t<MODE, 2, true>(a.stream_stores, nb, a, st) : launch2_t<MODE, 2, false>(a.stream_stores, nb, a, st);
+}
+
+hipError_t launch_step2_bf16(bool stochastic, int ns, int walls, int nb, const StepArgs &a, hipStream_t st) {
+  return stochastic ? launch2_m<MODE_BF16SR>(ns, walls, nb, a, st) : launch2_m<MODE_BF16>(ns, walls, nb, a, st);
+}
 
 }  // namespace lb355
