@@ -344,6 +344,19 @@ int lb_fit_cooperative_length(const double *z, const double *f, int32_t n, doubl
                               double zeta_max, double out[4]);
 
 /*
+ * Disjoining pressure of flat films from their film tensions, eq. (doppiasigma) (section "The
+ * case of two near-interfaces: emergence of the disjoining pressure"): a flat film of thickness
+ * h has the film tension gamma_f(h) (the integral across it of the normal minus the tangential
+ * pressure, e.g. the row sum of sigma_xx - sigma_yy from lb_stress_field across a film normal to
+ * x), and differentiating eq. (doppiasigma) gives d gamma_f = h d Pi.  With Pi = 0 at the
+ * thickest film and gamma_f taken linear between the given thicknesses,
+ * Pi(h) = -int_h^h_max gamma_f'(h') / h' dh', integrated exactly on each interval.  h, gamma_f:
+ * host arrays of n >= 2 films (any order; thicknesses positive and distinct); pi: host output
+ * in the input order.  LB_EINVAL otherwise.  Pure host call.
+ */
+int lb_disjoining_pressure(const double *h, const double *gamma_f, int32_t n, double *pi);
+
+/*
  * Adjoint (reverse-time) gradient of the time-averaged wall stress and flow rate (emulsion
  * section: Poiseuille flow of a confined emulsion) over the next T >= 1 steps:
  *   L = lw[0] * (1/T) sum_t (W_bot(t) + W_top(t)) / 2  +  lw[1] * (1/T) sum_t Q(t),

@@ -87,6 +87,7 @@ SIGNATURES = {
     "lb_profile": (ctypes.c_int, [_vp, _vp]),
     "lb_stress_field": (ctypes.c_int, [_vp, _vp, _i32]),
     "lb_profile_noalloc": (ctypes.c_int, [_vp, _vp]),
+    "lb_disjoining_pressure": (ctypes.c_int, [_dp, _dp, _i32, _dp]),
     "lb_profile_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp]),
     "lb_fit_cooperative_length": (ctypes.c_int, [_dp, _dp, _i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                  _dp]),

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "../../include/lb.h"
 
@@ -92,6 +93,31 @@ int lb_fit_cooperative_length(const double *z, const double *f, int32_t n, doubl
   out[1] = fb;
   out[2] = fw;
   out[3] = std::sqrt(sse / n);
+  return LB_OK;
+}
+
+int lb_disjoining_pressure(const double *h, const double *gamma_f, int32_t n, double *pi) {
+  if (!h || !gamma_f || !pi || n < 2) return LB_EINVAL;
+  // sort the thicknesses (stable order of the input indices), distinct and finite
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(h[i]) || !std::isfinite(gamma_f[i]) || !(h[i] > 0.0)) return LB_EINVAL;
+    order[i] = i;
+  }
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return h[a] < h[b]; });
+  for (int k = 1; k < n; ++k)
+    if (!(h[order[k]] > h[order[k - 1]])) return LB_EINVAL;
+  // eq. (doppiasigma) differentiated: d gamma_f = h d Pi; Pi = 0 at the thickest film and, with
+  // gamma_f linear on each interval, the integral of gamma_f'(h) / h over it is
+  // slope * ln(h_hi / h_lo)
+  pi[order[n - 1]] = 0.0;
+  double acc = 0.0;
+  for (int k = n - 2; k >= 0; --k) {
+    const int lo = order[k], hi = order[k + 1];
+    const double slope = (gamma_f[hi] - gamma_f[lo]) / (h[hi] - h[lo]);
+    acc -= slope * std::log(h[hi] / h[lo]);
+    pi[lo] = acc;
+  }
   return LB_OK;
 }
 

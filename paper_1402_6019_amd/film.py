@@ -9,8 +9,9 @@ pressure tensor across it, and differentiating (doppiasigma) gives d gamma_f = h
 Pi(h) = -int_h^inf gamma_f'(h') / h' dh' with Pi(inf) = 0 and gamma_f(inf) = 2 gamma.
 
 Every field comes from the GPU (lb_moments for the density along the axis through the film,
-lb_stress_field for the pressure tensor); the host only reads a few values, sums one row and
-interpolates the two crossings that bound the film.
+lb_stress_field for the pressure tensor), and the integration of eq. (doppiasigma) runs in the
+library (lb_disjoining_pressure); the host reads a few values of the fields, sums one row of the
+tensor (a few hundred numbers) and interpolates the two crossings that bound the film.
 """
 
 import numpy as np
@@ -101,20 +102,17 @@ def disjoining_from_tension(h, gamma_f):
     """Pi at the thicknesses h (any order, distinct) from the film tensions gamma_f(h) of flat
     films, by eq. (doppiasigma): dPi = dgamma_f / h, integrated from the thickest film, where
     Pi is taken as 0; gamma_f is taken linear between neighbouring thicknesses and 1/h is
-    integrated exactly on each interval.  Returns Pi in the order of the input."""
-    h = np.asarray(h, dtype=np.float64)
-    g = np.asarray(gamma_f, dtype=np.float64)
+    integrated exactly on each interval (lb_disjoining_pressure in the library).  Returns Pi in
+    the order of the input."""
+    import ctypes
+    from . import _binding as B
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(gamma_f, dtype=np.float64)
     if h.shape != g.shape or h.ndim != 1 or len(h) < 2:
         raise ValueError("h and gamma_f must be 1-D of the same length >= 2")
-    order = np.argsort(h)
-    hs, gs = h[order], g[order]
-    if np.any(np.diff(hs) <= 0):
-        raise ValueError("thicknesses must be distinct")
-    pi = np.zeros_like(hs)
-    for i in range(len(hs) - 2, -1, -1):
-        # int_{h_i}^{h_i+1} gamma_f'(h)/h dh over a linear piece of gamma_f: slope * ln(h_i+1/h_i)
-        slope = (gs[i + 1] - gs[i]) / (hs[i + 1] - hs[i])
-        pi[i] = pi[i + 1] - slope * np.log(hs[i + 1] / hs[i])
-    out = np.empty_like(pi)
-    out[order] = pi
+    out = np.empty_like(h)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = B.load().lb_disjoining_pressure(h.ctypes.data_as(dp), g.ctypes.data_as(dp), len(h), out.ctypes.data_as(dp))
+    if rc != B.LB_OK:
+        raise ValueError("thicknesses must be positive, finite and distinct")
     return out
