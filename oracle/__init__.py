@@ -21,6 +21,12 @@ _SRC = os.path.join(_HERE, "lb_oracle.cpp")
 _LIB = os.path.join(_HERE, "liblb_oracle.so")
 _SRC3 = os.path.join(_HERE, "lb_oracle3d.cpp")
 _LIB3 = os.path.join(_HERE, "liblb_oracle3d.so")
+# LB_ORACLE_LIB_DIR: load prebuilt oracle libraries from that directory instead (the sanitizer
+# run builds instrumented copies there)
+_ALT = os.environ.get("LB_ORACLE_LIB_DIR")
+if _ALT:
+    _LIB = os.path.join(_ALT, "liblb_oracle.so")
+    _LIB3 = os.path.join(_ALT, "liblb_oracle3d.so")
 # Plain FP64: no contraction of a*b+c into fma, no fast-math reassociation.
 _CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
 
@@ -42,7 +48,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not _ALT and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
@@ -233,7 +239,7 @@ def _load3():
     global _lib3
     if _lib3 is not None:
         return _lib3
-    if not os.path.exists(_LIB3) or os.path.getmtime(_LIB3) < os.path.getmtime(_SRC3):
+    if not _ALT and (not os.path.exists(_LIB3) or os.path.getmtime(_LIB3) < os.path.getmtime(_SRC3)):
         build(force=True)
     lib = ctypes.CDLL(_LIB3)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int

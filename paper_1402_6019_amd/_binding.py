@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblb355.so")
+# LB355_LIB: path of another build of the library (e.g. one with instrumented host code)
+LIB_PATH = os.environ.get("LB355_LIB") or os.path.join(HERE, "liblb355.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_F64, LB_F32, LB_BF16DEV = 0, 1, 2
