@@ -42,7 +42,7 @@ struct lb_ctx {
   int device = 0;  // device current at lb_init
   int reduce_every = 0;
   int store_policy = LB_STORES_AUTO;
-  int two_step = 0;  // plain steps in pairs, two time steps per launch (FP32 / BF16)
+  int two_step = LB_TWO_STEP_AUTO;  // plain steps in pairs, two time steps per launch
   int sy2 = 0;       // rows per segment of the two-step kernel (0: the resident-grid default)
   int rounding = LB_ROUND_NEAREST;  // BF16 stores: nearest or stochastic
   double *d_tbase = nullptr;        // step at which a graph replay starts (stochastic rounding)
@@ -138,13 +138,25 @@ int grid2(const lb_ctx *c, int *sy_out, int *nseg_out) {
   return nstrip * nseg;
 }
 
+// Whether plain steps go in pairs: forced on or off, or (auto) for FP32 storage whose two
+// population buffers exceed the Infinity Cache, where the pairs' halved HBM traffic outweighs
+// their recomputed overlaps (measured: faster on the 4096 x 512 and 4096 x 1024 channels, slower
+// on the cache-resident 1024^2 lattice and in BF16).
+bool pairs_on(const lb_ctx *c) {
+  if (c->two_step == LB_TWO_STEP_AUTO)
+    return c->lat.storage == LB_F32 && streaming_stores(lb_pop_bytes(&c->lat));
+  return c->two_step == LB_TWO_STEP_ON;
+}
+
 // Two plain steps in one launch (time steps t_step and t_step + 1) from buffer `from` to the
-// other one.
+// other one.  Stores write through unless streaming is forced: with the traffic halved, the
+// write-through variant measured faster at every footprint.
 hipError_t launch_two_steps(const lb_ctx *c, int from, hipStream_t st, uint32_t t_step, const double *t_base) {
   int sy = 0, nseg = 0;
   const int nb = grid2(c, &sy, &nseg);
   StepArgs a;
   fill_step_args(c, a);
+  a.stream_stores = c->store_policy == LB_STORES_STREAMING ? 1 : 0;
   a.sy = sy;
   a.nseg = nseg;
   a.src = c->pop[from];
@@ -395,7 +407,7 @@ int lb_step(lb_ctx *c, int64_t n) {
       hipGraphExec_t g = nullptr;
       const int from = c->cur;
       const double *tb = c->rounding == LB_ROUND_STOCHASTIC ? c->d_tbase : nullptr;
-      const bool pairs = c->two_step != 0;
+      const bool pairs = pairs_on(c);
       hipError_t e = c->graph.get(
           from,
           [&](int k, hipStream_t st) {
@@ -413,7 +425,7 @@ int lb_step(lb_ctx *c, int64_t n) {
       n -= c->graph.steps;
     }
   }
-  if (c->two_step && c->reduce_every == 0) {
+  if (pairs_on(c) && c->reduce_every == 0) {
     for (; n >= 2; n -= 2) {
       hipError_t e = launch_two_steps(c, c->cur, c->stream, (uint32_t)c->t, nullptr);
       if (e != hipSuccess) return hip_fail(c, e, "two-step kernel launch");
@@ -567,8 +579,10 @@ int64_t lb_time(const lb_ctx *c) { return c ? c->t : -1; }
 
 int lb_set_two_step(lb_ctx *c, int32_t enable, int32_t rows) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
-  if (enable != 0 && enable != 1) return fail(c, LB_EINVAL, "enable must be 0 or 1");
-  if (enable && c->lat.storage == LB_F64) return fail(c, LB_EINVAL, "two steps per launch: FP32 and BF16 storage only");
+  if (enable != LB_TWO_STEP_OFF && enable != LB_TWO_STEP_ON && enable != LB_TWO_STEP_AUTO)
+    return fail(c, LB_EINVAL, "enable must be LB_TWO_STEP_OFF, LB_TWO_STEP_ON or LB_TWO_STEP_AUTO");
+  if (enable == LB_TWO_STEP_ON && c->lat.storage == LB_F64)
+    return fail(c, LB_EINVAL, "two steps per launch: FP32 and BF16 storage only");
   if (rows < 0) return fail(c, LB_EINVAL, "rows must be >= 0");
   c->two_step = enable;
   c->sy2 = rows;

@@ -34,27 +34,43 @@ namespace lb355 {
 constexpr int kStrip2 = 54;  // output columns per wave
 constexpr int kPad2 = 5;     // lanes left of the first output column
 
-// LDS bytes of one two-step workgroup: the L1 and L2 rings (five rows of psi and rho of 68
-// entries each) and the L2 input ring (three rows of 9 planes of 66 entries).
+// LDS of one two-step workgroup, sized so that eight fit in the 160 KB of a compute unit (two
+// waves per SIMD).  Rings of psi (five rows) and rho (four rows) for both steps: rows of 64
+// entries laid end to end with two spare entries at each end, so a lane's neighbours two
+// columns away fall on the adjacent row's edge lanes (only lanes whose results are discarded
+// read them).  The input ring of the second step keeps each row of f*(t) only as long as its
+// planes are pulled: planes 0, 1, 3 (pulled in place) and 4, 7, 8 (pulled from the row above)
+// for two rows, planes 2, 5, 6 (pulled from the row below) for three; a plane row has 64
+// entries and the pull's neighbouring lane wraps round (again only for discarded lanes).
+constexpr int kRing2Psi = 5 * 64 + 4, kRing2Rho = 4 * 64 + 4, kIn2Rows = 21;
 inline size_t step2_lds_bytes(int mode, int ns) {
   const size_t r = mode == MODE_F64 ? 8 : 4;
-  return (2 * 2 * 5 * 68 + 3 * 9 * 66) * (size_t)ns * r;
+  return (2 * kRing2Psi + 2 * kRing2Rho + kIn2Rows * 64) * (size_t)ns * r;
+}
+
+// Plane row of the input ring holding plane l of f*(t) at row r (see step2_lds_bytes).
+__device__ inline int in2_row(int l, int r) {
+  // group of the plane: 0 {0, 1, 3} two slots, 1 {2, 5, 6} three slots, 2 {4, 7, 8} two slots
+  const int g = (l == 0 || l == 1 || l == 3) ? 0 : ((l == 2 || l == 5 || l == 6) ? 1 : 2);
+  const int pos = (l == 0 || l == 2 || l == 4) ? 0 : ((l == 1 || l == 5 || l == 7) ? 1 : 2);
+  const int base = g == 0 ? 0 : (g == 1 ? 6 : 15);
+  const int ns = g == 1 ? 3 : 2;
+  const int slot = ((r % ns) + ns) % ns;
+  return base + slot * 3 + pos;
 }
 
 template <int MODE, int NS, bool WALLS, int STP>
-__global__ __launch_bounds__(64) void step2_kernel(StepArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void step2_kernel(StepArgs a) {
   using C = Codec<MODE>;
   using R = typename C::R;
   using S = typename C::S;
   using L = typename C::L;
   using V = Vec<R, NS>;
-  constexpr int RW = 68;  // ring row: lanes 0..63 at entries 2..65
-  constexpr int IW = 66;  // input-ring plane row: lanes at entries 1..64
-  V *ring1 = reinterpret_cast<V *>(lb_smem);  // [5][RW] psi(t)
-  V *rho1 = ring1 + 5 * RW;                   // [5][RW] rho(t)
-  V *ring2 = rho1 + 5 * RW;                   // [5][RW] psi(t+1)
-  V *rho2 = ring2 + 5 * RW;                   // [5][RW] rho(t+1)
-  V *inr = rho2 + 5 * RW;                     // [3][9][IW] f*(t)
+  V *ring1 = reinterpret_cast<V *>(lb_smem);  // psi(t): row slot k, lane j at entry 64 k + 2 + j
+  V *rho1 = ring1 + kRing2Psi;                // rho(t), four row slots
+  V *ring2 = rho1 + kRing2Rho;                // psi(t+1)
+  V *rho2 = ring2 + kRing2Psi;                // rho(t+1)
+  V *inr = rho2 + kRing2Rho;                  // f*(t): [21 plane rows][64]
 
   const int lx = a.lx, ly = a.ly;
   const uint32_t site_b = (uint32_t)(NS * sizeof(S));
@@ -102,7 +118,8 @@ __global__ __launch_bounds__(64) void step2_kernel(StepArgs a) {
   const R psi0 = R(a.psi0), nirho0 = R(-a.irho0);
 
   auto slot5 = [](int r) { return (int)uni((uint32_t)(((r % 5) + 5) % 5)); };
-  auto slot3 = [](int r) { return (int)uni((uint32_t)(((r % 3) + 3) % 3)); };
+  auto slot4 = [](int r) { return (int)uni((uint32_t)(((r % 4) + 4) % 4)); };
+  auto inrow = [&](int l, int r) { return inr + (int)uni((uint32_t)in2_row(l, r)) * 64; };
 
   // psi and rho of a site from its pulled (decoded) populations, as the single-step ring does
   auto site_ring = [&](V *ps_row, V *rh_row, int r, const R (&f)[NS][9]) {
@@ -267,8 +284,7 @@ __global__ __launch_bounds__(64) void step2_kernel(StepArgs a) {
       for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int l = 0; l < 9; ++l) f[s][l] = C::dec(FR[s][l], s);
-      const int sl = slot5(r);
-      site_ring(ring1 + sl * RW, rho1 + sl * RW, r, f);
+      site_ring(ring1 + slot5(r) * 64, rho1 + slot4(r) * 64, r, f);
     }
 
     // (b) L1 update of row r - 2 -> the input ring
@@ -282,21 +298,21 @@ __global__ __launch_bounds__(64) void step2_kernel(StepArgs a) {
       V *prow[5];
       V *xrow[3];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) prow[k] = ring1 + slot5(u1 - 2 + k) * RW;
+      for (int k = 0; k < 5; ++k) prow[k] = ring1 + slot5(u1 - 2 + k) * 64;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) xrow[k] = (a.cross_psi ? ring1 : rho1) + slot5(u1 - 1 + k) * RW;
+      for (int k = 0; k < 3; ++k)
+        xrow[k] = a.cross_psi ? ring1 + slot5(u1 - 1 + k) * 64 : rho1 + slot4(u1 - 1 + k) * 64;
       R fsa[NS][9];
       update(u1, f, prow, xrow, fsa);
       const int yw = WALLS ? u1 : wrapi(u1, ly);
       uint32_t hs = 0;
       if constexpr (MODE == MODE_BF16SR) hs = mix32((uint32_t)(yw * lx + xc) ^ tseed1);
-      V *dst = inr + slot3(u1) * 9 * IW + lane + 1;
 #pragma unroll
       for (int l = 0; l < 9; ++l) {
         V v;
 #pragma unroll
         for (int s = 0; s < NS; ++s) v.v[s] = stored(fsa[s][l], s, l, hs);
-        dst[l * IW] = v;
+        inrow(l, u1)[lane] = v;
       }
     }
 
@@ -305,26 +321,25 @@ __global__ __launch_bounds__(64) void step2_kernel(StepArgs a) {
     if (p2 >= yA - 2) {
       if (row_fluid<WALLS>(p2, ly)) {
         const bool lo = WALLS && p2 == 0, hi = WALLS && p2 == ly - 1;
-        const V *rm = inr + slot3(p2 - 1) * 9 * IW + lane + 1;  // row below
-        const V *r0 = inr + slot3(p2) * 9 * IW + lane + 1;
-        const V *rp = inr + slot3(p2 + 1) * 9 * IW + lane + 1;  // row above
+        const int lm = (lane - 1) & 63, lp = (lane + 1) & 63;  // pull from x - 1 / x + 1
         V g[9];
-        g[0] = r0[0 * IW];
-        g[1] = r0[1 * IW - 1];
-        g[3] = r0[3 * IW + 1];
-        g[2] = lo ? r0[4 * IW] : rm[2 * IW];
-        g[5] = lo ? r0[7 * IW] : rm[5 * IW - 1];
-        g[6] = lo ? r0[8 * IW] : rm[6 * IW + 1];
-        g[4] = hi ? r0[2 * IW] : rp[4 * IW];
-        g[7] = hi ? r0[5 * IW] : rp[7 * IW + 1];
-        g[8] = hi ? r0[6 * IW] : rp[8 * IW - 1];
+        g[0] = inrow(0, p2)[lane];
+        g[1] = inrow(1, p2)[lm];
+        g[3] = inrow(3, p2)[lp];
+        // c_y = +1 from the row below, or reflected off the wall below (planes 4, 7, 8 in place)
+        g[2] = lo ? inrow(4, p2)[lane] : inrow(2, p2 - 1)[lane];
+        g[5] = lo ? inrow(7, p2)[lane] : inrow(5, p2 - 1)[lm];
+        g[6] = lo ? inrow(8, p2)[lane] : inrow(6, p2 - 1)[lp];
+        // c_y = -1 from the row above, or reflected off the wall above (planes 2, 5, 6 in place)
+        g[4] = hi ? inrow(2, p2)[lane] : inrow(4, p2 + 1)[lane];
+        g[7] = hi ? inrow(5, p2)[lane] : inrow(7, p2 + 1)[lp];
+        g[8] = hi ? inrow(6, p2)[lane] : inrow(8, p2 + 1)[lm];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
           for (int l = 0; l < 9; ++l) P2[s][l] = g[l].v[s];
       }
-      const int sl = slot5(p2);
-      site_ring(ring2 + sl * RW, rho2 + sl * RW, p2, P2);
+      site_ring(ring2 + slot5(p2) * 64, rho2 + slot4(p2) * 64, p2, P2);
     }
 
     // (d) L2 update of row r - 5 and the store of f*(t+1)
@@ -333,9 +348,10 @@ __global__ __launch_bounds__(64) void step2_kernel(StepArgs a) {
       V *prow[5];
       V *xrow[3];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) prow[k] = ring2 + slot5(u2 - 2 + k) * RW;
+      for (int k = 0; k < 5; ++k) prow[k] = ring2 + slot5(u2 - 2 + k) * 64;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) xrow[k] = (a.cross_psi ? ring2 : rho2) + slot5(u2 - 1 + k) * RW;
+      for (int k = 0; k < 3; ++k)
+        xrow[k] = a.cross_psi ? ring2 + slot5(u2 - 1 + k) * 64 : rho2 + slot4(u2 - 1 + k) * 64;
       R fsa[NS][9];
       update(u2, P2old, prow, xrow, fsa);
       if (out_lane) {

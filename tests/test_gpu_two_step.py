@@ -17,8 +17,7 @@ def run(c, steps, two_step=None, rows=0, graph=0, rounding=None, tile=None):
     sim = make_sim(c, tile=tile)
     if rounding:
         sim.set_rounding(rounding)
-    if two_step:
-        sim.set_two_step(True, rows)
+    sim.set_two_step(bool(two_step), rows)
     if graph:
         sim.set_graph(graph)
     sim.step(steps)
@@ -72,8 +71,7 @@ def test_two_step_bitwise_full_size_emulsion():
         out = []
         for two in (False, True):
             sim = Sim(1024, 1024, rho, storage=storage, **kw)
-            if two:
-                sim.set_two_step(True)
+            sim.set_two_step(two)
             sim.step(10)
             out.append(sim.checkpoint().cpu().numpy())
             sim.close()
@@ -87,3 +85,24 @@ def test_two_step_rejects_fp64():
     with pytest.raises(LbError):
         sim.set_two_step(True)
     sim.close()
+
+
+def test_two_step_auto_picks_pairs_beyond_the_cache():
+    """The default (auto) pairs the steps of an FP32 lattice whose buffers exceed the Infinity
+    Cache and leaves smaller ones alone; either way the populations equal those of forced single
+    steps."""
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    lx, ly = 4096, 512  # 2 x 151 MB in FP32
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.85, seed=3, walls=True)
+    kw = dict(n_species=2, walls=True, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+              body=(1e-6, 0.0), rho_wall=lbgen.EMULSION_POOR, rho0=lbgen.EMULSION_RHO0,
+              rho_ref=(float(rho[0].mean()), float(rho[1].mean())))
+    out = {}
+    for mode in ("auto", False):
+        sim = Sim(lx, ly, rho, storage="f32", **kw)
+        sim.set_two_step(mode)
+        sim.step(6)
+        out[mode] = sim.checkpoint().cpu().numpy()
+        sim.close()
+    assert np.array_equal(out["auto"], out[False])
