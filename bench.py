@@ -860,6 +860,8 @@ def main():
                     help="headline lattice and copy only (skip the channel, batched and adjoint legs)")
     ap.add_argument("--channel-only", action="store_true",
                     help="run only the 4096 x 512 channel leg (served by HBM) and print it")
+    ap.add_argument("--three-d-only", action="store_true",
+                    help="run only the 3-D leg (256^3 emulsion, FP32 and FP64) and print it")
     ap.add_argument("--couette-study", action="store_true",
                     help="run only the Couette-cell fluidity study (half a million steps at 1040^2) and print it")
     args = ap.parse_args()
@@ -874,6 +876,9 @@ def main():
         return
     if args.channel_only:
         print(json.dumps(channel_beyond_cache(args.steps)), flush=True)
+        return
+    if args.three_d_only:
+        print(json.dumps(three_d(max(5, args.steps // 40))), flush=True)
         return
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
 
