@@ -442,6 +442,11 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   const bool col_ok = tid < w;
   const int xc = x0 + (col_ok ? tid : 0);
   const uint32_t buf_b = 9u * (uint32_t)a.plane * site_b;
+  // A wave whose every lane lies past a ragged strip's last column loads and stores through
+  // a zero-length range (loads return zeros, stores are dropped): it moves no bytes, yet
+  // takes every barrier of the tile like the others.  Wave 0 always holds column x0.
+  const bool wave_idle = (int)uni((uint32_t)(tid & ~63)) >= w;
+  const uint32_t ld_b = wave_idle ? 0u : buf_b;
   const LaneCols pcc = {(uint32_t)xc * site_b, (uint32_t)wrapi(xc - 1, lx) * site_b,
                         (uint32_t)wrapi(xc + 1, lx) * site_b};
   // Store column: lanes past a ragged strip's end write into the row padding (the row
@@ -554,8 +559,8 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     L HP[5][2];
     auto load_row = [&](int r, L (&dstb)[NS][9], L (&hv)[2]) {
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r, ly), ly, row_b);
-      load_pull<C, NS>(src, buf_b, plane_b, pcc, pr, dstb);
-      halo_load(pr, hv, buf_b);
+      load_pull<C, NS>(src, ld_b, plane_b, pcc, pr, dstb);
+      halo_load(pr, hv, ld_b);
     };
     load_row(y0 - 2 * dir, B[D - 1], HP[0]);
     load_row(y0 - dir, B[D - 2], HP[1]);
@@ -605,13 +610,13 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       // and no longer waits for the previous row's stores before the ring row, which pays
       // once HBM serves the traffic; with cache-resident buffers the extra issue costs more.
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(past ? ylast : rl, ly), ly, row_b);
-      const uint32_t nb = past ? 0u : buf_b;
+      const uint32_t nb = past ? 0u : ld_b;
       load_pull<C, NS>(src, nb, plane_b, pcc, pr, FL);
       halo_load(pr, hv, nb);
     } else if (!past) {  // uniform branch
       const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(rl, ly), ly, row_b);
-      load_pull<C, NS>(src, buf_b, plane_b, pcc, pr, FL);
-      halo_load(pr, hv, buf_b);
+      load_pull<C, NS>(src, ld_b, plane_b, pcc, pr, FL);
+      halo_load(pr, hv, ld_b);
     }
 
     __syncthreads();
@@ -920,7 +925,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       }
     }
     if (STORE) {
-      const Rsrc rd = make_rsrc(dst, buf_b);
+      const Rsrc rd = make_rsrc(dst, ld_b);
       if constexpr (MODE == MODE_BF16SR) {
         // random bits from (site, plane, step): the same for every launch shape
         const uint32_t hs = mix32((uint32_t)(y * lx + (x0 + tid)) ^ tseed);
