@@ -29,7 +29,9 @@ BYTES_PER_VALUE = {"f64": 8, "f32": 4, "bf16dev": 2}
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lb_step.hpp", "lb_step_f64.hip", "lb_step_f32.hip", "lb_step_bf16.hip", "lb_kernels.hip",
+    # the step kernels' own source (lb_kernels.hip holds only their dispatch and the layout
+    # and reduction kernels)
+    for f in ("lb_step.hpp", "lb_step2.hpp", "lb_step_f64.hip", "lb_step_f32.hip", "lb_step_bf16.hip",
               "lb_internal.hpp", "lb_tables.hpp"):
         with open(os.path.join(ROOT, "paper_1402_6019_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -117,12 +119,18 @@ def channel_beyond_cache(steps):
     out = {"workload": f"confined emulsion channel {lx}x{ly}, walls + wetting, g = 1e-6, volume fraction 0.85, seed 3"}
     out["profiles_f32"] = channel_profiles(rho, kw, lx, ly)
     out["copy_ceiling_f32_footprint"] = stream_copy(9 * 2 * 4 * lx * ly, 100)  # one FP32 population buffer
+    # the kernel each mode runs at this footprint by default: FP32 two steps per launch, FP64
+    # single steps with streaming stores (both beyond the Infinity Cache), BF16 (2 x 75.5 MB,
+    # inside it) single steps with write-through stores
+    kernels = {"f32": "step2_kernel<F32, 2 species, channel>: two steps per launch, streaming stores",
+               "bf16dev": "step_kernel<BF16 deviations, 2 species, channel>, write-through stores",
+               "f64": "step_kernel<F64, 2 species, channel>, streaming stores"}
     for storage in ("f32", "bf16dev", "f64"):
         ms, wall, tile = time_storage(storage, rho, kw, steps, max(10, steps // 10), shape=(lx, ly))
         bpl = 2 * 9 * 2 * BYTES_PER_VALUE[storage]
         gbs = bpl * lx * ly / (ms * 1e-3) / 1e9
         out[storage] = {"ms_per_step": ms, "mlups": lx * ly / (ms * 1e-3) / 1e6, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
-                        "footprint_mb": 2 * bpl / 2 * lx * ly / 1e6, "tile": list(tile)}
+                        "footprint_mb": 2 * bpl / 2 * lx * ly / 1e6, "tile": list(tile), "kernel": kernels[storage]}
     return out
 
 
@@ -832,6 +840,15 @@ def cpu_model():
     return f"{name} ({os.cpu_count()} logical CPUs)"
 
 
+def leg(name, fn, *args, **kwargs):
+    """Run one benchmark leg, with a progress line on stderr before and after it."""
+    print(f"[bench] {name} ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    r = fn(*args, **kwargs)
+    print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return r
+
+
 def traffic_from_profile(kernel_hash, storage, tile):
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
     for a copy of known size) from the committed rocprofv3 counter summary, if it was taken
@@ -910,13 +927,13 @@ def main():
             "note": "footprint 2 x 75.5 MB fits in the 256 MB Infinity Cache, so this rate is served by that "
                     "cache, not by HBM; hbm_served gives the same kernel on the 4096 x 512 channel, whose "
                     "302 MB footprint exceeds it"}
-    beyond = None if args.core else channel_beyond_cache(max(50, args.steps // 4))
+    beyond = None if args.core else leg("beyond_infinity_cache", channel_beyond_cache, max(50, args.steps // 4))
     if beyond is not None:
         ch = beyond["f32"]
         roof["hbm_served"] = {"workload": beyond["workload"], "achieved": ch["gbs"], "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": ch["frac"], "mlups": ch["mlups"],
                               "footprint_mb": ch["footprint_mb"],
-                              "kernel": "step_kernel<F32, 2 species, channel>, streaming stores"}
+                              "kernel": ch["kernel"]}
 
     out = {
         # value: FP32 MLUPS; % of HBM peak in roofline.frac; FP64 (and BF16) beside it; the
@@ -951,19 +968,19 @@ def main():
         "tiles": {k: v["tile"] for k, v in res.items()},
         "copy_reference": copy,
         "beyond_infinity_cache": beyond,
-        "long_run_1024_20k": None if args.core else long_run_1024(),
-        "config1_single_component_64": None if args.core or args.no_cpu else single_component_64(),
-        "three_d": None if args.core else three_d(max(20, args.steps // 40)),
-        "channel_50k_averages": None if args.core else channel_long_run(),
-        "batched_sweep": None if args.core else batched_sweep(max(100, args.steps // 10)),
-        "couette_cell": None if args.core else couette_cell(max(200, args.steps // 2)),
-        "auxiliary_passes": None if args.core else auxiliary_passes(rho, kw),
-        "film_sweep": None if args.core else film_sweep(),
-        "adjoint": None if args.core else adjoint_channel(check_fd=not args.no_cpu),
+        "long_run_1024_20k": None if args.core else leg("long_run_1024_20k", long_run_1024),
+        "config1_single_component_64": None if args.core or args.no_cpu else leg("config1", single_component_64),
+        "three_d": None if args.core else leg("three_d", three_d, max(20, args.steps // 40)),
+        "channel_50k_averages": None if args.core else leg("channel_50k", channel_long_run),
+        "batched_sweep": None if args.core else leg("batched_sweep", batched_sweep, max(100, args.steps // 10)),
+        "couette_cell": None if args.core else leg("couette_cell", couette_cell, max(200, args.steps // 2)),
+        "auxiliary_passes": None if args.core else leg("auxiliary_passes", auxiliary_passes, rho, kw),
+        "film_sweep": None if args.core else leg("film_sweep", film_sweep),
+        "adjoint": None if args.core else leg("adjoint", adjoint_channel, check_fd=not args.no_cpu),
         "kernel_source_hash": khash,
     }
     if not args.no_cpu:
-        base, refs, chan_ref = cpu_baseline(rho, kw)
+        base, refs, chan_ref = leg("cpu_baseline", cpu_baseline, rho, kw)
         out["cpu_baseline"] = base
         out["error_vs_oracle"] = {"emulsion_1024_by_step": emulsion_errors(rho, kw, refs),
                                   "channel_256x128": channel_errors(chan_ref)}
