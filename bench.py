@@ -612,6 +612,13 @@ def adjoint_channel(T=4000, prerelax=2000, check_fd=True):
     sim.restore(f0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    loss_all, g7_all = sim.adjoint(T, lw, every=1, fp64_reverse=True)
+    t_adj_all = time.perf_counter() - t0
+    ws_ckpt = sim._lib.lb_adjoint_workspace_bytes(sim._h, T, 0, 1)
+    ws_all = sim._lib.lb_adjoint_workspace_bytes(sim._h, T, 1, 1)
+    sim.restore(f0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     loss32, g7_32 = sim.adjoint(T, lw, fp64_reverse=False)
     t_adj32 = time.perf_counter() - t0
     sim.restore(f0)
@@ -630,7 +637,12 @@ def adjoint_channel(T=4000, prerelax=2000, check_fd=True):
                       "FP64 (grad) and in FP32 (grad_fp32_reverse)",
            "loss": loss, "grad": dict(zip(keys, grad)), "grad_fp32_reverse": dict(zip(keys, grad32)),
            "seconds_adjoint": t_adj, "seconds_adjoint_fp32_reverse": t_adj32, "seconds_forward_only": t_fwd,
-           "adjoint_over_forward": t_adj / t_fwd}
+           "adjoint_over_forward": t_adj / t_fwd, "workspace_gb": ws_ckpt / 1e9,
+           "every_state_kept": {"note": "every = 1: the forward pass keeps what the reverse step reads of every "
+                                        "state, nothing is recomputed; same FP64 reverse sweep",
+                                "seconds_adjoint": t_adj_all, "adjoint_over_forward": t_adj_all / t_fwd,
+                                "workspace_gb": ws_all / 1e9,
+                                "grad_bitwise_equal_to_checkpointed": bool(loss_all == loss and (g7_all == g7).all())}}
     if check_fd:
         def fwd_loss(**kw):
             p = dict(base, **kw)

@@ -369,7 +369,10 @@ int lb_disjoining_pressure(const double *h, const double *gamma_f, int32_t n, do
  * The forward pass keeps an FP64 checkpoint of the populations every `every` steps
  * (every <= 0: ceil(sqrt(T))); the reverse sweep recomputes each segment's states from its
  * checkpoint and runs the hand-written reverse step (FP64 for LB_F64 contexts or with
- * flags & LB_ADJ_FP64, FP32 otherwise).  workspace: device buffer of
+ * flags & LB_ADJ_FP64, FP32 otherwise).  every = 1 keeps instead what the reverse step reads
+ * of every state (moments and pseudopotential of every site, populations of the two rows
+ * next to the walls): no recompute, at about T * 64 (FP64 reverse) or T * 32 (FP32) bytes per
+ * site of workspace.  workspace: device buffer of
  * lb_adjoint_workspace_bytes(ctx, T, every, flags) bytes,
  * owned by the caller.  On return the context holds the state after T steps, bit for bit as
  * lb_step(ctx, T) would leave it, and lb_time has advanced by T; the running wall-stress

@@ -180,8 +180,10 @@ class Sim:
     def adjoint(self, T, loss_weights=(1.0, 0.0), every=0, fp64_reverse=False):
         """Loss L = lw0 <(W_bot + W_top)/2> + lw1 <Q> over the next T steps and its gradient
         dL/d(G_AA,1, G_BB,1, G_AA,2, G_BB,2, G_AB, g_x, g_y) by the hand-written adjoint with
-        checkpoints every `every` steps (0: sqrt(T)); fp64_reverse runs the reverse sweep in
-        FP64 for FP32 / BF16 storage.  Advances the state by T steps."""
+        checkpoints every `every` steps (0: sqrt(T); 1: no checkpoints, the forward pass keeps
+        what the reverse step reads of every state, about T x 64 B per site with an FP64
+        reverse sweep, and nothing is recomputed); fp64_reverse runs the reverse sweep in FP64
+        for FP32 / BF16 storage.  Advances the state by T steps."""
         torch = self.torch
         flags = B.LB_ADJ_FP64 if fp64_reverse else 0
         nbytes = self._lib.lb_adjoint_workspace_bytes(self._h, int(T), int(every), flags)

@@ -76,57 +76,90 @@ __device__ inline T block_sum(T v, T *sm) {
 
 }  // namespace
 
-// Moments and pseudopotential of the forward state x(t).
-template <typename R, int NS>
-__global__ __launch_bounds__(256) void adj_fields_kernel(AdjArgs a) {
-  AdjView<R> v(a);
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= v.lx) return;
-  const size_t i = (size_t)y * v.lx + x;
-  for (int s = 0; s < NS; ++s) {
-    R r = 0, jx = 0, jy = 0;
+// The two reverse kernels work on 64 x 4 tiles of sites (one wave per tile row, 256 threads).
+// Everything a site reads from its two-belt neighbourhood (psi and rho of the forward state
+// for the force, psi_s Fbar_s and r_s Fbar_s for the gather) is first staged for the tile plus
+// a halo of two sites into LDS, so each neighbour value is fetched from memory once per tile
+// instead of once per reader.
+constexpr int ATX = 64, ATY = 4, AHX = ATX + 4, AHY = ATY + 4;
+
+// Site index of lattice point (x, y) for staging, any distance outside the lattice (x always
+// periodic; y periodic unless walls, where rows outside are not sites).
+template <bool WALLS>
+__device__ inline bool stage_site(int x, int y, int lx, int ly, size_t &i) {
+  if (WALLS && (y < 0 || y >= ly)) return false;
+  const int xi = ((x % lx) + lx) % lx;
+  const int yi = WALLS ? y : ((y % ly) + ly) % ly;
+  i = (size_t)yi * lx + xi;
+  return true;
+}
+
+// Per-tile sums of the nine sensitivities and loss terms: a wave reduction each, then the
+// four waves in order (one barrier), added to this tile's own row of running sums.
+__device__ inline void tile_accumulate(const double (&vals)[ADJ_N], double (*sm)[ADJ_N], double *row) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
-      const R f = R(a.x[((size_t)s * Q + l) * v.n + i]);
-      r += f;
-      jx += R(CXS[l]) * f;
-      jy += R(CYS[l]) * f;
-    }
-    v.fldw(0, s, i) = r;
-    v.fldw(1, s, i) = R(a.psi0) * (R(1) - exp(-r * R(a.irho0)));
-    v.fldw(2, s, i) = jx;
-    v.fldw(3, s, i) = jy;
+  for (int k = 0; k < ADJ_N; ++k) {
+    double v = vals[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sm[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < ADJ_N) {
+    const int k = threadIdx.x;
+    row[k] += ((sm[0][k] + sm[1][k]) + sm[2][k]) + sm[3][k];
   }
 }
 
 // Local part of the reverse step: force recompute, transposed streaming, the collision's
-// and velocity shift's adjoints; writes lampart, Fbar and per-block partial sums.
+// and velocity shift's adjoints; writes lam (the local part of lambda(t)), Fbar and per-tile
+// partial sums.
 template <typename R, int NS, bool WALLS>
 __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
   AdjView<R> v(a);
-  __shared__ double sm[4];
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  const bool live = x < v.lx;
-  const int xs = live ? x : 0;
+  __shared__ R sps[2][AHY][AHX];  // psi of the forward state, tile + halo
+  __shared__ R srh[2][AHY][AHX];  // rho
+  __shared__ R scn[2][ATY + 2][ATX + 2];  // corr of lambda(t+1), tile + halo of one
+  __shared__ double sm[4][ADJ_N];
+  const R *corr_next = static_cast<const R *>(a.corr_next);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * ATX, y0 = blockIdx.y * ATY;
+  for (int k = threadIdx.x; k < AHX * AHY; k += 256) {
+    const int hx = k % AHX, hy = k / AHX;
+    size_t j = 0;
+    const bool in = stage_site<WALLS>(x0 - 2 + hx, y0 - 2 + hy, v.lx, v.ly, j);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      sps[s][hy][hx] = in ? v.fld(1, s, j) : R(a.psi_w[s]);
+      srh[s][hy][hx] = in ? v.fld(0, s, j) : R(a.rho_w[s]);
+    }
+  }
+  for (int k = threadIdx.x; k < (ATX + 2) * (ATY + 2); k += 256) {
+    const int hx = k % (ATX + 2), hy = k / (ATX + 2);
+    size_t j = 0;
+    const bool in = stage_site<WALLS>(x0 - 1 + hx, y0 - 1 + hy, v.lx, v.ly, j);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) scn[s][hy][hx] = in ? corr_next[(size_t)s * v.n + j] : R(0);
+  }
+  __syncthreads();
+
+  const bool live = x0 + tx < v.lx && y0 + ty < v.ly;
+  // memory accesses of lanes past the lattice's end use its last site (results discarded)
+  const int xs = min(x0 + tx, v.lx - 1), y = min(y0 + ty, v.ly - 1);
   const size_t i = (size_t)y * v.lx + xs;
   const R *lam_next = static_cast<const R *>(a.lam_next);
-  R *lampart = static_cast<R *>(a.lampart);
+  R *lamout = static_cast<R *>(a.lam);
   R *fbar = static_cast<R *>(a.fbar);
 
-  auto psi_at = [&](int s, int dx, int dy) -> R {
-    size_t j;
-    return site_of<WALLS>(xs + dx, y + dy, v.lx, v.ly, j) ? v.fld(1, s, j) : R(a.psi_w[s]);
-  };
-  auto rho_at = [&](int s, int dx, int dy) -> R {
-    size_t j;
-    return site_of<WALLS>(xs + dx, y + dy, v.lx, v.ly, j) ? v.fld(0, s, j) : R(a.rho_w[s]);
-  };
+  auto psi_at = [&](int s, int dx, int dy) -> R { return sps[s][ty + 2 + dy][tx + 2 + dx]; };
+  auto rho_at = [&](int s, int dx, int dy) -> R { return srh[s][ty + 2 + dy][tx + 2 + dx]; };
 
   R rho[2], jx[2], jy[2], psi[2], Fx[2], Fy[2];
   R s1x[2], s1y[2], s2x[2], s2y[2], xx[2], xy[2], self[2];
   for (int s = 0; s < NS; ++s) {
-    rho[s] = v.fld(0, s, i);
-    psi[s] = v.fld(1, s, i);
+    rho[s] = rho_at(s, 0, 0);
+    psi[s] = psi_at(s, 0, 0);
     jx[s] = v.fld(2, s, i);
     jy[s] = v.fld(3, s, i);
     // two-belt sums with the attractive (w) and repulsive (p) shell weights
@@ -180,8 +213,11 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     mx += jx[s] + R(0.5) * Fx[s];
     my += jy[s] + R(0.5) * Fy[s];
   }
-  const R upx = nx / den, upy = ny / den;
-  const R urx = mx / rtot;  // reported (half-force) velocity, x component
+  // reciprocals taken once per site: the rest of the pass multiplies
+  const R iden = R(1) / den, irt = R(1) / rtot, ilx = R(1) / R(v.lx);
+  const R upx = nx * iden, upy = ny * iden;
+  const R urx = mx * irt;  // reported (half-force) velocity, x component
+  const R ilr = ilx * irt;  // 1 / (lx rho_tot)
 
   // adjoint sources of this step's loss
   const R cW = R(a.cW), cQ = R(a.cQ);
@@ -193,7 +229,8 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
   R lp[2][Q];
   for (int s = 0; s < NS; ++s) {
     const R om = R(a.omega[s]), tau = R(a.tau[s]);
-    const R ux = upx + tau * Fx[s] / rho[s], uy = upy + tau * Fy[s] / rho[s];
+    const R ir = R(1) / rho[s];
+    const R ux = upx + tau * Fx[s] * ir, uy = upy + tau * Fy[s] * ir;
     const R uu = ux * ux + uy * uy;
     R rb = 0, bx = 0, by = 0;
 #pragma unroll
@@ -202,21 +239,25 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
       // bounces back into opp(l) at x when x + c_l is a wall row
       size_t j;
       R al;
-      if (site_of<WALLS>(xs + CXS[l], y + CYS[l], v.lx, v.ly, j)) al = lam_next[((size_t)s * Q + l) * v.n + j];
-      else al = lam_next[((size_t)s * Q + OPPS[l]) * v.n + i];
+      if (site_of<WALLS>(xs + CXS[l], y + CYS[l], v.lx, v.ly, j))
+        al = lam_next[((size_t)s * Q + l) * v.n + j] + scn[s][ty + 1 + CYS[l]][tx + 1 + CXS[l]];
+      else
+        al = lam_next[((size_t)s * Q + OPPS[l]) * v.n + i] + scn[s][ty + 1][tx + 1];
       const R cu = R(CXS[l]) * ux + R(CYS[l]) * uy;
       const R wl = R(WD2Q9[l]);
-      const R feq = wl * rho[s] * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+      const R poly = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;  // f^eq_l / (W_l rho_s)
+      const R feq = wl * rho[s] * poly;
       if (WALLS && ((y == 0 && CYS[l] == -1) || (y == v.ly - 1 && CYS[l] == 1))) {
         // wall stress: d/dy_l of cW (1/2)(1/lx) (2 c_lx y_l - 6 W_l rho_w c_lx^2 U); the
         // moving wall's share is constant
-        al += cW * R(CXS[l]) / R(v.lx);
-        const R yl = (R(1) - om) * R(a.x[((size_t)s * Q + l) * v.n + i]) + om * feq;  // post-collision
+        al += cW * R(CXS[l]) * ilx;
+        // post-collision; x holds the two rows next to the walls, bottom then top
+        const R yl = (R(1) - om) * R(a.x[((size_t)(s * Q + l) * 2 + (y == 0 ? 0 : 1)) * v.lx + xs]) + om * feq;
         const R mw = R(3) * wl * R(a.rho_w[s]) * R(CXS[l] * CXS[l]) * R(y == 0 ? a.u_wall[0] : a.u_wall[1]);
         if (live) loss_w += double(cW * (R(CXS[l]) * yl - mw)) / v.lx;
       }
       lp[s][l] = (R(1) - om) * al;
-      rb += om * al * feq / rho[s];
+      rb += om * al * wl * poly;  // omega al f^eq / rho
       const R k = om * al * wl * rho[s];
       bx += k * (R(3) * R(CXS[l]) + R(9) * cu * R(CXS[l]) - R(3) * ux);
       by += k * (R(3) * R(CYS[l]) + R(9) * cu * R(CYS[l]) - R(3) * uy);
@@ -224,21 +265,21 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     // u_s = u' + tau F_s / rho_s
     ubx += bx;
     uby += by;
-    fbx[s] = tau * bx / rho[s];
-    fby[s] = tau * by / rho[s];
-    rb -= tau * (Fx[s] * bx + Fy[s] * by) / (rho[s] * rho[s]);
+    fbx[s] = tau * bx * ir;
+    fby[s] = tau * by * ir;
+    rb -= tau * (Fx[s] * bx + Fy[s] * by) * (ir * ir);
     rbar[s] = rb;
   }
   for (int s = 0; s < NS; ++s) {
     const R om = R(a.omega[s]);
     // u' = sum omega j / sum omega rho
-    jbx[s] = om * ubx / den;
-    jby[s] = om * uby / den;
-    rbar[s] -= om * (upx * ubx + upy * uby) / den;
+    jbx[s] = om * ubx * iden;
+    jby[s] = om * uby * iden;
+    rbar[s] -= om * (upx * ubx + upy * uby) * iden;
     // flow rate: Q = (1/lx) sum (sum_s j_s + F_s / 2)_x / sum_s rho_s
-    jbx[s] += cQ / (R(v.lx) * rtot);
-    fbx[s] += cQ / (R(2) * R(v.lx) * rtot);
-    rbar[s] -= cQ * urx / (R(v.lx) * rtot);
+    jbx[s] += cQ * ilr;
+    fbx[s] += R(0.5) * cQ * ilr;
+    rbar[s] -= cQ * urx * ilr;
   }
   // force: F_s = -psi_s S_s - G_AB self_s X_s + rho_s g
   double dg1[2] = {0, 0}, dg2[2] = {0, 0}, dgab = 0, dgx = 0, dgy = 0;
@@ -266,7 +307,7 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     for (int s = 0; s < NS; ++s) {
 #pragma unroll
       for (int l = 0; l < Q; ++l)
-        lampart[((size_t)s * Q + l) * v.n + i] = lp[s][l] + rbar[s] + R(CXS[l]) * jbx[s] + R(CYS[l]) * jby[s];
+        lamout[((size_t)s * Q + l) * v.n + i] = lp[s][l] + rbar[s] + R(CXS[l]) * jbx[s] + R(CYS[l]) * jby[s];
       // what the gather needs of this site: A_s = psi_s Fbar_s, B_s = r_s Fbar_s
       fbar[((size_t)s * 4 + 0) * v.n + i] = psi[s] * fbx[s];
       fbar[((size_t)s * 4 + 1) * v.n + i] = psi[s] * fby[s];
@@ -274,38 +315,42 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
       fbar[((size_t)s * 4 + 3) * v.n + i] = self[s] * fby[s];
     }
   }
-  // per-block partial sums, accumulated over the reverse steps in each block's own row
-  // (fixed order: waves, then steps, then blocks in the final pass)
+  // per-tile partial sums, accumulated over the reverse steps in each tile's own row
+  // (fixed order: waves, then steps, then tiles in the final pass)
   double vals[ADJ_N] = {dg1[0], dg1[1], dg2[0], dg2[1], dgab, dgx, dgy, loss_w, loss_q};
   const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-#pragma unroll
-  for (int k = 0; k < ADJ_N; ++k) {
-    const double t = block_sum(vals[k], sm);
-    if (threadIdx.x == 0) a.partials[blk * ADJ_N + k] += t;
-  }
+  tile_accumulate(vals, sm, a.partials + blk * ADJ_N);
 }
 
 // Nonlocal part: the force's dependence on the neighbours' psi (and rho), gathered with the
-// forward stencil; completes lambda(t).
+// forward stencil; writes corr, the term of lambda(t) common to every l (the next reverse step
+// adds it to lam as it reads lambda).
 template <typename R, int NS, bool WALLS>
 __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
   AdjView<R> v(a);
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= v.lx) return;
-  const size_t i = (size_t)y * v.lx + x;
+  // per species: psi_s Fbar_s (x, y) and r_s Fbar_s (x, y) of tile + halo, zero off the lattice
+  __shared__ R sab[2][4][AHY][AHX];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * ATX, y0 = blockIdx.y * ATY;
   const R *fbar = static_cast<const R *>(a.fbar);
-  const R *lampart = static_cast<const R *>(a.lampart);
-  R *lam = static_cast<R *>(a.lam);
-  // A_s = psi_s Fbar_s (which = 0) or B_s = r_s Fbar_s (which = 1) at a neighbour (zero on
-  // wall rows)
+  for (int k = threadIdx.x; k < AHX * AHY; k += 256) {
+    const int hx = k % AHX, hy = k / AHX;
+    size_t j = 0;
+    const bool in = stage_site<WALLS>(x0 - 2 + hx, y0 - 2 + hy, v.lx, v.ly, j);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sab[s][c][hy][hx] = in ? fbar[((size_t)s * 4 + c) * v.n + j] : R(0);
+  }
+  __syncthreads();
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= v.lx || y >= v.ly) return;  // after the kernel's only barrier
+  const size_t i = (size_t)y * v.lx + x;
+  R *corr = static_cast<R *>(a.corr);
+  // A_s = psi_s Fbar_s (which = 0) or B_s = r_s Fbar_s (which = 1) at a neighbour
   auto AB = [&](int which, int s, int dx, int dy, R &bx, R &by) {
-    size_t j;
-    if (!site_of<WALLS>(x + dx, y + dy, v.lx, v.ly, j)) {
-      bx = by = 0;
-      return;
-    }
-    bx = fbar[((size_t)s * 4 + 2 * which + 0) * v.n + j];
-    by = fbar[((size_t)s * 4 + 2 * which + 1) * v.n + j];
+    bx = sab[s][2 * which + 0][ty + 2 + dy][tx + 2 + dx];
+    by = sab[s][2 * which + 1][ty + 2 + dy][tx + 2 + dx];
   };
   R psib[2] = {0, 0}, rbar[2] = {0, 0};
   for (int s = 0; s < NS; ++s) {
@@ -340,9 +385,7 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
   }
   for (int s = 0; s < NS; ++s) {
     const R r = v.fld(0, s, i);
-    const R rb = rbar[s] + psib[s] * R(a.psi0) * R(a.irho0) * exp(-r * R(a.irho0));
-#pragma unroll
-    for (int l = 0; l < Q; ++l) lam[((size_t)s * Q + l) * v.n + i] = lampart[((size_t)s * Q + l) * v.n + i] + rb;
+    corr[(size_t)s * v.n + i] = rbar[s] + psib[s] * R(a.psi0) * R(a.irho0) * exp(-r * R(a.irho0));
   }
 }
 
@@ -362,14 +405,13 @@ __global__ void zero_kernel(uint32_t *p, size_t n) {
   if (i < n) p[i] = 0u;
 }
 
-int adj_blocks(int lx, int ly) { return ((lx + 255) / 256) * ly; }
+int adj_blocks(int lx, int ly) { return ((lx + ATX - 1) / ATX) * ((ly + ATY - 1) / ATY); }
 
 template <typename R, int NS, bool WALLS>
 static hipError_t adj_step_t(const AdjArgs &a, hipStream_t st) {
-  const dim3 grid((a.lx + 255) / 256, a.ly), block(256);
-  if (!a.fields_ready) hipLaunchKernelGGL((adj_fields_kernel<R, NS>), grid, block, 0, st, a);
-  hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS>), grid, block, 0, st, a);
-  hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), grid, block, 0, st, a);
+  const dim3 tiles((a.lx + ATX - 1) / ATX, (a.ly + ATY - 1) / ATY), block(ATX * ATY);
+  hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS>), tiles, block, 0, st, a);
+  hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), tiles, block, 0, st, a);
   return hipGetLastError();
 }
 

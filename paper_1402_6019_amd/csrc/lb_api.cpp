@@ -166,8 +166,9 @@ hipError_t launch_two_steps(const lb_ctx *c, int from, hipStream_t st, uint32_t 
   return launch_step2(step_mode(c), c->lat.n_species, c->lat.walls, nb, a, st);
 }
 
-// Canonical FP64 pre-collision populations of buffer `from` into dst, and the reverse step's
-// fields of that state (rho, psi, j per species; FP64 if fp64) into fields, on stream st.
+// What the adjoint's reverse step reads of the state in buffer `from`: the canonical FP64
+// pre-collision populations of the rows next to the walls into dst ([s][l][2][lx]), and the
+// fields rho, psi, j per species (FP64 if fp64) into fields, on stream st.
 hipError_t launch_checkpoint_fields_from(const lb_ctx *c, int from, void *dst, void *fields, int fp64, hipStream_t st) {
   LayoutArgs la{};
   la.in = c->pop[from];
@@ -784,8 +785,10 @@ namespace {
 
 struct AdjLayout {
   int every = 1, ncp = 1;
-  size_t s64 = 0, lamb = 0, nsite = 0, fb = 0;
-  size_t ckpt = 0, seg = 0, fin = 0, lam0 = 0, lam1 = 0, lampart = 0, fields = 0, fbar = 0, partials = 0, acc = 0;
+  bool all = false;  // every == 1: what the reverse step reads of every state, kept by the forward pass
+  size_t s64 = 0, lamb = 0, nsite = 0, fb = 0, xw = 0;
+  size_t corrb = 0;
+  size_t ckpt = 0, seg = 0, fin = 0, lam0 = 0, lam1 = 0, corr0 = 0, corr1 = 0, fields = 0, fbar = 0, partials = 0, acc = 0;
   size_t total = 0;
 };
 
@@ -801,17 +804,25 @@ AdjLayout adjoint_layout(const lb_ctx *c, int64_t T, int32_t every, int32_t flag
   L.nsite = (size_t)c->lat.lx * c->lat.ly;
   const size_t rs = adjoint_fp64(c, flags) ? 8 : 4;
   const int ns = c->lat.n_species;
+  L.all = L.every == 1;
+  // no checkpoints to restore from when every state is kept
+  if (L.all) L.ncp = 0;
+  // per state: the FP64 populations of the two rows next to the walls, and the fields
+  const int64_t nstate = L.all ? std::max<int64_t>(T, 1) : L.every;
   L.s64 = align256((size_t)ns * 9 * L.nsite * 8);
+  L.xw = align256((size_t)ns * 9 * 2 * c->lat.lx * 8);
   L.lamb = align256((size_t)ns * 9 * L.nsite * rs);
+  L.fb = align256(8 * L.nsite * rs);
   size_t o = 0;
   L.ckpt = o; o += (size_t)L.ncp * L.s64;
-  L.seg = o; o += (size_t)L.every * L.s64;
-  L.fin = o; o += align256(lb_pop_bytes(&c->lat));
+  L.seg = o; o += (size_t)nstate * L.xw;
+  L.fin = o; o += L.all ? 0 : align256(lb_pop_bytes(&c->lat));
   L.lam0 = o; o += L.lamb;
   L.lam1 = o; o += L.lamb;
-  L.lampart = o; o += L.lamb;
-  L.fb = align256(8 * L.nsite * rs);
-  L.fields = o; o += (size_t)L.every * L.fb;  // one set per state of a segment
+  L.corrb = align256((size_t)ns * L.nsite * rs);
+  L.corr0 = o; o += L.corrb;
+  L.corr1 = o; o += L.corrb;
+  L.fields = o; o += (size_t)nstate * L.fb;  // one set per state of a segment (of the run when all)
   L.fbar = o; o += align256(8 * L.nsite * rs);
   L.partials = o; o += align256((size_t)adj_blocks(c->lat.lx, c->lat.ly) * ADJ_N * 8);
   L.acc = o; o += align256(ADJ_N * 8);
@@ -881,37 +892,53 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
     c->reduce_every = keep_reduce;
     return code;
   };
-  // forward pass with a checkpoint every L.every steps
-  for (int k = 0; k < L.ncp; ++k) {
-    if ((rc = lb_checkpoint(c, ws + L.ckpt + (size_t)k * L.s64))) return done(rc);
-    if ((rc = lb_step(c, std::min<int64_t>(L.every, T - (int64_t)k * L.every)))) return done(rc);
+  const int fp64 = adjoint_fp64(c, flags) ? 1 : 0;
+  hipError_t e = hipSuccess;
+  if (L.all) {
+    // forward pass keeping what the reverse step reads of every state: no recompute later
+    for (int64_t t = 0; t < T && e == hipSuccess; ++t) {
+      e = launch_checkpoint_fields_from(c, c->cur, ws + L.seg + (size_t)t * L.xw, ws + L.fields + (size_t)t * L.fb,
+                                        fp64, c->stream);
+      if (e == hipSuccess) e = launch_plain_step(c, c->cur, c->stream, (uint32_t)c->t, nullptr);
+      c->cur ^= 1;
+      ++c->t;
+    }
+    if (e != hipSuccess) return done(hip_fail(c, e, "adjoint forward pass"));
+  } else {
+    // forward pass with a checkpoint every L.every steps
+    for (int k = 0; k < L.ncp; ++k) {
+      if ((rc = lb_checkpoint(c, ws + L.ckpt + (size_t)k * L.s64))) return done(rc);
+      if ((rc = lb_step(c, std::min<int64_t>(L.every, T - (int64_t)k * L.every)))) return done(rc);
+    }
   }
-  // the final state, bit for bit (the context continues from it)
+  // the final state, bit for bit (the context continues from it; the checkpointed sweep
+  // overwrites the population buffers while recomputing)
   const int cur_final = c->cur;
   const size_t popb = lb_pop_bytes(&c->lat);
-  hipError_t e = hipMemcpyAsync(ws + L.fin, c->pop[cur_final], popb, hipMemcpyDeviceToDevice, c->stream);
+  if (!L.all) e = hipMemcpyAsync(ws + L.fin, c->pop[cur_final], popb, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = launch_zero(ws + L.lam1, L.lamb, c->stream);
+  if (e == hipSuccess) e = launch_zero(ws + L.corr1, L.corrb, c->stream);
   if (e == hipSuccess) e = launch_zero(ws + L.acc, ADJ_N * 8, c->stream);
   if (e == hipSuccess)
     e = launch_zero(ws + L.partials, (size_t)adj_blocks(c->lat.lx, c->lat.ly) * ADJ_N * 8, c->stream);
   if (e != hipSuccess) return done(hip_fail(c, e, "adjoint setup"));
-  // reverse sweep, one checkpoint segment at a time
+  // reverse sweep: over the whole run when every state was kept, else one checkpoint segment at
+  // a time
   AdjArgs a = adjoint_args(c, loss_weights[0], loss_weights[1], T);
-  a.lampart = ws + L.lampart;
-  a.fields_ready = 1;
   a.fbar = ws + L.fbar;
   a.partials = reinterpret_cast<double *>(ws + L.partials);
   double *acc = reinterpret_cast<double *>(ws + L.acc);
-  char *lam_buf[2] = {ws + L.lam1, ws + L.lam0};  // lambda(t+1) is lam_buf[q], lambda(t) lam_buf[q ^ 1]
+  // lambda(t+1) is lam_buf[q] + corr_buf[q], lambda(t) lam_buf[q ^ 1] + corr_buf[q ^ 1]
+  char *lam_buf[2] = {ws + L.lam1, ws + L.lam0};
+  char *corr_buf[2] = {ws + L.corr1, ws + L.corr0};
   int q = 0;
-  const int fp64 = adjoint_fp64(c, flags) ? 1 : 0;
   // A full segment's recompute (checkpoint each state, step) and its reverse sweep are the
   // same launches for every full segment up to the ping-pong parities: each is captured
   // once per parity as a HIP graph and replayed; a shorter last segment runs eagerly.
   auto recompute = [&](int from, int len, hipStream_t st) -> hipError_t {
     hipError_t er = hipSuccess;
     for (int jj = 0; jj < len && er == hipSuccess; ++jj) {
-      er = launch_checkpoint_fields_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.s64,
+      er = launch_checkpoint_fields_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.xw,
                                          ws + L.fields + (size_t)jj * L.fb, fp64, st);
       if (er == hipSuccess && jj + 1 < len) er = launch_plain_step(c, from ^ (jj & 1), st, 0u, nullptr);
     }
@@ -921,10 +948,12 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
     hipError_t er = hipSuccess;
     int qq = q0;
     for (int jj = len - 1; jj >= 0 && er == hipSuccess; --jj) {
-      a.x = reinterpret_cast<const double *>(ws + L.seg + (size_t)jj * L.s64);
+      a.x = reinterpret_cast<const double *>(ws + L.seg + (size_t)jj * L.xw);
       a.fields = ws + L.fields + (size_t)jj * L.fb;
       a.lam_next = lam_buf[qq];
+      a.corr_next = corr_buf[qq];
       a.lam = lam_buf[qq ^ 1];
+      a.corr = corr_buf[qq ^ 1];
       er = launch_adjoint_step(fp64, c->lat.n_species, c->lat.walls, a, st);
       qq ^= 1;
     }
@@ -937,6 +966,11 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
     g_rev.destroy();
     return done(code);
   };
+  if (L.all) {
+    // every state was kept: one reverse sweep over the whole run
+    e = reverse(q, (int)T, c->stream);
+    if (e != hipSuccess) return graphs_done(hip_fail(c, e, "adjoint sweep"));
+  }
   for (int k = L.ncp - 1; k >= 0; --k) {
     const int len = (int)std::min<int64_t>(L.every, T - (int64_t)k * L.every);
     if ((rc = lb_restore(c, ws + L.ckpt + (size_t)k * L.s64))) return graphs_done(rc);
@@ -961,7 +995,7 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   g_fwd.destroy();
   g_rev.destroy();
   // back to the state after T steps
-  e = hipMemcpyAsync(c->pop[cur_final], ws + L.fin, popb, hipMemcpyDeviceToDevice, c->stream);
+  if (!L.all) e = hipMemcpyAsync(c->pop[cur_final], ws + L.fin, popb, hipMemcpyDeviceToDevice, c->stream);
   double h[ADJ_N];
   if (e == hipSuccess) e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -107,8 +107,9 @@ struct LayoutArgs {
   long long plane;
   int lx, ly, pitch, ns;
   double rho_ref[2];
-  // checkpoint with fields (adjoint recompute): rho, psi, jx, jy of each species of the
-  // canonical state, [4][2][ly][lx] in the adjoint's precision
+  // checkpoint with fields (adjoint): out receives only the canonical populations of the rows
+  // next to the walls ([s][l][2][lx], FP64), fields rho, psi, jx, jy of each species of the
+  // state, [4][2][ly][lx] in the adjoint's precision
   void *fields;
   double psi0, irho0;
 };
@@ -116,10 +117,14 @@ struct LayoutArgs {
 // Reverse step of the adjoint (lb_adjoint.hip).  Arrays are canonical [..][y][x]; R is
 // double for FP64 contexts and float otherwise.
 struct AdjArgs {
-  const double *x;       // forward pre-collision state f(t) [s][l][y][x], FP64
-  const void *lam_next;  // lambda(t+1) [s][l][y][x] (R)
-  void *lam;             // lambda(t) (R, written)
-  void *lampart;         // local part of lambda(t) (R, scratch)
+  const double *x;       // pre-collision populations f(t) of the rows next to the walls, [s][l][2][x]
+                         // (bottom row, then top row), FP64; read with walls only
+  // lambda(t) is kept in two parts: lam [s][l][y][x], written by the local pass, and corr
+  // [s][y][x], the term common to every l that the gather adds; lambda_l = lam_l + corr.
+  const void *lam_next;   // lam of lambda(t+1) (R)
+  const void *corr_next;  // corr of lambda(t+1) (R)
+  void *lam;              // lam of lambda(t) (R, written)
+  void *corr;             // corr of lambda(t) (R, written)
   void *fields;          // [4][2][y][x] (R): rho, psi, jx, jy of f(t)
   void *fbar;            // [2][4][y][x] (R): psi_s Fbar_s and r_s Fbar_s (x, y components)
   double *partials;      // [blocks][ADJ_N]
@@ -133,7 +138,6 @@ struct AdjArgs {
   double rho_w[2], psi_w[2];
   double cW, cQ;         // per-step loss weights
   double u_wall[2];      // x-velocity of the bottom and top wall
-  int fields_ready;      // fields already hold rho, psi, j of x (written with the checkpoint)
 };
 
 // Per-block partial sums of the adjoint: parameter sensitivities and the loss.

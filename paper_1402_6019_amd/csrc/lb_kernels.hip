@@ -202,8 +202,9 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
     }
 }
 
-// Checkpoint of the adjoint's recompute: the canonical state as checkpoint_kernel writes it,
-// and from the same values the moments and pseudopotential the reverse step needs
+// What the adjoint's reverse step reads of a state: the canonical populations of the rows next
+// to the walls (bottom row, then top row; the wall stress needs them), and the moments and
+// pseudopotential of every site
 // (rho_s = sum_l f_l, psi_s = psi0 (1 - exp(-rho_s / rho0)), j_s = sum_l c_l f_l), summed in
 // l order in the adjoint's precision RA.
 template <int MODE, bool WALLS, typename RA>
@@ -218,6 +219,9 @@ __global__ void checkpoint_fields_kernel(LayoutArgs a) {
   RA *fl = static_cast<RA *>(a.fields);
   const size_t nsite = (size_t)a.lx * a.ly;
   const size_t i = (size_t)y * a.lx + x;
+  // the reverse step reads the populations themselves only on the rows next to a wall (for
+  // the wall stress); elsewhere the fields suffice
+  const bool wall_row = WALLS && (y == 0 || y == a.ly - 1);
   for (int s = 0; s < a.ns; ++s) {
     RA r = 0, jx = 0, jy = 0;
 #pragma unroll
@@ -233,7 +237,7 @@ __global__ void checkpoint_fields_kernel(LayoutArgs a) {
       }
       const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), R(WD2Q9[lsrc] * a.rho_ref[s]));
       const double fv = double(v);
-      f[(size_t)(s * 9 + l) * nsite + i] = fv;
+      if (wall_row) f[((size_t)(s * 9 + l) * 2 + (y == 0 ? 0 : 1)) * a.lx + x] = fv;
       const RA g = RA(fv);
       r += g;
       jx += RA(CXS[l]) * g;

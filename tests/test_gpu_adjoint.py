@@ -30,7 +30,7 @@ def to4(g7):
     return np.array([g7[0] + g7[1], g7[2] + g7[3], g7[4], g7[5]])
 
 
-@pytest.mark.parametrize("every", [8, 0])
+@pytest.mark.parametrize("every", [8, 0, 1])
 def test_adjoint_fp64_matches_oracle_complex_step_channel(every):
     c = channel()
     T, lw = 60, (1.0, 0.3)
@@ -41,6 +41,33 @@ def test_adjoint_fp64_matches_oracle_complex_step_channel(every):
     assert loss == pytest.approx(L_o, rel=1e-10)
     np.testing.assert_allclose(to4(g7), d_o, rtol=1e-8, atol=1e-12 * np.abs(d_o).max())
     sim.close()
+
+
+@pytest.mark.parametrize("storage,fp64_reverse", [("f64", False), ("f32", True), ("f32", False)])
+def test_adjoint_keeping_every_state_matches_the_checkpointed_sweep(storage, fp64_reverse):
+    """every = 1 (the forward pass keeps what the reverse step reads of every state) and the
+    checkpointed sweeps (every = 7, every = sqrt(T)) run the same reverse steps.  With FP64
+    storage the recomputed states are bitwise the forward's, so loss and gradient agree
+    exactly.  With FP32 storage a checkpoint holds the populations f = d + W rho_ref, and the
+    restore rounds f - W rho_ref back to FP32: the recomputed states differ from the
+    forward's in the last bits of the smaller deviations, and loss and gradient agree to
+    1e-5.  The state after the call is bitwise that of plain stepping in every case."""
+    c = channel(storage=storage)
+    T, lw = 45, (1.0, 0.3)
+    res = {}
+    for every in (1, 7, 0):
+        sim = make_sim(c)
+        loss, g7 = sim.adjoint(T, lw, every=every, fp64_reverse=fp64_reverse)
+        res[every] = (loss, g7, sim.checkpoint().cpu().numpy())
+        sim.close()
+    for every in (7, 0):
+        if storage == "f64":
+            assert res[every][0] == res[1][0]
+            assert np.array_equal(res[every][1], res[1][1])
+        else:
+            assert res[every][0] == pytest.approx(res[1][0], rel=1e-5)
+            np.testing.assert_allclose(res[every][1], res[1][1], rtol=1e-5, atol=1e-9 * np.abs(res[1][1]).max())
+        assert np.array_equal(res[every][2], res[1][2])
 
 
 def test_adjoint_fp64_single_component_periodic():
@@ -226,14 +253,15 @@ def test_adjoint_full_horizon_against_oracle_gradient():
     c = dict(lx=mk.LX, ly=mk.LY, ns=2, walls=1, g1=P.g1, g2=P.g2, gab=P.gab, body=P.body, rho_wall=P.rho_wall,
              tau=P.tau, psi0=P.psi0, rho0=P.rho0, rho=rho, storage="f64", rho_ref=(0.0, 0.0))
     res = {}
-    for storage, tol in (("f64", 1e-8), ("f32", 1e-4)):
+    # every = 0: checkpoints every sqrt(T) steps; every = 1: every state kept (34 GB here)
+    for storage, every, tol in (("f64", 0, 1e-8), ("f32", 0, 1e-4), ("f64", 1, 1e-8)):
         sim = make_sim(dict(c, storage=storage, rho_ref=(0.0, 0.0) if storage == "f64" else
                             (float(rho[0].mean()), float(rho[1].mean()))))
         sim.restore(f0)
-        loss, g7 = sim.adjoint(fix["T"], tuple(fix["loss_weights"]), fp64_reverse=True)
+        loss, g7 = sim.adjoint(fix["T"], tuple(fix["loss_weights"]), every=every, fp64_reverse=True)
         sim.close()
         e = np.abs(to4(g7) - d_o) / np.abs(d_o)
-        res[storage] = e
-        print(f"T=4000 {storage} forward, FP64 reverse: loss {loss:.12e} vs {fix['loss']:.12e}; "
+        res[(storage, every)] = e
+        print(f"T=4000 {storage} forward (every={every}), FP64 reverse: loss {loss:.12e} vs {fix['loss']:.12e}; "
               f"rel err vs oracle {e}", flush=True)
-        assert e.max() < tol, (storage, e)
+        assert e.max() < tol, (storage, every, e)
