@@ -11,7 +11,9 @@
 // its 64 lanes cover the strip plus 5 columns on each side (lane i is column x0 - 5 + i).
 // The first step (L1) is valid on lanes 2..61 (its force needs psi two columns away), the
 // pull of the second step (L2) on lanes 3..60, and L2's force on lanes 5..58, the 54
-// output columns.  The wave marches its segment row by row; in the iteration of lead row r:
+// output columns.  The wave marches its segment row by row (up, or down in odd segments; the
+// offsets below are for the upward march and change sign downward); in the iteration of lead
+// row r:
 //   (a) psi(t), rho(t) of row r (from the pulled populations of r, loaded three iterations
 //       earlier into a register FIFO) into the L1 ring;
 //   (b) L1 update of row r - 2 (force from the L1 ring, collision) -> f*(t) of that row,
@@ -26,6 +28,8 @@
 // keeping f*(t) on chip.
 
 #pragma once
+
+#include <type_traits>
 
 #include "lb_step.hpp"
 
@@ -48,13 +52,17 @@ inline size_t step2_lds_bytes(int mode, int ns) {
   return (2 * kRing2Psi + 2 * kRing2Rho + kIn2Rows * 64) * (size_t)ns * r;
 }
 
-// Plane row of the input ring holding plane l of f*(t) at row r (see step2_lds_bytes).
-__device__ inline int in2_row(int l, int r) {
-  // group of the plane: 0 {0, 1, 3} two slots, 1 {2, 5, 6} three slots, 2 {4, 7, 8} two slots
+// Plane row of the input ring holding plane l of f*(t) at row r, for a wave marching in
+// direction dir (see step2_lds_bytes): the planes pulled from the row behind the march are kept
+// one row longer.
+__device__ inline int in2_row(int l, int r, int dir) {
+  // group of the plane: 0 {0, 1, 3} two slots; 1 {2, 5, 6} (pulled from the row below) and
+  // 2 {4, 7, 8} (from the row above): three slots for the one behind the march, two for the other
   const int g = (l == 0 || l == 1 || l == 3) ? 0 : ((l == 2 || l == 5 || l == 6) ? 1 : 2);
   const int pos = (l == 0 || l == 2 || l == 4) ? 0 : ((l == 1 || l == 5 || l == 7) ? 1 : 2);
-  const int base = g == 0 ? 0 : (g == 1 ? 6 : 15);
-  const int ns = g == 1 ? 3 : 2;
+  const int n1 = dir > 0 ? 3 : 2;
+  const int base = g == 0 ? 0 : (g == 1 ? 6 : 6 + 3 * n1);
+  const int ns = g == 0 ? 2 : (g == 1 ? n1 : 5 - n1);
   const int slot = ((r % ns) + ns) % ns;
   return base + slot * 3 + pos;
 }
@@ -84,6 +92,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void st
   const int lane = threadIdx.x;
   const int x0 = strip * kStrip2;
   const int yA = seg * a.sy, yB = min(yA + a.sy, ly);
+
 
   // this lane's column (wrapped onto the lattice) and whether it stores an output column
   const int xs = x0 - kPad2 + lane;
@@ -119,7 +128,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void st
 
   auto slot5 = [](int r) { return (int)uni((uint32_t)(((r % 5) + 5) % 5)); };
   auto slot4 = [](int r) { return (int)uni((uint32_t)(((r % 4) + 4) % 4)); };
-  auto inrow = [&](int l, int r) { return inr + (int)uni((uint32_t)in2_row(l, r)) * 64; };
 
   // psi and rho of a site from its pulled (decoded) populations, as the single-step ring does
   auto site_ring = [&](V *ps_row, V *rh_row, int r, const R (&f)[NS][9]) {
@@ -257,136 +265,151 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void st
     }
   };
 
-  // Register FIFO of pulled f(t) rows (6 rows: lead row r + 3 in flight ... row r - 2 held for
-  // its L1 update) and of pulled f(t+1) rows (3 rows: r - 3 .. r - 5).
-  constexpr int D1 = 6, D2 = 3;
-  L B1[D1][NS][9];
-  R B2[D2][NS][9];
-  const int rfirst = yA - 5, rlast = yB + 4;  // lead rows of the segment's iterations
-  auto load_row = [&](int r, L (&dstb)[NS][9]) {
-    const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r, ly), ly, row_b);
-    load_pull<C, NS>(a.src, buf_b, plane_b, pcc, pr, dstb);
-  };
-#pragma unroll
-  for (int m = 0; m < 3; ++m) load_row(rfirst + m, B1[m]);
+  // The march, for each direction as its own code: odd segments march down, so two neighbouring
+  // segments pull their shared lead rows at the same time (both at their start or both at their
+  // end) and L2 serves the second pull.  The direction is a compile-time constant of each copy:
+  // as a run-time value it costs the registers that the march cannot spare.
+  auto march = [&](auto dirc) {
+    constexpr int dir = decltype(dirc)::value;
+    auto inrow = [&](int l, int r) { return inr + (int)uni((uint32_t)in2_row(l, r, dir)) * 64; };
 
-  const int niter = rlast - rfirst + 1;
-  auto iteration = [&](const int r_in, L (&FL)[NS][9], const L (&FR)[NS][9], const L (&FU)[NS][9],
-                       R (&P2)[NS][9], const R (&P2old)[NS][9]) {
-    const int r = (int)uni((uint32_t)r_in);
-    // issue the loads of lead row r + 3
-    if (r + 3 <= rlast) load_row(r + 3, FL);
+    // Register FIFO of pulled f(t) rows (6 rows: lead row r + 3 in flight ... row r - 2 held for
+    // its L1 update) and of pulled f(t+1) rows (3 rows: r - 3 .. r - 5).
+    constexpr int D1 = 6, D2 = 3;
+    L B1[D1][NS][9];
+    R B2[D2][NS][9];
+    // lead rows of the segment's iterations: yA - 5 .. yB + 4, in march order from rstart
+    const int rlo = yA - 5, rhi = yB + 4;
+    const int rstart = dir > 0 ? rlo : rhi;
+    auto in_range = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
+    auto load_row = [&](int r, L (&dstb)[NS][9]) {
+      const RowOffs pr = row_pull<WALLS>(lead_row<WALLS>(r, ly), ly, row_b);
+      load_pull<C, NS>(a.src, buf_b, plane_b, pcc, pr, dstb);
+    };
+#pragma unroll
+    for (int m = 0; m < 3; ++m) load_row(rstart + dir * m, B1[m]);
 
-    // (a) psi(t), rho(t) of lead row r
-    {
-      R f[NS][9];
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-#pragma unroll
-        for (int l = 0; l < 9; ++l) f[s][l] = C::dec(FR[s][l], s);
-      site_ring(ring1 + slot5(r) * 64, rho1 + slot4(r) * 64, r, f);
-    }
+    const int niter = rhi - rlo + 1;
+    auto iteration = [&](const int r_in, L (&FL)[NS][9], const L (&FR)[NS][9], const L (&FU)[NS][9],
+                         R (&P2)[NS][9], const R (&P2old)[NS][9]) {
+      const int r = (int)uni((uint32_t)r_in);
+      // issue the loads of lead row r + 3
+      if (in_range(r + 3 * dir, rlo, rhi)) load_row(r + 3 * dir, FL);
 
-    // (b) L1 update of row r - 2 -> the input ring
-    const int u1 = r - 2;
-    if (u1 >= yA - 3 && row_fluid<WALLS>(u1, ly)) {
-      R f[NS][9];
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-#pragma unroll
-        for (int l = 0; l < 9; ++l) f[s][l] = C::dec(FU[s][l], s);
-      V *prow[5];
-      V *xrow[3];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) prow[k] = ring1 + slot5(u1 - 2 + k) * 64;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        xrow[k] = a.cross_psi ? ring1 + slot5(u1 - 1 + k) * 64 : rho1 + slot4(u1 - 1 + k) * 64;
-      R fsa[NS][9];
-      update(u1, f, prow, xrow, fsa);
-      const int yw = WALLS ? u1 : wrapi(u1, ly);
-      uint32_t hs = 0;
-      if constexpr (MODE == MODE_BF16SR) hs = mix32((uint32_t)(yw * lx + xc) ^ tseed1);
-#pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        V v;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) v.v[s] = stored(fsa[s][l], s, l, hs);
-        inrow(l, u1)[lane] = v;
-      }
-    }
-
-    // (c) L2 pull of row r - 3 from the input ring; psi(t+1), rho(t+1) into the L2 ring
-    const int p2 = r - 3;
-    if (p2 >= yA - 2) {
-      if (row_fluid<WALLS>(p2, ly)) {
-        const bool lo = WALLS && p2 == 0, hi = WALLS && p2 == ly - 1;
-        const int lm = (lane - 1) & 63, lp = (lane + 1) & 63;  // pull from x - 1 / x + 1
-        V g[9];
-        g[0] = inrow(0, p2)[lane];
-        g[1] = inrow(1, p2)[lm];
-        g[3] = inrow(3, p2)[lp];
-        // c_y = +1 from the row below, or reflected off the wall below (planes 4, 7, 8 in place)
-        g[2] = lo ? inrow(4, p2)[lane] : inrow(2, p2 - 1)[lane];
-        g[5] = lo ? inrow(7, p2)[lane] : inrow(5, p2 - 1)[lm];
-        g[6] = lo ? inrow(8, p2)[lane] : inrow(6, p2 - 1)[lp];
-        // c_y = -1 from the row above, or reflected off the wall above (planes 2, 5, 6 in place)
-        g[4] = hi ? inrow(2, p2)[lane] : inrow(4, p2 + 1)[lane];
-        g[7] = hi ? inrow(5, p2)[lane] : inrow(7, p2 + 1)[lp];
-        g[8] = hi ? inrow(6, p2)[lane] : inrow(8, p2 + 1)[lm];
+      // (a) psi(t), rho(t) of lead row r
+      {
+        R f[NS][9];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-          for (int l = 0; l < 9; ++l) P2[s][l] = g[l].v[s];
+          for (int l = 0; l < 9; ++l) f[s][l] = C::dec(FR[s][l], s);
+        site_ring(ring1 + slot5(r) * 64, rho1 + slot4(r) * 64, r, f);
       }
-      site_ring(ring2 + slot5(p2) * 64, rho2 + slot4(p2) * 64, p2, P2);
-    }
 
-    // (d) L2 update of row r - 5 and the store of f*(t+1)
-    const int u2 = r - 5;
-    if (u2 >= yA) {
-      V *prow[5];
-      V *xrow[3];
+      // (b) L1 update of row r - 2 -> the input ring
+      const int u1 = r - 2 * dir;
+      if (in_range(u1, yA - 3, yB + 2) && row_fluid<WALLS>(u1, ly)) {
+        R f[NS][9];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) prow[k] = ring2 + slot5(u2 - 2 + k) * 64;
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        xrow[k] = a.cross_psi ? ring2 + slot5(u2 - 1 + k) * 64 : rho2 + slot4(u2 - 1 + k) * 64;
-      R fsa[NS][9];
-      update(u2, P2old, prow, xrow, fsa);
-      if (out_lane) {
-        const Rsrc rd = make_rsrc(a.dst, buf_b);
-        const uint32_t rb0 = (uint32_t)u2 * row_b;
-        const uint32_t sto = (uint32_t)xc * site_b;
-        if constexpr (MODE == MODE_BF16SR) {
-          const uint32_t hs = mix32((uint32_t)(u2 * lx + xc) ^ tseed2);
+          for (int l = 0; l < 9; ++l) f[s][l] = C::dec(FU[s][l], s);
+        V *prow[5];
+        V *xrow[3];
 #pragma unroll
-          for (int l = 0; l < 9; ++l) {
-            const uint32_t rnd = mix32(hs + (uint32_t)l * 0x9e3779b9u);
-            if (NS == 2) C::template bstore2_sr<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l], rnd);
-            else C::template bstore_sr<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], rnd);
+        for (int k = 0; k < 5; ++k) prow[k] = ring1 + slot5(u1 - 2 + k) * 64;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          xrow[k] = a.cross_psi ? ring1 + slot5(u1 - 1 + k) * 64 : rho1 + slot4(u1 - 1 + k) * 64;
+        R fsa[NS][9];
+        update(u1, f, prow, xrow, fsa);
+        const int yw = WALLS ? u1 : wrapi(u1, ly);
+        uint32_t hs = 0;
+        if constexpr (MODE == MODE_BF16SR) hs = mix32((uint32_t)(yw * lx + xc) ^ tseed1);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+          V v;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) v.v[s] = stored(fsa[s][l], s, l, hs);
+          inrow(l, u1)[lane] = v;
+        }
+      }
+
+      // (c) L2 pull of row r - 3 from the input ring; psi(t+1), rho(t+1) into the L2 ring
+      const int p2 = r - 3 * dir;
+      if (in_range(p2, yA - 2, yB + 1)) {
+        if (row_fluid<WALLS>(p2, ly)) {
+          const bool lo = WALLS && p2 == 0, hi = WALLS && p2 == ly - 1;
+          const int lm = (lane - 1) & 63, lp = (lane + 1) & 63;  // pull from x - 1 / x + 1
+          V g[9];
+          g[0] = inrow(0, p2)[lane];
+          g[1] = inrow(1, p2)[lm];
+          g[3] = inrow(3, p2)[lp];
+          // c_y = +1 from the row below, or reflected off the wall below (planes 4, 7, 8 in place)
+          g[2] = lo ? inrow(4, p2)[lane] : inrow(2, p2 - 1)[lane];
+          g[5] = lo ? inrow(7, p2)[lane] : inrow(5, p2 - 1)[lm];
+          g[6] = lo ? inrow(8, p2)[lane] : inrow(6, p2 - 1)[lp];
+          // c_y = -1 from the row above, or reflected off the wall above (planes 2, 5, 6 in place)
+          g[4] = hi ? inrow(2, p2)[lane] : inrow(4, p2 + 1)[lane];
+          g[7] = hi ? inrow(5, p2)[lane] : inrow(7, p2 + 1)[lp];
+          g[8] = hi ? inrow(6, p2)[lane] : inrow(8, p2 + 1)[lm];
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int l = 0; l < 9; ++l) P2[s][l] = g[l].v[s];
+        }
+        site_ring(ring2 + slot5(p2) * 64, rho2 + slot4(p2) * 64, p2, P2);
+      }
+
+      // (d) L2 update of row r - 5 and the store of f*(t+1)
+      const int u2 = r - 5 * dir;
+      if (in_range(u2, yA, yB - 1)) {
+        V *prow[5];
+        V *xrow[3];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) prow[k] = ring2 + slot5(u2 - 2 + k) * 64;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          xrow[k] = a.cross_psi ? ring2 + slot5(u2 - 1 + k) * 64 : rho2 + slot4(u2 - 1 + k) * 64;
+        R fsa[NS][9];
+        update(u2, P2old, prow, xrow, fsa);
+        if (out_lane) {
+          const Rsrc rd = make_rsrc(a.dst, buf_b);
+          const uint32_t rb0 = (uint32_t)u2 * row_b;
+          const uint32_t sto = (uint32_t)xc * site_b;
+          if constexpr (MODE == MODE_BF16SR) {
+            const uint32_t hs = mix32((uint32_t)(u2 * lx + xc) ^ tseed2);
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {
+              const uint32_t rnd = mix32(hs + (uint32_t)l * 0x9e3779b9u);
+              if (NS == 2) C::template bstore2_sr<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l], rnd);
+              else C::template bstore_sr<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], rnd);
+            }
+          } else {
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {
+              if (NS == 2) C::template bstore2<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
+              else C::template bstore<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
+            }
           }
-        } else {
+        }
+      }
+    };
+
+    // Rows: lead row r = rstart + dir i lives in B1[i mod 6]; the pulled f(t+1) of row p2 = r - 3 dir
+    // in B2[i mod 3] (its update, three iterations later, reads B2[(i + 0) mod 3] again).
+    for (int i0 = 0; i0 < niter; i0 += 6) {
 #pragma unroll
-          for (int l = 0; l < 9; ++l) {
-            if (NS == 2) C::template bstore2<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l], fsa[NS - 1][l]);
-            else C::template bstore<STP>(rd, sto, uni(rb0 + (uint32_t)l * plane_b), fsa[0][l]);
-          }
+      for (int k = 0; k < 6; ++k) {
+        if (i0 + k < niter) {
+          iteration(rstart + dir * (i0 + k), B1[(k + 3) % D1], B1[k % D1], B1[(k + 4) % D1], B2[k % D2],
+                    B2[(k + 1) % D2]);
         }
       }
     }
   };
-
-  // Rows: lead row r = rfirst + i lives in B1[i mod 6]; the pulled f(t+1) of row p2 = r - 3
-  // in B2[i mod 3] (its update, three iterations later, reads B2[(i + 0) mod 3] again).
-  for (int i0 = 0; i0 < niter; i0 += 6) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      if (i0 + k < niter) {
-        iteration(rfirst + i0 + k, B1[(k + 3) % D1], B1[k % D1], B1[(k + 4) % D1], B2[k % D2], B2[(k + 1) % D2]);
-      }
-    }
-  }
+  if (seg & 1) march(std::integral_constant<int, -1>{});
+  else march(std::integral_constant<int, 1>{});
 }
 
 }  // namespace lb355
