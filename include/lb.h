@@ -254,9 +254,10 @@ int lb_set_rounding(lb_ctx *ctx, int32_t mode);
    `rows` rows (0: the default, sized so the whole grid is resident), recomputing the overlaps.
    The per-site arithmetic and the rounding of the intermediate to the storage format are those
    of two single steps: results are bitwise identical to LB_TWO_STEP_OFF (also with stochastic
-   BF16 rounding and under graph replay).  LB_TWO_STEP_AUTO (the default) pairs the steps of FP32
-   lattices whose two population buffers exceed the 256 MiB Infinity Cache, where the pairs
-   measured faster.  LB_EINVAL for LB_TWO_STEP_ON with FP64 storage, or rows < 0.  Host call. */
+   BF16 rounding and under graph replay).  LB_TWO_STEP_AUTO (the default) pairs the steps of
+   walled FP32 lattices whose two population buffers exceed the 256 MiB Infinity Cache, where the
+   pairs measured faster.  LB_EINVAL for LB_TWO_STEP_ON with FP64 storage, or rows < 0.  Host
+   call. */
 enum lb_two_step { LB_TWO_STEP_OFF = 0, LB_TWO_STEP_ON = 1, LB_TWO_STEP_AUTO = 2 };
 int lb_set_two_step(lb_ctx *ctx, int32_t enable, int32_t rows);
 

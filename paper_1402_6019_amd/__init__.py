@@ -133,7 +133,7 @@ class Sim:
 
     def set_two_step(self, enable=True, rows=0):
         """Advance plain steps two per launch (FP32 / BF16; bitwise the same results): True, False
-        or "auto" (the default: pairs for FP32 lattices beyond the Infinity Cache)."""
+        or "auto" (the default: pairs for walled FP32 lattices beyond the Infinity Cache)."""
         mode = 2 if enable == "auto" else (1 if enable else 0)
         self._chk(self._lib.lb_set_two_step(self._h, mode, int(rows)))
 

@@ -138,13 +138,14 @@ int grid2(const lb_ctx *c, int *sy_out, int *nseg_out) {
   return nstrip * nseg;
 }
 
-// Whether plain steps go in pairs: forced on or off, or (auto) for FP32 storage whose two
-// population buffers exceed the Infinity Cache, where the pairs' halved HBM traffic outweighs
-// their recomputed overlaps (measured: faster on the 4096 x 512 and 4096 x 1024 channels, slower
-// on the cache-resident 1024^2 lattice and in BF16).
+// Whether plain steps go in pairs: forced on or off, or (auto) for walled FP32 lattices whose
+// two population buffers exceed the Infinity Cache, where the pairs' halved HBM traffic
+// outweighs their recomputed overlaps (measured: 10% faster on the 4096 x 512, 4096 x 1024 and
+// 2048^2 channels; slower on the cache-resident 1024^2 lattice, in BF16, and for periodic
+// lattices, whose instantiation spills registers).
 bool pairs_on(const lb_ctx *c) {
   if (c->two_step == LB_TWO_STEP_AUTO)
-    return c->lat.storage == LB_F32 && streaming_stores(lb_pop_bytes(&c->lat));
+    return c->lat.storage == LB_F32 && c->lat.walls && streaming_stores(lb_pop_bytes(&c->lat));
   return c->two_step == LB_TWO_STEP_ON;
 }
 
