@@ -349,6 +349,21 @@ def batched_sweep(steps, n=64):
     stop.record(b.stream)
     torch.cuda.synchronize()
     ms_eager = start.elapsed_time(stop) / steps
+    # the persistent grid (as many workgroups as are resident at two waves per SIMD, each
+    # taking tiles in rounds) at the tuned strip width and a few segment heights, graph-replayed
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    persistent = {}
+    for sy_p in sorted({sy, 8, 16, 24}):
+        b.set_tile(tx, sy_p, 2 * 4 * n_cu * 64 // tx)
+        b.set_graph(graph)
+        b.step(2 * graph)
+        torch.cuda.synchronize()
+        start.record(b.stream)
+        b.step(steps)
+        stop.record(b.stream)
+        torch.cuda.synchronize()
+        persistent[sy_p] = start.elapsed_time(stop) / steps
+    b.set_tile(tx, sy, grid)
     # the sweep's horizon: 10,000 graph-replayed steps in all, then every instance's health
     # and FP64 species masses against the initial ones
     tot0 = b.totals()
@@ -365,6 +380,9 @@ def batched_sweep(steps, n=64):
                         f"couplings and body force, seed 4, FP32", "sites": sites,
             "ms_per_step": ms, "ms_per_step_eager": ms_eager, "mlups": sites / (ms * 1e-3) / 1e6, "gbs": gbs,
             "frac": gbs / HBM_PEAK_GBS, "graph_steps": graph, "tile": [tx, sy], "grid": grid,
+            "persistent_grid": {"workgroups": 2 * 4 * n_cu * 64 // tx,
+                                "ms_per_step_by_sy": {str(k): v for k, v in persistent.items()},
+                                "best_over_tuned": min(persistent.values()) / ms},
             "default_tile": list(default_tile), "autotune_best_ms": tuned_ms,
             "footprint_mb": 144 * sites / 1e6, "steps_total": steps_done, "all_instances_healthy": True,
             "max_species_mass_drift_fp32": mass_drift}

@@ -30,6 +30,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "lb_internal.hpp"
 #include "lb_tables.hpp"
 
@@ -50,6 +53,44 @@ struct AdjView {
   __device__ R fld(int k, int s, size_t i) const { return fields()[((size_t)k * 2 + s) * n + i]; }
   __device__ R &fldw(int k, int s, size_t i) const { return fields()[((size_t)k * 2 + s) * n + i]; }
 };
+
+// Calls f(std::integral_constant<int, i>{}) for i = 0, 1, ..., N - 1 in order, so that the stencil
+// constants indexed by i are compile-time values inside f.
+template <typename F, int... I>
+__device__ inline void each_index(F &f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ inline void each_index(F &&f) {
+  each_index(f, std::make_integer_sequence<int, N>{});
+}
+
+// C v for a stencil constant C in {-2, ..., 2}, C != 0: +-1 are a copy or a negation.  Terms
+// whose constant is zero are left out of the sums below altogether: they only add a signed
+// zero, which leaves a sum unchanged.
+template <int C, typename R>
+__device__ inline R cmul(R v) {
+  static_assert(C != 0, "zero terms are left out");
+  if constexpr (C == 1) return v;
+  else if constexpr (C == -1) return -v;
+  else return R(C) * v;
+}
+
+// The equilibrium polynomial's derivative along one axis, 3 c + 9 (c_l . u) c - 3 u_a for
+// c = c_l,a, grouped as ((3 c) + (9 (c_l . u)) c) - 3 u_a.
+template <int C, typename R>
+__device__ inline R eq_grad(R cu, R ua) {
+  if constexpr (C == 0) return -(R(3) * ua);
+  else return (R(3 * C) + cmul<C>(R(9) * cu)) - R(3) * ua;
+}
+
+// c . d for a half-link c = (CX, CY), zero components left out.
+template <int CX, int CY, typename R>
+__device__ inline R pair_dot(R dx, R dy) {
+  if constexpr (CX != 0 && CY != 0) return cmul<CX>(dx) + cmul<CY>(dy);
+  else if constexpr (CX != 0) return cmul<CX>(dx);
+  else return cmul<CY>(dy);
+}
 
 template <bool WALLS>
 __device__ inline bool site_of(int x, int y, int lx, int ly, size_t &i) {
@@ -164,15 +205,19 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     jy[s] = v.fld(3, s, i);
     // two-belt sums with the attractive (w) and repulsive (p) shell weights
     R ax = 0, ay = 0, bx = 0, by = 0;
-#pragma unroll
-    for (int h = 0; h < NHALF; ++h) {
-      const R d = psi_at(s, HX[h], HY[h]) - psi_at(s, -HX[h], -HY[h]);
+    each_index<NHALF>([&](auto H) {
+      constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
+      const R d = psi_at(s, hx, hy) - psi_at(s, -hx, -hy);
       const R wq = R(a.w[HQ[h]]), pq = R(a.p[HQ[h]]);
-      ax += wq * R(HX[h]) * d;
-      ay += wq * R(HY[h]) * d;
-      bx += pq * R(HX[h]) * d;
-      by += pq * R(HY[h]) * d;
-    }
+      if constexpr (hx != 0) {
+        ax += cmul<hx>(wq) * d;
+        bx += cmul<hx>(pq) * d;
+      }
+      if constexpr (hy != 0) {
+        ay += cmul<hy>(wq) * d;
+        by += cmul<hy>(pq) * d;
+      }
+    });
     s1x[s] = ax; s1y[s] = ay; s2x[s] = bx; s2y[s] = by;
     Fx[s] = -psi[s] * (R(a.g1[s]) * ax + R(a.g2[s]) * bx);
     Fy[s] = -psi[s] * (R(a.g1[s]) * ay + R(a.g2[s]) * by);
@@ -182,14 +227,13 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     for (int s = 0; s < 2; ++s) {
       const int o = 1 - s;
       R cx = 0, cy = 0;
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const R d = a.cross_psi ? psi_at(o, HX[h], HY[h]) - psi_at(o, -HX[h], -HY[h])
-                                : rho_at(o, HX[h], HY[h]) - rho_at(o, -HX[h], -HY[h]);
+      each_index<4>([&](auto H) {
+        constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
+        const R d = a.cross_psi ? psi_at(o, hx, hy) - psi_at(o, -hx, -hy) : rho_at(o, hx, hy) - rho_at(o, -hx, -hy);
         const R tq = R(a.t[HQ[h]]);
-        cx += tq * R(HX[h]) * d;
-        cy += tq * R(HY[h]) * d;
-      }
+        if constexpr (hx != 0) cx += cmul<hx>(tq) * d;
+        if constexpr (hy != 0) cy += cmul<hy>(tq) * d;
+      });
       xx[s] = cx;
       xy[s] = cy;
       self[s] = a.cross_psi ? psi[s] : rho[s];
@@ -233,35 +277,40 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     const R ux = upx + tau * Fx[s] * ir, uy = upy + tau * Fy[s] * ir;
     const R uu = ux * ux + uy * uy;
     R rb = 0, bx = 0, by = 0;
-#pragma unroll
-    for (int l = 0; l < Q; ++l) {
+    each_index<Q>([&](auto L) {
+      constexpr int l = decltype(L)::value, cx = CXS[l], cy = CYS[l];
       // transposed streaming: the population leaving x along c_l arrives at x + c_l, or
       // bounces back into opp(l) at x when x + c_l is a wall row
       size_t j;
       R al;
-      if (site_of<WALLS>(xs + CXS[l], y + CYS[l], v.lx, v.ly, j))
-        al = lam_next[((size_t)s * Q + l) * v.n + j] + scn[s][ty + 1 + CYS[l]][tx + 1 + CXS[l]];
+      if (site_of<WALLS>(xs + cx, y + cy, v.lx, v.ly, j))
+        al = lam_next[((size_t)s * Q + l) * v.n + j] + scn[s][ty + 1 + cy][tx + 1 + cx];
       else
         al = lam_next[((size_t)s * Q + OPPS[l]) * v.n + i] + scn[s][ty + 1][tx + 1];
-      const R cu = R(CXS[l]) * ux + R(CYS[l]) * uy;
+      R cu = R(0);  // c_l . u
+      if constexpr (cx != 0 && cy != 0) cu = cmul<cx>(ux) + cmul<cy>(uy);
+      else if constexpr (cx != 0) cu = cmul<cx>(ux);
+      else if constexpr (cy != 0) cu = cmul<cy>(uy);
       const R wl = R(WD2Q9[l]);
       const R poly = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;  // f^eq_l / (W_l rho_s)
       const R feq = wl * rho[s] * poly;
-      if (WALLS && ((y == 0 && CYS[l] == -1) || (y == v.ly - 1 && CYS[l] == 1))) {
-        // wall stress: d/dy_l of cW (1/2)(1/lx) (2 c_lx y_l - 6 W_l rho_w c_lx^2 U); the
-        // moving wall's share is constant
-        al += cW * R(CXS[l]) * ilx;
-        // post-collision; x holds the two rows next to the walls, bottom then top
-        const R yl = (R(1) - om) * R(a.x[((size_t)(s * Q + l) * 2 + (y == 0 ? 0 : 1)) * v.lx + xs]) + om * feq;
-        const R mw = R(3) * wl * R(a.rho_w[s]) * R(CXS[l] * CXS[l]) * R(y == 0 ? a.u_wall[0] : a.u_wall[1]);
-        if (live) loss_w += double(cW * (R(CXS[l]) * yl - mw)) / v.lx;
+      if constexpr (WALLS && cy != 0) {
+        if (y == (cy < 0 ? 0 : v.ly - 1)) {
+          // wall stress: d/dy_l of cW (1/2)(1/lx) (2 c_lx y_l - 6 W_l rho_w c_lx^2 U); the
+          // moving wall's share is constant
+          if constexpr (cx != 0) al += cmul<cx>(cW) * ilx;
+          // post-collision; x holds the two rows next to the walls, bottom then top
+          const R yl = (R(1) - om) * R(a.x[((size_t)(s * Q + l) * 2 + (cy < 0 ? 0 : 1)) * v.lx + xs]) + om * feq;
+          const R mw = R(3) * wl * R(a.rho_w[s]) * R(cx * cx) * R(cy < 0 ? a.u_wall[0] : a.u_wall[1]);
+          if (live) loss_w += double(cW * (R(cx) * yl - mw)) / v.lx;
+        }
       }
       lp[s][l] = (R(1) - om) * al;
       rb += om * al * wl * poly;  // omega al f^eq / rho
       const R k = om * al * wl * rho[s];
-      bx += k * (R(3) * R(CXS[l]) + R(9) * cu * R(CXS[l]) - R(3) * ux);
-      by += k * (R(3) * R(CYS[l]) + R(9) * cu * R(CYS[l]) - R(3) * uy);
-    }
+      bx += k * eq_grad<cx>(cu, ux);
+      by += k * eq_grad<cy>(cu, uy);
+    });
     // u_s = u' + tau F_s / rho_s
     ubx += bx;
     uby += by;
@@ -305,9 +354,13 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
   }
   if (live) {
     for (int s = 0; s < NS; ++s) {
-#pragma unroll
-      for (int l = 0; l < Q; ++l)
-        lamout[((size_t)s * Q + l) * v.n + i] = lp[s][l] + rbar[s] + R(CXS[l]) * jbx[s] + R(CYS[l]) * jby[s];
+      each_index<Q>([&](auto L) {
+        constexpr int l = decltype(L)::value, cx = CXS[l], cy = CYS[l];
+        R lam_l = lp[s][l] + rbar[s];
+        if constexpr (cx != 0) lam_l += cmul<cx>(jbx[s]);
+        if constexpr (cy != 0) lam_l += cmul<cy>(jby[s]);
+        lamout[((size_t)s * Q + l) * v.n + i] = lam_l;
+      });
       // what the gather needs of this site: A_s = psi_s Fbar_s, B_s = r_s Fbar_s
       fbar[((size_t)s * 4 + 0) * v.n + i] = psi[s] * fbx[s];
       fbar[((size_t)s * 4 + 1) * v.n + i] = psi[s] * fby[s];
@@ -358,26 +411,26 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) Kq[q] = R(a.K[s][q]);
     R acc = 0;
-#pragma unroll
-    for (int h = 0; h < NHALF; ++h) {
+    each_index<NHALF>([&](auto H) {
+      constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
       R px, py, mx, my;
-      AB(0, s, HX[h], HY[h], px, py);
-      AB(0, s, -HX[h], -HY[h], mx, my);
-      acc += Kq[HQ[h]] * (R(HX[h]) * (px - mx) + R(HY[h]) * (py - my));
-    }
+      AB(0, s, hx, hy, px, py);
+      AB(0, s, -hx, -hy, mx, my);
+      acc += Kq[HQ[h]] * pair_dot<hx, hy>(px - mx, py - my);
+    });
     psib[s] += acc;
   }
   if (NS == 2) {
     for (int s = 0; s < 2; ++s) {  // species s's force depends on species o = 1 - s's field
       const int o = 1 - s;
       R acc = 0;
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      each_index<4>([&](auto H) {
+        constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
         R px, py, mx, my;
-        AB(1, s, HX[h], HY[h], px, py);
-        AB(1, s, -HX[h], -HY[h], mx, my);
-        acc += R(a.t[HQ[h]]) * (R(HX[h]) * (px - mx) + R(HY[h]) * (py - my));
-      }
+        AB(1, s, hx, hy, px, py);
+        AB(1, s, -hx, -hy, mx, my);
+        acc += R(a.t[HQ[h]]) * pair_dot<hx, hy>(px - mx, py - my);
+      });
       // B_s uses species s's own r (r_s Fbar_s); it lands on the other species' field
       if (a.cross_psi) psib[o] += R(a.gab) * acc;
       else rbar[o] += R(a.gab) * acc;
