@@ -121,6 +121,24 @@ hipError_t launch_plain_step(const lb_ctx *c, int from, hipStream_t st, uint32_t
   return launch_step(step_mode(c), c->lat.n_species, c->lat.walls, WHAT_STEP, c->tx, nb, a, st);
 }
 
+// One plain step from buffer `from` that also writes what the adjoint's reverse step reads of
+// that state (as launch_checkpoint_fields_from does): fields (FP64 if fp64) and the FP64
+// populations of the rows next to the walls into dst.  Bitwise the same step and the same
+// fields as the two separate launches, with one pass over the state.
+hipError_t launch_plain_step_fields(const lb_ctx *c, int from, void *dst, void *fields, int fp64, hipStream_t st) {
+  int nseg = 0;
+  const int nb = grid_blocks(c, c->tx, c->sy, &nseg);
+  StepArgs a;
+  fill_step_args(c, a);
+  a.nseg = nseg;
+  a.src = c->pop[from];
+  a.dst = c->pop[from ^ 1];
+  a.out_rho = fields;
+  a.out_u = dst;
+  return launch_step(step_mode(c), c->lat.n_species, c->lat.walls, fp64 ? WHAT_STEP_FIELDS : WHAT_STEP_FIELDS32, c->tx,
+                     nb, a, st);
+}
+
 // Segments of the two-step kernel: rows per segment (the context's choice, or the default that
 // makes the whole grid resident at once) and the grid size.
 int grid2(const lb_ctx *c, int *sy_out, int *nseg_out) {
@@ -898,9 +916,8 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   if (L.all) {
     // forward pass keeping what the reverse step reads of every state: no recompute later
     for (int64_t t = 0; t < T && e == hipSuccess; ++t) {
-      e = launch_checkpoint_fields_from(c, c->cur, ws + L.seg + (size_t)t * L.xw, ws + L.fields + (size_t)t * L.fb,
-                                        fp64, c->stream);
-      if (e == hipSuccess) e = launch_plain_step(c, c->cur, c->stream, (uint32_t)c->t, nullptr);
+      e = launch_plain_step_fields(c, c->cur, ws + L.seg + (size_t)t * L.xw, ws + L.fields + (size_t)t * L.fb, fp64,
+                                   c->stream);
       c->cur ^= 1;
       ++c->t;
     }
@@ -938,10 +955,12 @@ int lb_adjoint(lb_ctx *c, int64_t T, int32_t every, int32_t flags, const double 
   // once per parity as a HIP graph and replayed; a shorter last segment runs eagerly.
   auto recompute = [&](int from, int len, hipStream_t st) -> hipError_t {
     hipError_t er = hipSuccess;
+    // every state but the last is stepped from, which writes its fields on the way; the last
+    // one's fields come from a pass of their own
     for (int jj = 0; jj < len && er == hipSuccess; ++jj) {
-      er = launch_checkpoint_fields_from(c, from ^ (jj & 1), ws + L.seg + (size_t)jj * L.xw,
-                                         ws + L.fields + (size_t)jj * L.fb, fp64, st);
-      if (er == hipSuccess && jj + 1 < len) er = launch_plain_step(c, from ^ (jj & 1), st, 0u, nullptr);
+      char *xw = ws + L.seg + (size_t)jj * L.xw, *fields = ws + L.fields + (size_t)jj * L.fb;
+      if (jj + 1 < len) er = launch_plain_step_fields(c, from ^ (jj & 1), xw, fields, fp64, st);
+      else er = launch_checkpoint_fields_from(c, from ^ (jj & 1), xw, fields, fp64, st);
     }
     return er;
   };

@@ -18,7 +18,12 @@ enum StepWhat {
   WHAT_OBSERVE = 3,      // partial sums of the current state, store nothing
   WHAT_PROFILE = 4,      // per-row sums of the current state (velocity, stress parts), store nothing
   WHAT_STRESS = 5,       // write the site pressure tensor of the current state, store nothing
-  WHAT_STEP_ACCUM = 6    // step, adding wall stress and health counts to per-workgroup FP64 running sums
+  WHAT_STEP_ACCUM = 6,   // step, adding wall stress and health counts to per-workgroup FP64 running sums
+  // step, also writing what the adjoint's reverse step reads of the state it steps from: rho,
+  // psi, j of every site (out_rho, [4][2][ly][lx], FP64 / FP32) and the canonical FP64
+  // populations of the rows next to the walls (out_u, [s][l][2][lx])
+  WHAT_STEP_FIELDS = 7,
+  WHAT_STEP_FIELDS32 = 8
 };
 
 // Running sums of WHAT_STEP_ACCUM, per workgroup row.

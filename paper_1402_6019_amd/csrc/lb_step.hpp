@@ -372,9 +372,10 @@ __device__ inline T wave_sum(T v) {
 
 // One tile: strip `strip` (tx = blockDim.x columns) and segment `seg` (a.sy rows) of the
 // lattice described by a, read from src and written to dst.  part: this tile's row of
-// reduction partials; out0: the output of a pass that stores nothing (WHAT_MOMENTS: rho;
+// reduction partials; out0: the output of a pass beside the populations (WHAT_STEP_FIELDS*:
+// the reverse step's fields) or of one that stores nothing (WHAT_MOMENTS: rho;
 // WHAT_STRESS: the pressure tensor; WHAT_PROFILE: the [64-column block][row][PROF_N] sums);
-// out_u: the WHAT_MOMENTS velocity.
+// out_u: the WHAT_MOMENTS velocity, or the WHAT_STEP_FIELDS* wall-row populations.
 template <int MODE, int NS, bool WALLS, int WHAT, int STP>
 __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const src, void *const dst, const int strip,
                                          const int seg, double *const part, void *const out0,
@@ -384,7 +385,8 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
   using S = typename C::S;
   using L = typename C::L;
   using V = Vec<R, NS>;
-  constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_ACCUM);
+  constexpr bool FIELDS = (WHAT == WHAT_STEP_FIELDS || WHAT == WHAT_STEP_FIELDS32);
+  constexpr bool STORE = (WHAT == WHAT_STEP || WHAT == WHAT_STEP_ACCUM || FIELDS);
   constexpr bool REDUCE = (WHAT == WHAT_OBSERVE || WHAT == WHAT_STEP_ACCUM);
   // WHAT_STEP_ACCUM keeps only what stepping averages (wall stress) and the health count,
   // added to this workgroup's own row of running sums; the second pass runs when the host
@@ -635,6 +637,35 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int l = 0; l < 9; ++l) f[s][l] = C::dec(fraw[s][l], s);
+    if constexpr (FIELDS) {
+      // the reverse step's inputs, from the pulled (pre-collision) populations of this row, as
+      // a checkpoint of the state would give them: f_l = d_l + W_l rho_ref in the storage's
+      // arithmetic, then rho, j summed in l order and psi in the adjoint's precision RA
+      using RA = typename std::conditional<WHAT == WHAT_STEP_FIELDS, double, float>::type;
+      if (col_ok) {
+        const size_t site = (size_t)y * lx + xc, nsite = (size_t)lx * ly;
+        RA *fl = static_cast<RA *>(out0);
+        double *xw = static_cast<double *>(out_u);
+        const bool wall_row = WALLS && (y == 0 || y == ly - 1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          RA r = 0, px = 0, py = 0;
+#pragma unroll
+          for (int l = 0; l < 9; ++l) {
+            const double fv = double(f[s][l] + R(WD2Q9[l] * a.rho_ref[s]));
+            if (wall_row) xw[((size_t)(s * 9 + l) * 2 + (y == 0 ? 0 : 1)) * lx + xc] = fv;
+            const RA g = RA(fv);
+            r += g;
+            px += RA(CXS[l]) * g;
+            py += RA(CYS[l]) * g;
+          }
+          fl[(size_t)(0 * 2 + s) * nsite + site] = r;
+          fl[(size_t)(1 * 2 + s) * nsite + site] = RA(a.psi0) * (RA(1) - exp(-r * RA(a.irho0)));
+          fl[(size_t)(2 * 2 + s) * nsite + site] = px;
+          fl[(size_t)(3 * 2 + s) * nsite + site] = py;
+        }
+      }
+    }
     R drho[NS], rho[NS], jx[NS], jy[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -1105,6 +1136,12 @@ static hipError_t launch_step_t(int what, int tx, int nb, const StepArgs &a, hip
       break;
     case WHAT_STRESS:
       hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STRESS>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_STEP_FIELDS:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_FIELDS>), dim3(nb), dim3(tx), lds, st, a);
+      break;
+    case WHAT_STEP_FIELDS32:
+      hipLaunchKernelGGL((step_kernel<MODE, NS, WALLS, WHAT_STEP_FIELDS32>), dim3(nb), dim3(tx), lds, st, a);
       break;
     default: return hipErrorInvalidValue;
   }
