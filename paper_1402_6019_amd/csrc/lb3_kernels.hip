@@ -576,7 +576,6 @@ __device__ inline size_t pop3_index(int s, int l, int z, int y, int x, int ly, i
 template <int MODE, bool WALLS>
 __global__ void init3_kernel(Lb3Layout a) {  // in: rho [ns][lz][ly][lx] FP64; state at rest
   using C = Codec<MODE>;
-  using R = typename C::R;
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= a.lx) return;
@@ -593,14 +592,13 @@ __global__ void init3_kernel(Lb3Layout a) {  // in: rho [ns][lz][ly][lx] FP64; s
       }
       const double W = l == 0 ? 1.0 / 3.0 : (l <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
       const double v = W * rho[s * nsite + ((size_t)wz * a.ly + wy) * a.lx + wx];
-      C::store(out + pop3_index(s, l, z, y, x, a.ly, a.pitch, a.ns), R(v), R(W * a.rho_ref[s]));
+      C::store(out + pop3_index(s, l, z, y, x, a.ly, a.pitch, a.ns), v, W * a.rho_ref[s]);
     }
 }
 
 template <int MODE, bool WALLS>
 __global__ void restore3_kernel(Lb3Layout a) {  // in: canonical f (FP64)
   using C = Codec<MODE>;
-  using R = typename C::R;
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= a.lx) return;
@@ -620,14 +618,13 @@ __global__ void restore3_kernel(Lb3Layout a) {  // in: canonical f (FP64)
       }
       const double W = l == 0 ? 1.0 / 3.0 : (l <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
       const double v = f[((size_t)s * 19 + lsrc) * nsite + ((size_t)vz * a.ly + vy) * a.lx + vx];
-      C::store(out + pop3_index(s, l, z, y, x, a.ly, a.pitch, a.ns), R(v), R(W * a.rho_ref[s]));
+      C::store(out + pop3_index(s, l, z, y, x, a.ly, a.pitch, a.ns), v, W * a.rho_ref[s]);
     }
 }
 
 template <int MODE, bool WALLS>
 __global__ void checkpoint3_kernel(Lb3Layout a) {  // out: canonical f (FP64)
   using C = Codec<MODE>;
-  using R = typename C::R;
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= a.lx) return;
@@ -646,7 +643,7 @@ __global__ void checkpoint3_kernel(Lb3Layout a) {  // out: canonical f (FP64)
         wx = d3::wrap(wx, a.lx); wy = d3::wrap(wy, a.ly); wz = d3::wrap(wz, a.lz);
       }
       const double W = l == 0 ? 1.0 / 3.0 : (l <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
-      const R v = C::load(g + pop3_index(s, lsrc, wz, wy, wx, a.ly, a.pitch, a.ns), R(W * a.rho_ref[s]));
+      const double v = C::load(g + pop3_index(s, lsrc, wz, wy, wx, a.ly, a.pitch, a.ns), W * a.rho_ref[s]);
       f[((size_t)s * 19 + l) * nsite + ((size_t)z * a.ly + y) * a.lx + x] = double(v);
     }
 }

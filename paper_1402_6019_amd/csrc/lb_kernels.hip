@@ -123,7 +123,6 @@ template <int MODE, bool WALLS>
 __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
   using C = Codec<MODE>;
   using S = typename C::S;
-  using R = typename C::R;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
   const double *rho = static_cast<const double *>(a.in);
@@ -141,8 +140,7 @@ __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
         zy = wrapi(zy, a.ly);
       }
       const double v = WD2Q9[l] * rho[s * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), R(v),
-               R(WD2Q9[l] * a.rho_ref[s]));
+      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), v, WD2Q9[l] * a.rho_ref[s]);
     }
 }
 
@@ -150,7 +148,6 @@ template <int MODE, bool WALLS>
 __global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][lx] (FP64)
   using C = Codec<MODE>;
   using S = typename C::S;
-  using R = typename C::R;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
   const double *f = static_cast<const double *>(a.in);
@@ -169,8 +166,7 @@ __global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][l
         zy = wrapi(zy, a.ly);
       }
       const double v = f[(size_t)(s * 9 + lsrc) * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), R(v),
-               R(WD2Q9[l] * a.rho_ref[s]));
+      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), v, WD2Q9[l] * a.rho_ref[s]);
     }
 }
 
@@ -178,7 +174,6 @@ template <int MODE, bool WALLS>
 __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][ly][lx] (FP64)
   using C = Codec<MODE>;
   using S = typename C::S;
-  using R = typename C::R;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
   const S *in = static_cast<const S *>(a.in);
@@ -196,9 +191,8 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns),
-                          R(WD2Q9[lsrc] * a.rho_ref[s]));
-      f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] = double(v);
+      f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] =
+          C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), WD2Q9[lsrc] * a.rho_ref[s]);
     }
 }
 
@@ -211,7 +205,6 @@ template <int MODE, bool WALLS, typename RA>
 __global__ void checkpoint_fields_kernel(LayoutArgs a) {
   using C = Codec<MODE>;
   using S = typename C::S;
-  using R = typename C::R;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
   const S *in = static_cast<const S *>(a.in);
@@ -235,8 +228,7 @@ __global__ void checkpoint_fields_kernel(LayoutArgs a) {
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const R v = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), R(WD2Q9[lsrc] * a.rho_ref[s]));
-      const double fv = double(v);
+      const double fv = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), WD2Q9[lsrc] * a.rho_ref[s]);
       if (wall_row) f[((size_t)(s * 9 + l) * 2 + (y == 0 ? 0 : 1)) * a.lx + x] = fv;
       const RA g = RA(fv);
       r += g;

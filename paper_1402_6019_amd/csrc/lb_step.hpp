@@ -86,9 +86,11 @@ constexpr int kStoreWriteThrough = 16;      // SC1
 constexpr int kStoreStreaming = 16 | 2;     // SC1 | NT
 
 // Every storage mode holds deviations d_l = f_l - W_l rho_ref from the rest equilibrium of a
-// per-species reference density.  load/store (layout kernels) convert to and from f; the
-// step works on deviations directly (bload/bstore), which costs nothing and keeps the
-// rounding of each stored value relative to |d_l| instead of |f_l|.
+// per-species reference density.  load/store (layout kernels) convert to and from the canonical
+// FP64 f with wref = W_l rho_ref in FP64 arithmetic, so a checkpoint (f = d + wref) restores to
+// the stored d exactly whenever the sum is exact in FP64 (for FP32, |d| >= 2^-29 |wref|; BF16
+// always); the step works on deviations directly (bload/bstore), which costs nothing and keeps
+// the rounding of each stored value relative to |d_l| instead of |f_l|.
 // L is the type a pulled population is held in between its load and its use (the register
 // FIFO of the step); dec(v, s) turns it into species s's value in the arithmetic type.
 template <> struct Codec<MODE_F64> {
@@ -96,8 +98,8 @@ template <> struct Codec<MODE_F64> {
   using R = double;
   using L = double;
   __device__ static R dec(L v, int) { return v; }
-  __device__ static R load(const S *p, R wref) { return *p + wref; }
-  __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
+  __device__ static double load(const S *p, double wref) { return *p + wref; }
+  __device__ static void store(S *p, double v, double wref) { *p = v - wref; }
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
@@ -125,8 +127,8 @@ template <> struct Codec<MODE_F32> {
   using R = float;
   using L = float;
   __device__ static R dec(L v, int) { return v; }
-  __device__ static R load(const S *p, R wref) { return *p + wref; }
-  __device__ static void store(S *p, R v, R wref) { *p = v - wref; }
+  __device__ static double load(const S *p, double wref) { return double(*p) + wref; }
+  __device__ static void store(S *p, double v, double wref) { *p = float(v - wref); }
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
@@ -177,8 +179,8 @@ template <> struct Codec<MODE_BF16> {
   __device__ static R decode(uint32_t h) { return __uint_as_float(h << 16); }
   // the hardware conversion (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
   __device__ static uint16_t encode(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-  __device__ static R load(const S *p, R wref) { return decode(*p) + wref; }
-  __device__ static void store(S *p, R v, R wref) { *p = encode(v - wref); }
+  __device__ static double load(const S *p, double wref) { return double(decode(*p)) + wref; }
+  __device__ static void store(S *p, double v, double wref) { *p = encode(float(v - wref)); }
   __device__ static L bload(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
   }
@@ -639,8 +641,8 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
       for (int l = 0; l < 9; ++l) f[s][l] = C::dec(fraw[s][l], s);
     if constexpr (FIELDS) {
       // the reverse step's inputs, from the pulled (pre-collision) populations of this row, as
-      // a checkpoint of the state would give them: f_l = d_l + W_l rho_ref in the storage's
-      // arithmetic, then rho, j summed in l order and psi in the adjoint's precision RA
+      // a checkpoint of the state would give them: f_l = d_l + W_l rho_ref in FP64, then rho,
+      // j summed in l order and psi in the adjoint's precision RA
       using RA = typename std::conditional<WHAT == WHAT_STEP_FIELDS, double, float>::type;
       if (col_ok) {
         const size_t site = (size_t)y * lx + xc, nsite = (size_t)lx * ly;
@@ -652,7 +654,7 @@ __device__ __forceinline__ void run_tile(const StepArgs &a, const void *const sr
           RA r = 0, px = 0, py = 0;
 #pragma unroll
           for (int l = 0; l < 9; ++l) {
-            const double fv = double(f[s][l] + R(WD2Q9[l] * a.rho_ref[s]));
+            const double fv = double(f[s][l]) + WD2Q9[l] * a.rho_ref[s];
             if (wall_row) xw[((size_t)(s * 9 + l) * 2 + (y == 0 ? 0 : 1)) * lx + xc] = fv;
             const RA g = RA(fv);
             r += g;

@@ -46,12 +46,11 @@ def test_adjoint_fp64_matches_oracle_complex_step_channel(every):
 @pytest.mark.parametrize("storage,fp64_reverse", [("f64", False), ("f32", True), ("f32", False)])
 def test_adjoint_keeping_every_state_matches_the_checkpointed_sweep(storage, fp64_reverse):
     """every = 1 (the forward pass keeps what the reverse step reads of every state) and the
-    checkpointed sweeps (every = 7, every = sqrt(T)) run the same reverse steps.  With FP64
-    storage the recomputed states are bitwise the forward's, so loss and gradient agree
-    exactly.  With FP32 storage a checkpoint holds the populations f = d + W rho_ref, and the
-    restore rounds f - W rho_ref back to FP32: the recomputed states differ from the
-    forward's in the last bits of the smaller deviations, and loss and gradient agree to
-    1e-5.  The state after the call is bitwise that of plain stepping in every case."""
+    checkpointed sweeps (every = 7, every = sqrt(T)) run the same reverse steps on the same
+    states: a checkpoint restores to bitwise the stored state (f = d + W rho_ref formed and
+    undone in FP64), so the recomputed states are the forward's, and loss and gradient agree
+    exactly in every storage mode.  The state after the call is bitwise that of plain
+    stepping."""
     c = channel(storage=storage)
     T, lw = 45, (1.0, 0.3)
     res = {}
@@ -61,12 +60,8 @@ def test_adjoint_keeping_every_state_matches_the_checkpointed_sweep(storage, fp6
         res[every] = (loss, g7, sim.checkpoint().cpu().numpy())
         sim.close()
     for every in (7, 0):
-        if storage == "f64":
-            assert res[every][0] == res[1][0]
-            assert np.array_equal(res[every][1], res[1][1])
-        else:
-            assert res[every][0] == pytest.approx(res[1][0], rel=1e-5)
-            np.testing.assert_allclose(res[every][1], res[1][1], rtol=1e-5, atol=1e-9 * np.abs(res[1][1]).max())
+        assert res[every][0] == res[1][0]
+        assert np.array_equal(res[every][1], res[1][1])
         assert np.array_equal(res[every][2], res[1][2])
 
 

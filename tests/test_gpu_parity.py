@@ -184,8 +184,12 @@ def test_store_policies_bitwise(walls, storage):
     sim.close()
 
 
-def test_checkpoint_restore_roundtrip():
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16dev"])
+def test_checkpoint_restore_roundtrip(storage):
+    """A checkpoint (canonical FP64 f = d + W rho_ref) restores to bitwise the stored state in
+    every storage mode, so stepping on from a restore repeats the original run bit for bit."""
     c = emulsion_case(70, 50, walls=True, fraction=0.6, seed=4, rmin=5, rmax=9)
+    c["storage"] = storage
     sim = make_sim(c)
     sim.step(7)
     f = sim.checkpoint()
