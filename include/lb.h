@@ -370,7 +370,10 @@ int lb_disjoining_pressure(const double *h, const double *gamma_f, int32_t n, do
  * The forward pass keeps an FP64 checkpoint of the populations every `every` steps
  * (every <= 0: ceil(sqrt(T))); the reverse sweep recomputes each segment's states from its
  * checkpoint and runs the hand-written reverse step (FP64 for LB_F64 contexts or with
- * flags & LB_ADJ_FP64, FP32 otherwise).  every = 1 keeps instead what the reverse step reads
+ * flags & LB_ADJ_FP64, FP32 otherwise).  With several segments the reverse steps run on a
+ * second stream of the library's own, created and destroyed by the call, one segment behind
+ * the recompute on the context's stream (two segment buffers in the workspace); the result
+ * does not depend on the overlap.  every = 1 keeps instead what the reverse step reads
  * of every state (moments and pseudopotential of every site, populations of the two rows
  * next to the walls): no recompute, at about T * 64 (FP64 reverse) or T * 32 (FP32) bytes per
  * site of workspace.  workspace: device buffer of

@@ -92,15 +92,6 @@ __device__ inline R pair_dot(R dx, R dy) {
   else return cmul<CY>(dy);
 }
 
-template <bool WALLS>
-__device__ inline bool site_of(int x, int y, int lx, int ly, size_t &i) {
-  if (WALLS && (y < 0 || y >= ly)) return false;
-  const int xi = wrapx(x, lx);
-  const int yi = WALLS ? y : wrapx(y, ly);
-  i = (size_t)yi * lx + xi;
-  return true;
-}
-
 template <typename T>
 __device__ inline T block_sum(T v, T *sm) {
   // wave reduction, then across the waves of the block (sm: one slot per wave)
@@ -153,38 +144,65 @@ __device__ inline void tile_accumulate(const double (&vals)[ADJ_N], double (*sm)
   }
 }
 
+// The term of lambda common to every l at one site: the force's dependence on the
+// neighbours' psi (and rho), gathered with the forward stencil from A_s = psi_s Fbar_s and
+// B_s = r_s Fbar_s.  ab(which, s, dx, dy, bx, by) gives A_s (which = 0) or B_s (which = 1) at
+// the neighbour (dx, dy), zero off the lattice; rho holds the site's densities.
+template <typename R, int NS, typename AB>
+__device__ inline void gather_corr(const AdjArgs &a, const AB &ab, const R (&rho)[2], R (&corr)[2]) {
+  R psib[2] = {0, 0}, rbar[2] = {0, 0};
+  for (int s = 0; s < NS; ++s) {
+    R Kq[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Kq[q] = R(a.K[s][q]);
+    R acc = 0;
+    each_index<NHALF>([&](auto H) {
+      constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
+      R px, py, mx, my;
+      ab(0, s, hx, hy, px, py);
+      ab(0, s, -hx, -hy, mx, my);
+      acc += Kq[HQ[h]] * pair_dot<hx, hy>(px - mx, py - my);
+    });
+    psib[s] += acc;
+  }
+  if (NS == 2) {
+    for (int s = 0; s < 2; ++s) {  // species s's force depends on species o = 1 - s's field
+      const int o = 1 - s;
+      R acc = 0;
+      each_index<4>([&](auto H) {
+        constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
+        R px, py, mx, my;
+        ab(1, s, hx, hy, px, py);
+        ab(1, s, -hx, -hy, mx, my);
+        acc += R(a.t[HQ[h]]) * pair_dot<hx, hy>(px - mx, py - my);
+      });
+      // B_s uses species s's own r (r_s Fbar_s); it lands on the other species' field
+      if (a.cross_psi) psib[o] += R(a.gab) * acc;
+      else rbar[o] += R(a.gab) * acc;
+    }
+  }
+  for (int s = 0; s < NS; ++s) corr[s] = rbar[s] + psib[s] * R(a.psi0) * R(a.irho0) * exp(-rho[s] * R(a.irho0));
+}
+
 // Local part of the reverse step: force recompute, transposed streaming, the collision's
 // and velocity shift's adjoints; writes lam (the local part of lambda(t)), Fbar and per-tile
 // partial sums.
-template <typename R, int NS, bool WALLS>
+//
+// GIN: the common term of lambda(t+1) is not read from memory but gathered here, for the tile
+// plus a halo of one, from A_s and B_s of step t + 1 (tile plus a halo of three) and the
+// densities of state t + 1: the separate gather of step t + 1 is not needed.
+template <typename R, int NS, bool WALLS, bool GIN>
 __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
   AdjView<R> v(a);
+  constexpr int GX = ATX + 6, GY = ATY + 6;  // A_s, B_s of step t + 1 staged with a halo of three
   __shared__ R sps[2][AHY][AHX];  // psi of the forward state, tile + halo
   __shared__ R srh[2][AHY][AHX];  // rho
   __shared__ R scn[2][ATY + 2][ATX + 2];  // corr of lambda(t+1), tile + halo of one
+  __shared__ R sab[GIN ? 2 : 1][GIN ? 4 : 1][GIN ? GY : 1][GIN ? GX : 1];
   __shared__ double sm[4][ADJ_N];
   const R *corr_next = static_cast<const R *>(a.corr_next);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = blockIdx.x * ATX, y0 = blockIdx.y * ATY;
-  for (int k = threadIdx.x; k < AHX * AHY; k += 256) {
-    const int hx = k % AHX, hy = k / AHX;
-    size_t j = 0;
-    const bool in = stage_site<WALLS>(x0 - 2 + hx, y0 - 2 + hy, v.lx, v.ly, j);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      sps[s][hy][hx] = in ? v.fld(1, s, j) : R(a.psi_w[s]);
-      srh[s][hy][hx] = in ? v.fld(0, s, j) : R(a.rho_w[s]);
-    }
-  }
-  for (int k = threadIdx.x; k < (ATX + 2) * (ATY + 2); k += 256) {
-    const int hx = k % (ATX + 2), hy = k / (ATX + 2);
-    size_t j = 0;
-    const bool in = stage_site<WALLS>(x0 - 1 + hx, y0 - 1 + hy, v.lx, v.ly, j);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) scn[s][hy][hx] = in ? corr_next[(size_t)s * v.n + j] : R(0);
-  }
-  __syncthreads();
-
   const bool live = x0 + tx < v.lx && y0 + ty < v.ly;
   // memory accesses of lanes past the lattice's end use its last site (results discarded)
   const int xs = min(x0 + tx, v.lx - 1), y = min(y0 + ty, v.ly - 1);
@@ -193,16 +211,142 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
   R *lamout = static_cast<R *>(a.lam);
   R *fbar = static_cast<R *>(a.fbar);
 
+  // Every load of the pass is issued before its first use, with no branch between the
+  // requests, so that they are in flight together (a wave holds one tile row and has nothing
+  // else to overlap them with).  First what the site reads outside the staged neighbourhood:
+  // j_s, and lambda(t+1) at the transposed-streaming sources.  The population leaving x along
+  // c_l arrives at x + c_l, or bounces back into opp(l) at x when x + c_l is a wall row; the
+  // bounce is folded into the address (y is the same across a wave, so is the bounce).
+  R rho[2], jx[2], jy[2], psi[2], Fx[2], Fy[2];
+  R lsrc[2][Q];
+  for (int s = 0; s < NS; ++s) {
+    jx[s] = v.fld(2, s, i);
+    jy[s] = v.fld(3, s, i);
+  }
+  each_index<Q>([&](auto L) {
+    constexpr int l = decltype(L)::value, cx = CXS[l], cy = CYS[l];
+    const int yn = y + cy;
+    const bool bounce = WALLS && cy != 0 && (yn < 0 || yn >= v.ly);
+    const size_t j = bounce ? i : (size_t)(WALLS ? yn : wrapx(yn, v.ly)) * v.lx + wrapx(xs + cx, v.lx);
+    const int pl = bounce ? OPPS[l] : l;
+    for (int s = 0; s < NS; ++s) lsrc[s][l] = lam_next[((size_t)s * Q + pl) * v.n + j];
+  });
+  // and, on the two wall rows, their pre-collision populations (the wall stress's source)
+  R xwr[2][Q];
+  if constexpr (WALLS) {
+    if (y == 0 || y == v.ly - 1) {
+      each_index<Q>([&](auto L) {
+        constexpr int l = decltype(L)::value, cy = CYS[l];
+        if constexpr (cy != 0)
+          for (int s = 0; s < NS; ++s) xwr[s][l] = R(a.x[((size_t)(s * Q + l) * 2 + (cy < 0 ? 0 : 1)) * v.lx + xs]);
+      });
+    }
+  }
+  // Then the staging: psi and rho of the tile plus a halo of two, the common term of
+  // lambda(t+1) plus a halo of one.  Points that are not sites (past a wall, or past the end of
+  // the staging range) load site 0 and store the wall value or zero instead.
+  constexpr int NPS = (AHX * AHY + 255) / 256, NCN = ((ATX + 2) * (ATY + 2) + 255) / 256;
+  R vps[NPS][2], vrh[NPS][2], vcn[NCN][2];
+  bool inps[NPS], incn[NCN];
+#pragma unroll
+  for (int it = 0; it < NPS; ++it) {
+    const int k = threadIdx.x + it * 256, hx = k % AHX, hy = k / AHX;
+    size_t j = 0;
+    inps[it] = k < AHX * AHY && stage_site<WALLS>(x0 - 2 + hx, y0 - 2 + hy, v.lx, v.ly, j);
+    if (!inps[it]) j = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      vps[it][s] = v.fld(1, s, j);
+      vrh[it][s] = v.fld(0, s, j);
+    }
+  }
+  // with GIN: A_s, B_s of step t + 1 (tile + halo of three), and in vcn the densities of state
+  // t + 1 at the points where the common term is gathered; else the common term itself
+  constexpr int NAB = GIN ? (GX * GY + 255) / 256 : 1;
+  R vab[NAB][2][4];
+  bool inab[NAB];
+  const R *fbar_next = static_cast<const R *>(a.fbar_next);
+  const R *rho_next = static_cast<const R *>(a.fields_next);  // field 0 (rho) of state t + 1
+  if constexpr (GIN) {
+#pragma unroll
+    for (int it = 0; it < NAB; ++it) {
+      const int k = threadIdx.x + it * 256, hx = k % GX, hy = k / GX;
+      size_t j = 0;
+      inab[it] = k < GX * GY && stage_site<WALLS>(x0 - 3 + hx, y0 - 3 + hy, v.lx, v.ly, j);
+      if (!inab[it]) j = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vab[it][s][c] = fbar_next[((size_t)s * 4 + c) * v.n + j];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NCN; ++it) {
+    const int k = threadIdx.x + it * 256, hx = k % (ATX + 2), hy = k / (ATX + 2);
+    size_t j = 0;
+    incn[it] = k < (ATX + 2) * (ATY + 2) && stage_site<WALLS>(x0 - 1 + hx, y0 - 1 + hy, v.lx, v.ly, j);
+    if (!incn[it]) j = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) vcn[it][s] = GIN ? rho_next[(size_t)s * v.n + j] : corr_next[(size_t)s * v.n + j];
+  }
+#pragma unroll
+  for (int it = 0; it < NPS; ++it) {
+    const int k = threadIdx.x + it * 256, hx = k % AHX, hy = k / AHX;
+    if (k < AHX * AHY) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        sps[s][hy][hx] = inps[it] ? vps[it][s] : R(a.psi_w[s]);
+        srh[s][hy][hx] = inps[it] ? vrh[it][s] : R(a.rho_w[s]);
+      }
+    }
+  }
+  if constexpr (GIN) {
+#pragma unroll
+    for (int it = 0; it < NAB; ++it) {
+      const int k = threadIdx.x + it * 256, hx = k % GX, hy = k / GX;
+      if (k < GX * GY) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) sab[s][c][hy][hx] = inab[it] ? vab[it][s][c] : R(0);
+      }
+    }
+    __syncthreads();
+    // the common term of lambda(t+1) at the tile + halo of one, exactly as the gather pass
+    // computes it at those sites (zero at points that are not sites)
+#pragma unroll
+    for (int it = 0; it < NCN; ++it) {
+      const int k = threadIdx.x + it * 256, hx = k % (ATX + 2), hy = k / (ATX + 2);
+      if (k < (ATX + 2) * (ATY + 2)) {
+        auto ab = [&](int which, int s, int dx, int dy, R &bx, R &by) {
+          bx = sab[s][2 * which + 0][hy + 2 + dy][hx + 2 + dx];
+          by = sab[s][2 * which + 1][hy + 2 + dy][hx + 2 + dx];
+        };
+        R rn[2] = {vcn[it][0], NS == 2 ? vcn[it][NS - 1] : R(0)}, cn[2];
+        gather_corr<R, NS>(a, ab, rn, cn);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) scn[s][hy][hx] = incn[it] ? cn[s] : R(0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < NCN; ++it) {
+      const int k = threadIdx.x + it * 256, hx = k % (ATX + 2), hy = k / (ATX + 2);
+      if (k < (ATX + 2) * (ATY + 2)) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) scn[s][hy][hx] = incn[it] ? vcn[it][s] : R(0);
+      }
+    }
+  }
+  __syncthreads();
+
   auto psi_at = [&](int s, int dx, int dy) -> R { return sps[s][ty + 2 + dy][tx + 2 + dx]; };
   auto rho_at = [&](int s, int dx, int dy) -> R { return srh[s][ty + 2 + dy][tx + 2 + dx]; };
 
-  R rho[2], jx[2], jy[2], psi[2], Fx[2], Fy[2];
   R s1x[2], s1y[2], s2x[2], s2y[2], xx[2], xy[2], self[2];
   for (int s = 0; s < NS; ++s) {
     rho[s] = rho_at(s, 0, 0);
     psi[s] = psi_at(s, 0, 0);
-    jx[s] = v.fld(2, s, i);
-    jy[s] = v.fld(3, s, i);
     // two-belt sums with the attractive (w) and repulsive (p) shell weights
     R ax = 0, ay = 0, bx = 0, by = 0;
     each_index<NHALF>([&](auto H) {
@@ -279,14 +423,9 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     R rb = 0, bx = 0, by = 0;
     each_index<Q>([&](auto L) {
       constexpr int l = decltype(L)::value, cx = CXS[l], cy = CYS[l];
-      // transposed streaming: the population leaving x along c_l arrives at x + c_l, or
-      // bounces back into opp(l) at x when x + c_l is a wall row
-      size_t j;
-      R al;
-      if (site_of<WALLS>(xs + cx, y + cy, v.lx, v.ly, j))
-        al = lam_next[((size_t)s * Q + l) * v.n + j] + scn[s][ty + 1 + cy][tx + 1 + cx];
-      else
-        al = lam_next[((size_t)s * Q + OPPS[l]) * v.n + i] + scn[s][ty + 1][tx + 1];
+      // lambda(t+1) at the transposed-streaming source (loaded above) and its common term
+      const bool bounce = WALLS && cy != 0 && (y + cy < 0 || y + cy >= v.ly);
+      R al = lsrc[s][l] + (bounce ? scn[s][ty + 1][tx + 1] : scn[s][ty + 1 + cy][tx + 1 + cx]);
       R cu = R(0);  // c_l . u
       if constexpr (cx != 0 && cy != 0) cu = cmul<cx>(ux) + cmul<cy>(uy);
       else if constexpr (cx != 0) cu = cmul<cx>(ux);
@@ -299,8 +438,8 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
           // wall stress: d/dy_l of cW (1/2)(1/lx) (2 c_lx y_l - 6 W_l rho_w c_lx^2 U); the
           // moving wall's share is constant
           if constexpr (cx != 0) al += cmul<cx>(cW) * ilx;
-          // post-collision; x holds the two rows next to the walls, bottom then top
-          const R yl = (R(1) - om) * R(a.x[((size_t)(s * Q + l) * 2 + (cy < 0 ? 0 : 1)) * v.lx + xs]) + om * feq;
+          // post-collision population leaving the wall row
+          const R yl = (R(1) - om) * xwr[s][l] + om * feq;
           const R mw = R(3) * wl * R(a.rho_w[s]) * R(cx * cx) * R(cy < 0 ? a.u_wall[0] : a.u_wall[1]);
           if (live) loss_w += double(cW * (R(cx) * yl - mw)) / v.lx;
         }
@@ -386,60 +525,48 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = blockIdx.x * ATX, y0 = blockIdx.y * ATY;
   const R *fbar = static_cast<const R *>(a.fbar);
-  for (int k = threadIdx.x; k < AHX * AHY; k += 256) {
-    const int hx = k % AHX, hy = k / AHX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool live = x < v.lx && y < v.ly;
+  const size_t i = live ? (size_t)y * v.lx + x : 0;
+  // every load is issued before the barrier, together: rho_s of this site, then the staged
+  // values (points that are not sites load site 0 and store zero)
+  R rho[2];
+  for (int s = 0; s < NS; ++s) rho[s] = v.fld(0, s, i);
+  constexpr int NST = (AHX * AHY + 255) / 256;
+  R vab[NST][2][4];
+  bool in[NST];
+#pragma unroll
+  for (int it = 0; it < NST; ++it) {
+    const int k = threadIdx.x + it * 256, hx = k % AHX, hy = k / AHX;
     size_t j = 0;
-    const bool in = stage_site<WALLS>(x0 - 2 + hx, y0 - 2 + hy, v.lx, v.ly, j);
+    in[it] = k < AHX * AHY && stage_site<WALLS>(x0 - 2 + hx, y0 - 2 + hy, v.lx, v.ly, j);
+    if (!in[it]) j = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) sab[s][c][hy][hx] = in ? fbar[((size_t)s * 4 + c) * v.n + j] : R(0);
+      for (int c = 0; c < 4; ++c) vab[it][s][c] = fbar[((size_t)s * 4 + c) * v.n + j];
+  }
+#pragma unroll
+  for (int it = 0; it < NST; ++it) {
+    const int k = threadIdx.x + it * 256, hx = k % AHX, hy = k / AHX;
+    if (k < AHX * AHY) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sab[s][c][hy][hx] = in[it] ? vab[it][s][c] : R(0);
+    }
   }
   __syncthreads();
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= v.lx || y >= v.ly) return;  // after the kernel's only barrier
-  const size_t i = (size_t)y * v.lx + x;
+  if (!live) return;  // after the kernel's only barrier
   R *corr = static_cast<R *>(a.corr);
   // A_s = psi_s Fbar_s (which = 0) or B_s = r_s Fbar_s (which = 1) at a neighbour
-  auto AB = [&](int which, int s, int dx, int dy, R &bx, R &by) {
+  auto ab = [&](int which, int s, int dx, int dy, R &bx, R &by) {
     bx = sab[s][2 * which + 0][ty + 2 + dy][tx + 2 + dx];
     by = sab[s][2 * which + 1][ty + 2 + dy][tx + 2 + dx];
   };
-  R psib[2] = {0, 0}, rbar[2] = {0, 0};
-  for (int s = 0; s < NS; ++s) {
-    R Kq[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) Kq[q] = R(a.K[s][q]);
-    R acc = 0;
-    each_index<NHALF>([&](auto H) {
-      constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
-      R px, py, mx, my;
-      AB(0, s, hx, hy, px, py);
-      AB(0, s, -hx, -hy, mx, my);
-      acc += Kq[HQ[h]] * pair_dot<hx, hy>(px - mx, py - my);
-    });
-    psib[s] += acc;
-  }
-  if (NS == 2) {
-    for (int s = 0; s < 2; ++s) {  // species s's force depends on species o = 1 - s's field
-      const int o = 1 - s;
-      R acc = 0;
-      each_index<4>([&](auto H) {
-        constexpr int h = decltype(H)::value, hx = HX[h], hy = HY[h];
-        R px, py, mx, my;
-        AB(1, s, hx, hy, px, py);
-        AB(1, s, -hx, -hy, mx, my);
-        acc += R(a.t[HQ[h]]) * pair_dot<hx, hy>(px - mx, py - my);
-      });
-      // B_s uses species s's own r (r_s Fbar_s); it lands on the other species' field
-      if (a.cross_psi) psib[o] += R(a.gab) * acc;
-      else rbar[o] += R(a.gab) * acc;
-    }
-  }
-  for (int s = 0; s < NS; ++s) {
-    const R r = v.fld(0, s, i);
-    corr[(size_t)s * v.n + i] = rbar[s] + psib[s] * R(a.psi0) * R(a.irho0) * exp(-r * R(a.irho0));
-  }
+  R cn[2];
+  gather_corr<R, NS>(a, ab, rho, cn);
+  for (int s = 0; s < NS; ++s) corr[(size_t)s * v.n + i] = cn[s];
 }
 
 // acc[k] += sum over blocks of partials[block][k], in block order (deterministic).
@@ -461,21 +588,24 @@ __global__ void zero_kernel(uint32_t *p, size_t n) {
 int adj_blocks(int lx, int ly) { return ((lx + ATX - 1) / ATX) * ((ly + ATY - 1) / ATY); }
 
 template <typename R, int NS, bool WALLS>
-static hipError_t adj_step_t(const AdjArgs &a, hipStream_t st) {
+static hipError_t adj_step_t(const AdjArgs &a, int gin, int gout, hipStream_t st) {
   const dim3 tiles((a.lx + ATX - 1) / ATX, (a.ly + ATY - 1) / ATY), block(ATX * ATY);
-  hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS>), tiles, block, 0, st, a);
-  hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), tiles, block, 0, st, a);
+  if (gin) hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS, true>), tiles, block, 0, st, a);
+  else hipLaunchKernelGGL((adj_local_kernel<R, NS, WALLS, false>), tiles, block, 0, st, a);
+  if (gout) hipLaunchKernelGGL((adj_gather_kernel<R, NS, WALLS>), tiles, block, 0, st, a);
   return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t adj_step_r(int ns, int walls, const AdjArgs &a, hipStream_t st) {
-  if (ns == 1) return walls ? adj_step_t<R, 1, true>(a, st) : adj_step_t<R, 1, false>(a, st);
-  return walls ? adj_step_t<R, 2, true>(a, st) : adj_step_t<R, 2, false>(a, st);
+static hipError_t adj_step_r(int ns, int walls, const AdjArgs &a, int gin, int gout, hipStream_t st) {
+  if (ns == 1) return walls ? adj_step_t<R, 1, true>(a, gin, gout, st) : adj_step_t<R, 1, false>(a, gin, gout, st);
+  return walls ? adj_step_t<R, 2, true>(a, gin, gout, st) : adj_step_t<R, 2, false>(a, gin, gout, st);
 }
 
-hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, hipStream_t st) {
-  return fp64 ? adj_step_r<double>(ns, walls, a, st) : adj_step_r<float>(ns, walls, a, st);
+hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, int gather_in, int gather_out,
+                               hipStream_t st) {
+  return fp64 ? adj_step_r<double>(ns, walls, a, gather_in, gather_out, st)
+              : adj_step_r<float>(ns, walls, a, gather_in, gather_out, st);
 }
 
 hipError_t launch_adjoint_reduce(const double *partials, int lx, int ly, double *acc, hipStream_t st) {

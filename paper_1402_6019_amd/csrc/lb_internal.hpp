@@ -131,7 +131,11 @@ struct AdjArgs {
   void *lam;              // lam of lambda(t) (R, written)
   void *corr;             // corr of lambda(t) (R, written)
   void *fields;          // [4][2][y][x] (R): rho, psi, jx, jy of f(t)
-  void *fbar;            // [2][4][y][x] (R): psi_s Fbar_s and r_s Fbar_s (x, y components)
+  void *fbar;            // [2][4][y][x] (R): psi_s Fbar_s and r_s Fbar_s (x, y components), written
+  // With the common term of lambda(t+1) gathered in the local pass instead of read from
+  // corr_next: fbar of step t + 1 and the fields of f(t + 1).
+  const void *fbar_next;
+  const void *fields_next;
   double *partials;      // [blocks][ADJ_N]
   int lx, ly;
   int cross_psi, pad_;
@@ -149,8 +153,12 @@ struct AdjArgs {
 enum AdjSlot { ADJ_G1A = 0, ADJ_G1B, ADJ_G2A, ADJ_G2B, ADJ_GAB, ADJ_GX, ADJ_GY, ADJ_LW, ADJ_LQ, ADJ_N };
 
 int adj_blocks(int lx, int ly);
-// One reverse step; adds this step's per-block sensitivities to a.partials.
-hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, hipStream_t st);
+// One reverse step; adds this step's per-block sensitivities to a.partials.  gather_in: the
+// local pass gathers the common term of lambda(t+1) from a.fbar_next and a.fields_next
+// instead of reading a.corr_next; gather_out: a gather pass writes a.corr for lambda(t) (the
+// next reverse step reads it from memory).
+hipError_t launch_adjoint_step(int fp64, int ns, int walls, const AdjArgs &a, int gather_in, int gather_out,
+                               hipStream_t st);
 // acc[k] += sum over blocks of partials[block][k] (fixed order).
 hipError_t launch_adjoint_reduce(const double *partials, int lx, int ly, double *acc, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
