@@ -92,8 +92,9 @@ int lb3_totals(lb3_ctx *ctx, double mass[2], double momentum[3], double *flow);
 int lb3_checkpoint(lb3_ctx *ctx, void *dst_f64);
 int lb3_restore(lb3_ctx *ctx, const void *src_f64);
 
-/* Launch shape: ty in {1, 2, 4} rows of 64 columns per workgroup (ty waves) and sz >= 1
-   z-planes per workgroup; any shape gives bitwise identical results.  Host call. */
+/* Launch shape: ty in {1, 2, 4} rows of 64 columns per workgroup (ty waves), or 8 with FP32
+   storage, and sz >= 1 z-planes per workgroup; any shape gives bitwise identical results.
+   LB_EINVAL otherwise.  Host call. */
 int lb3_set_tile(lb3_ctx *ctx, int32_t ty, int32_t sz);
 int lb3_get_tile(const lb3_ctx *ctx, int32_t *ty, int32_t *sz);
 

@@ -323,7 +323,8 @@ int lb3_restore(lb3_ctx *c, const void *src) {
 
 int lb3_set_tile(lb3_ctx *c, int32_t ty, int32_t sz) {
   if (!c) return fail3(nullptr, LB_EINVAL, "null context");
-  if ((ty != 1 && ty != 2 && ty != 4) || sz < 1) return fail3(c, LB_EINVAL, "ty must be 1, 2 or 4 and sz >= 1");
+  const bool ty_ok = ty == 1 || ty == 2 || ty == 4 || (ty == 8 && c->lat.storage != LB_F64);
+  if (!ty_ok || sz < 1) return fail3(c, LB_EINVAL, "ty must be 1, 2, 4 (or 8 with FP32 storage) and sz >= 1");
   c->ty = ty;
   c->sz = std::min(sz, c->lat.lz);
   return LB_OK;

@@ -74,7 +74,7 @@ __device__ inline Rsrc zplane_rsrc(const void *p, const Geo3 &g, int z) {
   /* shell 8 */ X(6, 2, 2, 0) X(6, -2, 2, 0) X(6, 2, 0, 2) X(6, -2, 0, 2) X(6, 0, 2, 2) X(6, 0, -2, 2)
 
 template <int MODE, int NS, bool WALLS, int WHAT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step3_kernel(Lb3Args a) {
+__global__ __launch_bounds__(MODE == MODE_F64 ? 256 : 512) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step3_kernel(Lb3Args a) {
   using C = Codec<MODE>;
   using R = typename C::R;
   using S = typename C::S;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == MOD
   const int SLOT = W4 * H4;
   V *psi_ring = reinterpret_cast<V *>(lb3_smem);   // [6][H4][W4]
   V *rho_ring = psi_ring + 6 * SLOT;              // [6][H4][W4] (two species)
-  __shared__ double red_lds[4][RED3_N];
+  __shared__ double red_lds[8][RED3_N];
 
   const int lx = a.lx, ly = a.ly, lz = a.lz;
   Geo3 g;

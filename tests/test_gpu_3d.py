@@ -76,7 +76,10 @@ def test_3d_tile_shape_invariance_bitwise(storage, walls):
     rho, kw = case3(lx, ly, lz, 2, walls, seed=32, tau=(0.9, 1.2))
     ref = None
     from paper_1402_6019_amd import Sim3
-    for tile in (None, (1, 1), (2, 3), (4, 5), (4, 13), (1, 13)):
+    tiles = [None, (1, 1), (2, 3), (4, 5), (4, 13), (1, 13)]
+    if storage == "f32":  # eight-row workgroups (FP32 only); 21 rows leave a band of five
+        tiles += [(8, 4), (8, 13)]
+    for tile in tiles:
         sim = Sim3(lx, ly, lz, rho, n_species=2, walls=walls, storage=storage, tile=tile, **kw)
         sim.step(7)
         f = sim.checkpoint().cpu().numpy()
@@ -84,6 +87,16 @@ def test_3d_tile_shape_invariance_bitwise(storage, walls):
             ref = f
         assert np.array_equal(f, ref), tile
         sim.close()
+
+
+def test_3d_eight_row_tile_is_refused_for_fp64():
+    lx, ly, lz = 70, 21, 13
+    rho, kw = case3(lx, ly, lz, 2, False, seed=33, tau=(1.0, 1.0))
+    from paper_1402_6019_amd import Sim3, LbError
+    sim = Sim3(lx, ly, lz, rho, n_species=2, walls=False, storage="f64", **kw)
+    with pytest.raises(LbError):
+        sim.set_tile(8, 4)
+    sim.close()
 
 
 @pytest.mark.parametrize("walls", [False, True])
