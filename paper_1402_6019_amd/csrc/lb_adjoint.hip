@@ -402,14 +402,15 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
     my += jy[s] + R(0.5) * Fy[s];
   }
   // reciprocals taken once per site: the rest of the pass multiplies
-  const R iden = R(1) / den, irt = R(1) / rtot, ilx = R(1) / R(v.lx);
+  // 1 / lx comes from the host, rounded in R as a division here would round it
+  const R iden = R(1) / den, irt = R(1) / rtot, ilx = sizeof(R) == 8 ? R(a.ilx) : R(a.ilxf);
   const R upx = nx * iden, upy = ny * iden;
   const R urx = mx * irt;  // reported (half-force) velocity, x component
   const R ilr = ilx * irt;  // 1 / (lx rho_tot)
 
   // adjoint sources of this step's loss
   const R cW = R(a.cW), cQ = R(a.cQ);
-  double loss_w = 0.0;
+  double loss_w = 0.0;  // summed over the wall row's links, divided by lx once
   const double loss_q = live ? double(cQ * urx) / v.lx : 0.0;
 
   R ubx = 0, uby = 0;  // adjoint of u'
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
           // post-collision population leaving the wall row
           const R yl = (R(1) - om) * xwr[s][l] + om * feq;
           const R mw = R(3) * wl * R(a.rho_w[s]) * R(cx * cx) * R(cy < 0 ? a.u_wall[0] : a.u_wall[1]);
-          if (live) loss_w += double(cW * (R(cx) * yl - mw)) / v.lx;
+          if (live) loss_w += double(cW * (R(cx) * yl - mw));
         }
       }
       lp[s][l] = (R(1) - om) * al;
@@ -509,6 +510,7 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs a) {
   }
   // per-tile partial sums, accumulated over the reverse steps in each tile's own row
   // (fixed order: waves, then steps, then tiles in the final pass)
+  if (WALLS) loss_w /= v.lx;
   double vals[ADJ_N] = {dg1[0], dg1[1], dg2[0], dg2[1], dgab, dgx, dgy, loss_w, loss_q};
   const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
   tile_accumulate(vals, sm, a.partials + blk * ADJ_N);

@@ -885,6 +885,8 @@ AdjArgs adjoint_args(const lb_ctx *c, double lw0, double lw1, int64_t T) {
   a.gab = c->cpl.g_ab;
   a.psi0 = c->psi.psi0;
   a.irho0 = 1.0 / c->psi.rho0;
+  a.ilx = 1.0 / (double)c->lat.lx;
+  a.ilxf = 1.0f / (float)c->lat.lx;
   a.cW = lw0 / (double)T;
   a.cQ = lw1 / (double)T;
   a.u_wall[0] = c->lat.walls ? c->cpl.wall_velocity[0] : 0.0;

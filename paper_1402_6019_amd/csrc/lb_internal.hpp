@@ -146,6 +146,8 @@ struct AdjArgs {
   double psi0, irho0;
   double rho_w[2], psi_w[2];
   double cW, cQ;         // per-step loss weights
+  double ilx;            // 1 / lx, and the same rounded from a float division
+  float ilxf, pad2_;
   double u_wall[2];      // x-velocity of the bottom and top wall
 };
 
