@@ -148,7 +148,7 @@ def channel_beyond_cache(steps):
     # the kernel each mode runs at this footprint by default: FP32 two steps per launch, FP64
     # single steps with streaming stores (both beyond the Infinity Cache), BF16 (2 x 75.5 MB,
     # inside it) single steps with write-through stores
-    kernels = {"f32": "step2_kernel<F32, 2 species, channel>: two steps per launch, streaming stores",
+    kernels = {"f32": "step2_kernel<F32, 2 species, channel>: two steps per launch, write-through stores",
                "bf16dev": "step_kernel<BF16 deviations, 2 species, channel>, write-through stores",
                "f64": "step_kernel<F64, 2 species, channel>, streaming stores"}
     for storage in ("f32", "bf16dev", "f64"):
