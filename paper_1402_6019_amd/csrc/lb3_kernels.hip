@@ -193,67 +193,109 @@ __global__ __launch_bounds__(MODE == MODE_F64 ? 256 : 512) __attribute__((amdgpu
     }
   };
 
-  // Lead plane p into ring slot sl: the tile's own sites, then the halo.
-  auto ring_plane = [&](int p, int sl) {
+  // Pulls of halo site h of plane z, its ring index, and whether it lies past a wall.  Rows are
+  // clamped onto the lattice, so every load has a valid address and a caller may issue them
+  // unconditionally (a solid site's values are discarded).
+  auto halo_pull = [&](int h, int z, L (&f)[NS][19], bool &solid, int &hi) {
+    int hdx, hdy;
+    halo_site(h, hdx, hdy);
+    const int hx = ((x0 + hdx) % lx + lx) % lx;
+    const int hy_raw = y0 + hdy;
+    solid = WALLS && (hy_raw < 0 || hy_raw >= ly);
+    const int hy = WALLS ? min(max(hy_raw, 0), ly - 1) : ((hy_raw % ly) + ly) % ly;
+    const uint32_t hcol[3] = {(uint32_t)d3::wrap(hx - 1, lx) * g.site_b, (uint32_t)hx * g.site_b,
+                              (uint32_t)d3::wrap(hx + 1, lx) * g.site_b};
+    const Rsrc rz[3] = {zplane_rsrc(a.src, g, d3::wrap(z + 1, lz)), zplane_rsrc(a.src, g, z),
+                        zplane_rsrc(a.src, g, d3::wrap(z - 1, lz))};
+#pragma unroll
+    for (int l = 0; l < 19; ++l) {
+      const int sy = hy - d3::cy(l);
+      const bool bb = WALLS && (sy < 0 || sy >= ly);
+      uint32_t off;
+      int zi;
+      if (bb) {
+        off = (uint32_t)hy * g.row_b + (uint32_t)d3::opp(l) * g.plane_b + hcol[1];
+        zi = 1;
+      } else {
+        off = (uint32_t)d3::wrap(sy, ly) * g.row_b + (uint32_t)l * g.plane_b + hcol[1 - d3::cx(l)];
+        zi = 1 + d3::cz(l);
+      }
+      if (NS == 2) C::bload2(rz[zi], off, 0u, f[0][l], f[NS - 1][l]);
+      else f[0][l] = C::bload(rz[zi], off, 0u);
+    }
+    hi = (hdy + 2) * W4 + (hdx + 2);
+  };
+  // psi and rho of a site from its pulls, or the wall's values past a wall
+  auto ring_value = [&](bool solid, const L (&f)[NS][19], V &vp, V &vr) {
+    if (solid) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        vp.v[s] = psiw[s];
+        vr.v[s] = rhow[s];
+      }
+    } else {
+      site_psi(f, vp, vr);
+    }
+  };
+
+  // Lead plane p into ring slot sl: the tile's own sites, then the halo, and with pull_u the
+  // update's own pull of plane zu into fu.  FP32: the loads of the own sites, of the first halo
+  // round (one site per thread) and of the update's pull are issued together before any of them
+  // is waited for, so three memory latencies overlap instead of following each other.  FP64
+  // keeps them in turn: its three sets of pulls would take 228 of its 256 registers.
+  auto ring_plane = [&](int p, int sl, bool pull_u, int zu, L (&fu)[NS][19]) {
     const int z = d3::wrap(d3::wrap(p, lz), lz);
     V *ps = psi_ring + sl * SLOT;
     V *rh = rho_ring + sl * SLOT;
+    if constexpr (MODE == MODE_F64) {
+      {
+        L fo[NS][19];
+        pull_own(z, fo);
+        V vp, vr;
+        ring_value(y_solid, fo, vp, vr);
+        const int i = (wv + 2) * W4 + lane + 2;
+        ps[i] = vp;
+        if (NS == 2) rh[i] = vr;
+      }
+      for (int h = tid; h < nhalo; h += nthreads) {
+        L f2[NS][19];
+        bool hs = false;
+        int hi = 0;
+        halo_pull(h, z, f2, hs, hi);
+        V vp, vr;
+        ring_value(hs, f2, vp, vr);
+        ps[hi] = vp;
+        if (NS == 2) rh[hi] = vr;
+      }
+      if (pull_u) pull_own(zu, fu);  // its latency overlaps the barrier
+      return;
+    }
+    L fo[NS][19], fh[NS][19];
+    pull_own(z, fo);
+    bool hsolid = false;
+    int hi0 = 0;
+    halo_pull(min(tid, nhalo - 1), z, fh, hsolid, hi0);
+    if (pull_u) pull_own(zu, fu);
     {
       V vp, vr;
-      if (y_solid) {  // uniform per wave
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          vp.v[s] = psiw[s];
-          vr.v[s] = rhow[s];
-        }
-      } else {
-        L f[NS][19];
-        pull_own(z, f);
-        site_psi(f, vp, vr);
-      }
+      ring_value(y_solid, fo, vp, vr);
       const int i = (wv + 2) * W4 + lane + 2;
       ps[i] = vp;
       if (NS == 2) rh[i] = vr;
     }
-    for (int h = tid; h < nhalo; h += nthreads) {
-      int hdx, hdy;
-      halo_site(h, hdx, hdy);
-      const int hx = ((x0 + hdx) % lx + lx) % lx;
-      const int hy_raw = y0 + hdy;
-      const bool h_solid = WALLS && (hy_raw < 0 || hy_raw >= ly);
-      const int hy = WALLS ? min(max(hy_raw, 0), ly - 1) : ((hy_raw % ly) + ly) % ly;
-      const uint32_t hcol[3] = {(uint32_t)d3::wrap(hx - 1, lx) * g.site_b, (uint32_t)hx * g.site_b,
-                                (uint32_t)d3::wrap(hx + 1, lx) * g.site_b};
+    if (tid < nhalo) {
       V vp, vr;
-      if (h_solid) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          vp.v[s] = psiw[s];
-          vr.v[s] = rhow[s];
-        }
-      } else {
-        const Rsrc rz[3] = {zplane_rsrc(a.src, g, d3::wrap(z + 1, lz)), zplane_rsrc(a.src, g, z),
-                            zplane_rsrc(a.src, g, d3::wrap(z - 1, lz))};
-        L f[NS][19];
-#pragma unroll
-        for (int l = 0; l < 19; ++l) {
-          const int sy = hy - d3::cy(l);
-          const bool bb = WALLS && (sy < 0 || sy >= ly);
-          uint32_t off;
-          int zi;
-          if (bb) {
-            off = (uint32_t)hy * g.row_b + (uint32_t)d3::opp(l) * g.plane_b + hcol[1];
-            zi = 1;
-          } else {
-            off = (uint32_t)d3::wrap(sy, ly) * g.row_b + (uint32_t)l * g.plane_b + hcol[1 - d3::cx(l)];
-            zi = 1 + d3::cz(l);
-          }
-          if (NS == 2) C::bload2(rz[zi], off, 0u, f[0][l], f[NS - 1][l]);
-          else f[0][l] = C::bload(rz[zi], off, 0u);
-        }
-        site_psi(f, vp, vr);
-      }
-      const int hi = (hdy + 2) * W4 + (hdx + 2);
+      ring_value(hsolid, fh, vp, vr);
+      ps[hi0] = vp;
+      if (NS == 2) rh[hi0] = vr;
+    }
+    for (int h = tid + nthreads; h < nhalo; h += nthreads) {
+      L f2[NS][19];
+      bool hs = false;
+      int hi = 0;
+      halo_pull(h, z, f2, hs, hi);
+      V vp, vr;
+      ring_value(hs, f2, vp, vr);
       ps[hi] = vp;
       if (NS == 2) rh[hi] = vr;
     }
@@ -264,13 +306,15 @@ __global__ __launch_bounds__(MODE == MODE_F64 ? 256 : 512) __attribute__((amdgpu
   for (int k = 0; k < RED3_N; ++k) acc[k] = 0.0;
 
   // Prologue: planes zA - 2 .. zA + 1 into slots 0..3 (plane p lives in slot (p - zA + 2) mod 6).
-  for (int k = 0; k < 4; ++k) ring_plane(zA - 2 + k, k);
+  {
+    L unused[NS][19];
+    for (int k = 0; k < 4; ++k) ring_plane(zA - 2 + k, k, false, 0, unused);
+  }
 
   for (int z = zA; z < zB; ++z) {
     const int k0 = z - zA;  // slot of plane z - 2
-    ring_plane(z + 2, (k0 + 4) % 6);
-    L f[NS][19];
-    pull_own(z, f);  // the site to update: its latency overlaps the barrier
+    L f[NS][19];  // the site to update, pulled together with the lead plane
+    ring_plane(z + 2, (k0 + 4) % 6, true, z, f);
     __syncthreads();
 
     // ---- update plane z ---------------------------------------------------------------

@@ -125,10 +125,12 @@ __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
-  const double *rho = static_cast<const double *>(a.in);
-  S *out = static_cast<S *>(a.out);
+  const double *__restrict__ rho = static_cast<const double *>(a.in);
+  S *__restrict__ out = static_cast<S *>(a.out);
   const size_t nsite = (size_t)a.lx * a.ly;
-  for (int s = 0; s < a.ns; ++s)
+  for (int s = 0; s < a.ns; ++s) {
+    // the nine loads first, so that they are in flight together
+    double rn[9];
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
       int zx = x + CXS[l], zy = y + CYS[l];
@@ -139,9 +141,12 @@ __global__ void init_kernel(LayoutArgs a) {  // in: rho [ns][ly][lx] (FP64)
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const double v = WD2Q9[l] * rho[s * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), v, WD2Q9[l] * a.rho_ref[s]);
+      rn[l] = rho[s * nsite + (size_t)zy * a.lx + zx];
     }
+#pragma unroll
+    for (int l = 0; l < 9; ++l)
+      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), WD2Q9[l] * rn[l], WD2Q9[l] * a.rho_ref[s]);
+  }
 }
 
 template <int MODE, bool WALLS>
@@ -150,10 +155,12 @@ __global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][l
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
-  const double *f = static_cast<const double *>(a.in);
-  S *out = static_cast<S *>(a.out);
+  const double *__restrict__ f = static_cast<const double *>(a.in);
+  S *__restrict__ out = static_cast<S *>(a.out);
   const size_t nsite = (size_t)a.lx * a.ly;
-  for (int s = 0; s < a.ns; ++s)
+  for (int s = 0; s < a.ns; ++s) {
+    // the nine loads first, so that they are in flight together
+    double v[9];
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
       int zx = x + CXS[l], zy = y + CYS[l], lsrc = l;
@@ -165,9 +172,11 @@ __global__ void restore_kernel(LayoutArgs a) {  // in: canonical f [ns][9][ly][l
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const double v = f[(size_t)(s * 9 + lsrc) * nsite + (size_t)zy * a.lx + zx];
-      C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), v, WD2Q9[l] * a.rho_ref[s]);
+      v[l] = f[(size_t)(s * 9 + lsrc) * nsite + (size_t)zy * a.lx + zx];
     }
+#pragma unroll
+    for (int l = 0; l < 9; ++l) C::store(out + pop_index(s, l, y, x, a.pitch, a.ns), v[l], WD2Q9[l] * a.rho_ref[s]);
+  }
 }
 
 template <int MODE, bool WALLS>
@@ -176,10 +185,12 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
-  const S *in = static_cast<const S *>(a.in);
-  double *f = static_cast<double *>(a.out);
+  const S *__restrict__ in = static_cast<const S *>(a.in);
+  double *__restrict__ f = static_cast<double *>(a.out);
   const size_t nsite = (size_t)a.lx * a.ly;
-  for (int s = 0; s < a.ns; ++s)
+  for (int s = 0; s < a.ns; ++s) {
+    // the nine pulls first, so that their loads are in flight together
+    double v[9];
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
       int zx = x - CXS[l], zy = y - CYS[l], lsrc = l;
@@ -191,9 +202,11 @@ __global__ void checkpoint_kernel(LayoutArgs a) {  // out: canonical f [ns][9][l
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] =
-          C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), WD2Q9[lsrc] * a.rho_ref[s]);
+      v[l] = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), WD2Q9[lsrc] * a.rho_ref[s]);
     }
+#pragma unroll
+    for (int l = 0; l < 9; ++l) f[(size_t)(s * 9 + l) * nsite + (size_t)y * a.lx + x] = v[l];
+  }
 }
 
 // What the adjoint's reverse step reads of a state: the canonical populations of the rows next
@@ -207,16 +220,17 @@ __global__ void checkpoint_fields_kernel(LayoutArgs a) {
   using S = typename C::S;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= a.lx) return;
-  const S *in = static_cast<const S *>(a.in);
-  double *f = static_cast<double *>(a.out);
-  RA *fl = static_cast<RA *>(a.fields);
+  const S *__restrict__ in = static_cast<const S *>(a.in);
+  double *__restrict__ f = static_cast<double *>(a.out);
+  RA *__restrict__ fl = static_cast<RA *>(a.fields);
   const size_t nsite = (size_t)a.lx * a.ly;
   const size_t i = (size_t)y * a.lx + x;
   // the reverse step reads the populations themselves only on the rows next to a wall (for
   // the wall stress); elsewhere the fields suffice
   const bool wall_row = WALLS && (y == 0 || y == a.ly - 1);
   for (int s = 0; s < a.ns; ++s) {
-    RA r = 0, jx = 0, jy = 0;
+    // the nine pulls first, so that their loads are in flight together
+    double fp[9];
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
       int zx = x - CXS[l], zy = y - CYS[l], lsrc = l;
@@ -228,7 +242,12 @@ __global__ void checkpoint_fields_kernel(LayoutArgs a) {
         zx = wrapi(zx, a.lx);
         zy = wrapi(zy, a.ly);
       }
-      const double fv = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), WD2Q9[lsrc] * a.rho_ref[s]);
+      fp[l] = C::load(in + pop_index(s, lsrc, zy, zx, a.pitch, a.ns), WD2Q9[lsrc] * a.rho_ref[s]);
+    }
+    RA r = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const double fv = fp[l];
       if (wall_row) f[((size_t)(s * 9 + l) * 2 + (y == 0 ? 0 : 1)) * a.lx + x] = fv;
       const RA g = RA(fv);
       r += g;
