@@ -50,16 +50,17 @@ def test_adjoint_keeping_every_state_matches_the_checkpointed_sweep(storage, fp6
     states: a checkpoint restores to bitwise the stored state (f = d + W rho_ref formed and
     undone in FP64), so the recomputed states are the forward's, and loss and gradient agree
     exactly in every storage mode.  The state after the call is bitwise that of plain
-    stepping."""
+    stepping.  Seven segments, two (the least that recompute beside the reverse sweep on a
+    second stream) and one (a single stream) give the same."""
     c = channel(storage=storage)
     T, lw = 45, (1.0, 0.3)
     res = {}
-    for every in (1, 7, 0):
+    for every in (1, 7, 0, 23, 45):
         sim = make_sim(c)
         loss, g7 = sim.adjoint(T, lw, every=every, fp64_reverse=fp64_reverse)
         res[every] = (loss, g7, sim.checkpoint().cpu().numpy())
         sim.close()
-    for every in (7, 0):
+    for every in (7, 0, 23, 45):
         assert res[every][0] == res[1][0]
         assert np.array_equal(res[every][1], res[1][1])
         assert np.array_equal(res[every][2], res[1][2])
