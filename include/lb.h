@@ -247,19 +247,22 @@ int lb_set_store_policy(lb_ctx *ctx, int32_t policy);
    stochastically rounding contexts (it recomputes states).  Host call. */
 int lb_set_rounding(lb_ctx *ctx, int32_t mode);
 
-/* Temporal blocking (FP32 and BF16 storage): with LB_TWO_STEP_ON, lb_step advances plain
-   steps (no reductions, lb_set_reduce_every k = 0) two at a time, one launch per pair, keeping
-   the intermediate post-collision populations on chip, so the populations cross HBM once per
-   two steps.  Each wave updates a strip of 54 columns from a 64-column window and a segment of
+/* Temporal blocking (every storage mode): with LB_TWO_STEP_ON, lb_step advances plain steps
+   (no reductions, lb_set_reduce_every k = 0) two at a time, one launch per pair, keeping the
+   intermediate post-collision populations on chip, so the populations cross HBM once per two
+   steps.  Each wave updates a strip of 54 columns from a 64-column window and a segment of
    `rows` rows (0: the default, sized so the whole grid is resident), recomputing the overlaps.
    The per-site arithmetic and the rounding of the intermediate to the storage format are those
    of two single steps: results are bitwise identical to LB_TWO_STEP_OFF (also with stochastic
-   BF16 rounding and under graph replay).  LB_TWO_STEP_AUTO (the default) pairs the steps of
-   walled FP32 lattices whose two population buffers exceed the 256 MiB Infinity Cache, where the
-   pairs measured faster.  LB_EINVAL for LB_TWO_STEP_ON with FP64 storage, or rows < 0.  Host
-   call. */
+   BF16 rounding and under graph replay).  LB_TWO_STEP_AUTO (the default) pairs the steps where
+   they measured faster, for lattices whose two population buffers exceed the 256 MiB Infinity
+   Cache: walled FP32 and periodic FP64 lattices.  LB_EINVAL for rows < 0.  Host call. */
 enum lb_two_step { LB_TWO_STEP_OFF = 0, LB_TWO_STEP_ON = 1, LB_TWO_STEP_AUTO = 2 };
 int lb_set_two_step(lb_ctx *ctx, int32_t enable, int32_t rows);
+
+/* 1 if lb_step currently advances plain steps in pairs (lb_set_two_step and the reduction
+   setting), 0 if one per launch, -1 for a NULL context.  Pure host call. */
+int lb_two_step_active(const lb_ctx *ctx);
 
 /* Replay plain steps from captured HIP graphs: with steps > 0 (even) and no reductions
    (lb_set_reduce_every k = 0), lb_step runs whole groups of `steps` launches as one graph

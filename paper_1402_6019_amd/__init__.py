@@ -132,10 +132,16 @@ class Sim:
         self._chk(self._lib.lb_set_time(self._h, int(t)))
 
     def set_two_step(self, enable=True, rows=0):
-        """Advance plain steps two per launch (FP32 / BF16; bitwise the same results): True, False
-        or "auto" (the default: pairs for walled FP32 lattices beyond the Infinity Cache)."""
+        """Advance plain steps two per launch (bitwise the same results): True, False or "auto"
+        (the default: pairs for walled FP32 and periodic FP64 lattices beyond the Infinity
+        Cache)."""
         mode = 2 if enable == "auto" else (1 if enable else 0)
         self._chk(self._lib.lb_set_two_step(self._h, mode, int(rows)))
+
+    @property
+    def two_step_active(self):
+        """Whether step() currently advances plain steps two per launch."""
+        return self._lib.lb_two_step_active(self._h) == 1
 
     def step(self, n=1):
         self._chk(self._lib.lb_step(self._h, int(n)))

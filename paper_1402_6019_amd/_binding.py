@@ -76,6 +76,7 @@ SIGNATURES = {
     "lb_time": (_i64, [_vp]),
     "lb_set_time": (ctypes.c_int, [_vp, _i64]),
     "lb_set_two_step": (ctypes.c_int, [_vp, _i32, _i32]),
+    "lb_two_step_active": (ctypes.c_int, [_vp]),
     "lb_set_tile": (ctypes.c_int, [_vp, _i32, _i32]),
     "lb_set_store_policy": (ctypes.c_int, [_vp, _i32]),
     "lb_set_rounding": (ctypes.c_int, [_vp, _i32]),

@@ -149,7 +149,9 @@ int grid2(const lb_ctx *c, int *sy_out, int *nseg_out) {
   const int nstrip = (c->lat.lx + 53) / 54;
   int sy = c->sy2;
   if (sy <= 0) {
-    const int resident = std::max(1, blocks2_per_cu_f32(c->lat.n_species, c->lat.walls)) * c->n_cu;
+    const int per_cu = c->lat.storage == LB_F64 ? blocks2_per_cu_f64(c->lat.n_species, c->lat.walls)
+                                                : blocks2_per_cu_f32(c->lat.n_species, c->lat.walls);
+    const int resident = std::max(1, per_cu) * c->n_cu;
     const int nseg = std::max(1, resident / nstrip);
     sy = std::max(1, (c->lat.ly + nseg - 1) / nseg);
   }
@@ -160,14 +162,17 @@ int grid2(const lb_ctx *c, int *sy_out, int *nseg_out) {
   return nstrip * nseg;
 }
 
-// Whether plain steps go in pairs: forced on or off, or (auto) for walled FP32 lattices whose
-// two population buffers exceed the Infinity Cache, where the pairs' halved HBM traffic
-// outweighs their recomputed overlaps (measured: 10% faster on the 4096 x 512, 4096 x 1024 and
-// 2048^2 channels; slower on the cache-resident 1024^2 lattice, in BF16, and for periodic
-// lattices, whose instantiation spills registers).
+// Whether plain steps go in pairs: forced on or off, or (auto) where the pairs' halved HBM
+// traffic measured worth more than their recomputed overlaps, for lattices whose two population
+// buffers exceed the Infinity Cache: walled FP32 (10% faster on the 4096 x 512, 4096 x 1024 and
+// 2048^2 channels; its periodic instantiation spills registers and is slower) and periodic
+// FP64 (9-14% faster at 1024^2, 2048 x 1024, 4096 x 512 and 2048^2; walled FP64 gained nothing).
+// Never for BF16, nor for a cache-resident FP32 lattice.
 bool pairs_on(const lb_ctx *c) {
-  if (c->two_step == LB_TWO_STEP_AUTO)
-    return c->lat.storage == LB_F32 && c->lat.walls && streaming_stores(lb_pop_bytes(&c->lat));
+  if (c->two_step == LB_TWO_STEP_AUTO) {
+    if (!streaming_stores(lb_pop_bytes(&c->lat))) return false;
+    return (c->lat.storage == LB_F32 && c->lat.walls) || (c->lat.storage == LB_F64 && !c->lat.walls);
+  }
   return c->two_step == LB_TWO_STEP_ON;
 }
 
@@ -605,14 +610,14 @@ int lb_set_two_step(lb_ctx *c, int32_t enable, int32_t rows) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (enable != LB_TWO_STEP_OFF && enable != LB_TWO_STEP_ON && enable != LB_TWO_STEP_AUTO)
     return fail(c, LB_EINVAL, "enable must be LB_TWO_STEP_OFF, LB_TWO_STEP_ON or LB_TWO_STEP_AUTO");
-  if (enable == LB_TWO_STEP_ON && c->lat.storage == LB_F64)
-    return fail(c, LB_EINVAL, "two steps per launch: FP32 and BF16 storage only");
   if (rows < 0) return fail(c, LB_EINVAL, "rows must be >= 0");
   c->two_step = enable;
   c->sy2 = rows;
   c->graph.clear();  // captured launches change
   return LB_OK;
 }
+
+int lb_two_step_active(const lb_ctx *c) { return c ? (pairs_on(c) && c->reduce_every == 0 ? 1 : 0) : -1; }
 
 int lb_set_time(lb_ctx *c, int64_t t) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");

@@ -220,11 +220,13 @@ hipError_t launch_batch_f32(int ns, int walls, int what, int tx, int grid, const
 hipError_t launch_batch_bf16(bool stochastic, int ns, int walls, int what, int tx, int grid, const BatchArgs &b,
                              hipStream_t st);
 int blocks_per_cu_f64(int ns, int walls, int tx);
-// Two time steps per launch (lb_step2.hpp; FP32 and BF16 storage): one wave per workgroup,
-// strips of 54 columns, nb = strips x segments workgroups, a.sy rows per segment.
+// Two time steps per launch (lb_step2.hpp): one wave per workgroup, strips of 54 columns,
+// nb = strips x segments workgroups, a.sy rows per segment.
+hipError_t launch_step2_f64(int ns, int walls, int nb, const StepArgs &a, hipStream_t st);
 hipError_t launch_step2_f32(int ns, int walls, int nb, const StepArgs &a, hipStream_t st);
 hipError_t launch_step2_bf16(bool stochastic, int ns, int walls, int nb, const StepArgs &a, hipStream_t st);
-int blocks2_per_cu_f32(int ns, int walls);
+int blocks2_per_cu_f32(int ns, int walls);  // also BF16 (the same registers and LDS)
+int blocks2_per_cu_f64(int ns, int walls);
 int blocks_per_cu_f32(int ns, int walls, int tx);
 int blocks_per_cu_bf16(int ns, int walls, int tx);
 // Workgroups of tx threads of the plain step kernel that one compute unit holds at once.

@@ -291,6 +291,7 @@ hipError_t launch_batch_reduce(const double *partials, const ReduceJob *jobs, in
 
 hipError_t launch_step2(int mode, int ns, int walls, int nb, const StepArgs &a, hipStream_t st) {
   switch (mode) {
+    case MODE_F64: return launch_step2_f64(ns, walls, nb, a, st);
     case MODE_F32: return launch_step2_f32(ns, walls, nb, a, st);
     case MODE_BF16: return launch_step2_bf16(false, ns, walls, nb, a, st);
     case MODE_BF16SR: return launch_step2_bf16(true, ns, walls, nb, a, st);

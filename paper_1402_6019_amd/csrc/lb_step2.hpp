@@ -38,8 +38,9 @@ namespace lb355 {
 constexpr int kStrip2 = 54;  // output columns per wave
 constexpr int kPad2 = 5;     // lanes left of the first output column
 
-// LDS of one two-step workgroup, sized so that eight fit in the 160 KB of a compute unit (two
-// waves per SIMD).  Rings of psi (five rows) and rho (four rows) for both steps: rows of 64
+// LDS of one two-step workgroup, sized so that eight fit in the 160 KB of a compute unit in FP32
+// and BF16 (two waves per SIMD), four in FP64 (one wave per SIMD, whose 512 registers, 256 of
+// them accumulation registers, hold the FP64 register FIFOs).  Rings of psi (five rows) and rho (four rows) for both steps: rows of 64
 // entries laid end to end with two spare entries at each end, so a lane's neighbours two
 // columns away fall on the adjacent row's edge lanes (only lanes whose results are discarded
 // read them).  The input ring of the second step keeps each row of f*(t) only as long as its
@@ -68,7 +69,7 @@ __device__ inline int in2_row(int l, int r, int dir) {
 }
 
 template <int MODE, int NS, bool WALLS, int STP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void step2_kernel(StepArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == MODE_F64 ? 1 : 2))) void step2_kernel(StepArgs a) {
   using C = Codec<MODE>;
   using R = typename C::R;
   using S = typename C::S;

@@ -78,13 +78,28 @@ def test_two_step_bitwise_full_size_emulsion():
         assert np.array_equal(out[0], out[1]), storage
 
 
-def test_two_step_rejects_fp64():
-    from paper_1402_6019_amd import LbError
-    c = film_case(64, 64)
-    sim = make_sim(c)
-    with pytest.raises(LbError):
-        sim.set_two_step(True)
-    sim.close()
+@pytest.mark.parametrize("walls", [True, False])
+def test_two_step_bitwise_fp64(walls):
+    """FP64 runs the same march at one wave per SIMD (its register FIFOs in the accumulation
+    registers), the intermediate kept exactly."""
+    c = emulsion_case(130, 45, walls=walls, fraction=0.7, seed=43, rmin=5, rmax=9, g=1e-5 if walls else 0.0)
+    c["storage"] = "f64"
+    c["tau"] = (0.9, 1.2)
+    if walls:
+        c["u_wall"] = (-0.01, 0.02)
+    for steps in (14, 13):
+        ref, _ = run(c, steps)
+        for rows in (0, 1, 7, 45):
+            f, t = run(c, steps, two_step=True, rows=rows)
+            assert t == steps
+            assert np.array_equal(f, ref), (steps, rows)
+    ref, _ = run(c, 24)
+    f, _ = run(c, 24, two_step=True, graph=8)
+    assert np.array_equal(f, ref), "graph replay"
+    c1 = film_case(61, 20, storage="f64", tau=0.8)
+    ref, _ = run(c1, 11)
+    f, _ = run(c1, 11, two_step=True, rows=3)
+    assert np.array_equal(f, ref), "one species"
 
 
 def test_two_step_auto_picks_pairs_beyond_the_cache():
@@ -102,7 +117,35 @@ def test_two_step_auto_picks_pairs_beyond_the_cache():
     for mode in ("auto", False):
         sim = Sim(lx, ly, rho, storage="f32", **kw)
         sim.set_two_step(mode)
+        assert sim.two_step_active == (mode == "auto")
         sim.step(6)
+        out[mode] = sim.checkpoint().cpu().numpy()
+        sim.close()
+    assert np.array_equal(out["auto"], out[False])
+    # a reducing context steps one launch at a time
+    sim = Sim(lx, ly, rho, storage="f32", **kw)
+    sim.set_reduce_every(1)
+    assert not sim.two_step_active
+    sim.close()
+
+
+@pytest.mark.parametrize("walls,storage,pairs", [(False, "f64", True), (True, "f64", False), (False, "f32", False)])
+def test_two_step_auto_rule_at_1024(walls, storage, pairs):
+    """At 1024^2, auto pairs the steps of the periodic FP64 lattice (2 x 151 MB) and of no walled
+    FP64 one, nor of the cache-resident FP32 lattice; the populations equal forced single steps."""
+    import lbgen
+    from paper_1402_6019_amd import Sim
+    lx = ly = 1024
+    rho, _ = lbgen.emulsion(lx, ly, fraction=0.8, seed=2, walls=walls)
+    kw = dict(n_species=2, walls=walls, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
+              rho_wall=lbgen.EMULSION_POOR, rho0=lbgen.EMULSION_RHO0,
+              rho_ref=(float(rho[0].mean()), float(rho[1].mean())))
+    out = {}
+    for mode in ("auto", False):
+        sim = Sim(lx, ly, rho, storage=storage, **kw)
+        sim.set_two_step(mode)
+        assert sim.two_step_active == (pairs and mode == "auto")
+        sim.step(5)
         out[mode] = sim.checkpoint().cpu().numpy()
         sim.close()
     assert np.array_equal(out["auto"], out[False])
