@@ -522,16 +522,48 @@ def couette_cell(steps, sample_every=100):
     torch.cuda.synchronize()
     ms_run = start.elapsed_time(stop) / (nsamp * sample_every)
     sig = st["sigma"].cpu().numpy()
+
+    # two steps per launch (lb_set_two_step), timed over whole runs of steps
+    def bulk(s, n):
+        s.step(20)
+        start.record(s.stream)
+        s.step(n)
+        stop.record(s.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / n
+
+    sim.set_two_step(True)
+    ms_two = bulk(sim, steps)
     sim.close()
+    # the same cell at 1024 x 1024 (whole 128- and 256-wide strips, whole 8-row segments) for
+    # the cost per site of the ragged width
+    rho_r, _ = lbgen.emulsion(1024, 1024, fraction=0.8, seed=6, walls=True)
+    ref = Sim(1024, 1024, rho_r, n_species=2, walls=True, storage="f32", g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2,
+              gab=lbgen.EMULSION_GAB, rho_wall=lbgen.EMULSION_POOR, tau=(1.0, 1.0), psi0=1.0,
+              rho0=lbgen.EMULSION_RHO0, u_wall=(-uw, uw))
+    ref.step(50)
+    ref.autotune(trial_steps=20)
+    ref_single = bulk(ref, steps)
+    ref.set_two_step(True)
+    ref_two = bulk(ref, steps)
+    ref.close()
+    ps = lambda ms, n: ms * 1e9 / (n * n)
     read_bytes = 9 * 2 * 4 * lx * ly
     return {"workload": f"Couette cell {lx}x{ly}, confined emulsion, volume fraction 0.8, seed 6, walls +-{uw}, FP32",
             "mass_fraction": info["mass_fraction"], "tile": list(tile), "default_tile": list(default_tile),
             "ms_per_step": ms_step, "mlups": lx * ly / (ms_step * 1e-3) / 1e6,
             "gbs": 144 * lx * ly / (ms_step * 1e-3) / 1e9,
+            "ms_per_step_two_step": ms_two, "gbs_two_step": 144 * lx * ly / (ms_two * 1e-3) / 1e9,
             "ms_per_profile": ms_prof, "profile_read_gbs": read_bytes / (ms_prof * 1e-3) / 1e9,
             "profile_every": sample_every, "ms_per_step_with_profiles": ms_run,
             "profile_overhead": ms_run / ms_step - 1.0, "samples": nsamp,
-            "mean_wall_stress": [float(sig[0]), float(-sig[-1])]}
+            "mean_wall_stress": [float(sig[0]), float(-sig[-1])],
+            "ragged_width": {"note": "ps per site of the 1040^2 cell against the same cell at 1024^2 (autotuned tile, "
+                                     "whole runs of steps), single steps and two steps per launch",
+                             "ps_per_site_1040": {"single": ps(ms_step, lx), "two_step": ps(ms_two, lx)},
+                             "ps_per_site_1024": {"single": ps(ref_single, 1024), "two_step": ps(ref_two, 1024)},
+                             "best_1040_over_best_1024": min(ps(ms_step, lx), ps(ms_two, lx)) /
+                                                         min(ps(ref_single, 1024), ps(ref_two, 1024))}}
 
 
 def couette_study(u_wall=0.01, fraction=0.8, warm=200000, samples=1500, every=200):
