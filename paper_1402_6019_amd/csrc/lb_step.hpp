@@ -204,25 +204,33 @@ template <> struct Codec<MODE_BF16> {
   }
 };
 
-// BF16 with stochastic rounding at the population stores: the 16 bits that BF16 drops are
-// compared with 16 random bits, so a value rounds away from zero with probability equal to
-// the dropped fraction.  The rounding is unbiased, so increments far below one BF16 step (a
-// weak body force) still accumulate on average.  Non-finite values take the nearest rounding.
+// BF16 with stochastic rounding at the population stores: 16 random bits are added to the 16
+// bits that BF16 drops before they are cut off, so a value rounds away from zero with
+// probability equal to the dropped fraction.  The rounding is unbiased, so increments far
+// below one BF16 step (a weak body force) still accumulate on average.
+// The hardware conversion (v_cvt_sr_bf16_f32) does this: it adds the high 16 bits of its random
+// operand to the float's bits and keeps the top 16, (bits + r16) >> 16 for a finite value (checked
+// bit for bit against that expression over a million random values and random bits); a value
+// rounds away from zero with probability equal to the dropped fraction, and infinities stay
+// infinite.
 template <> struct Codec<MODE_BF16SR> : Codec<MODE_BF16> {
   static constexpr bool kStochastic = true;
+  // bits of bf16(v) rounded with the 16 random bits r16
   __device__ static uint32_t round_sr(float v, uint32_t r16) {
-    const uint32_t b = __float_as_uint(v);
-    if ((b & 0x7f800000u) == 0x7f800000u) return encode(v);
-    return (b + r16) >> 16;  // magnitude bits round up with probability (b & 0xffff) / 2^16
+    const bf16x2 z = {};
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_sr_bf16_f32(z, v, r16 << 16, false)) & 0xffffu;
   }
   template <int AUX>
   __device__ static void bstore_sr(Rsrc r, uint32_t voff, uint32_t soff, R v, uint32_t rnd) {
     __builtin_amdgcn_raw_buffer_store_b16((uint16_t)round_sr(v, rnd & 0xffffu), r, voff, soff, AUX);
   }
+  // both species in one word: a rounded with the low 16 random bits, b with the high 16
   template <int AUX>
   __device__ static void bstore2_sr(Rsrc r, uint32_t voff, uint32_t soff, R a, R b, uint32_t rnd) {
-    __builtin_amdgcn_raw_buffer_store_b32(round_sr(a, rnd & 0xffffu) | (round_sr(b, rnd >> 16) << 16), r, voff, soff,
-                                          AUX);
+    bf16x2 w = {};
+    w = __builtin_amdgcn_cvt_sr_bf16_f32(w, a, rnd << 16, false);
+    w = __builtin_amdgcn_cvt_sr_bf16_f32(w, b, rnd & 0xffff0000u, true);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, w), r, voff, soff, AUX);
   }
 };
 
