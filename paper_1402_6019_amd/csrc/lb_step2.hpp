@@ -40,10 +40,10 @@ constexpr int kPad2 = 5;     // lanes left of the first output column
 
 // LDS of one two-step workgroup, sized so that eight fit in the 160 KB of a compute unit in FP32
 // and BF16 (two waves per SIMD), four in FP64 (one wave per SIMD, whose 512 registers, 256 of
-// them accumulation registers, hold the FP64 register FIFOs).  Rings of psi (five rows) and rho (four rows) for both steps: rows of 64
-// entries laid end to end with two spare entries at each end, so a lane's neighbours two
-// columns away fall on the adjacent row's edge lanes (only lanes whose results are discarded
-// read them).  The input ring of the second step keeps each row of f*(t) only as long as its
+// them accumulation registers, hold the FP64 register FIFOs).  Rings of psi (five rows) and
+// rho (four rows) for both steps: rows of 64 entries laid end to end with two spare entries at
+// each end, so a lane's neighbours two columns away fall on the adjacent row's edge lanes (only
+// lanes whose results are discarded read them).  The input ring of the second step keeps each row of f*(t) only as long as its
 // planes are pulled: planes 0, 1, 3 (pulled in place) and 4, 7, 8 (pulled from the row above)
 // for two rows, planes 2, 5, 6 (pulled from the row below) for three; a plane row has 64
 // entries and the pull's neighbouring lane wraps round (again only for discarded lanes).
