@@ -43,10 +43,11 @@ constexpr int kPad2 = 5;     // lanes left of the first output column
 // them accumulation registers, hold the FP64 register FIFOs).  Rings of psi (five rows) and
 // rho (four rows) for both steps: rows of 64 entries laid end to end with two spare entries at
 // each end, so a lane's neighbours two columns away fall on the adjacent row's edge lanes (only
-// lanes whose results are discarded read them).  The input ring of the second step keeps each row of f*(t) only as long as its
-// planes are pulled: planes 0, 1, 3 (pulled in place) and 4, 7, 8 (pulled from the row above)
-// for two rows, planes 2, 5, 6 (pulled from the row below) for three; a plane row has 64
-// entries and the pull's neighbouring lane wraps round (again only for discarded lanes).
+// lanes whose results are discarded read them).  The input ring of the second step keeps each
+// row of f*(t) only as long as its planes are pulled: planes 0, 1, 3 (pulled in place) and 4, 7,
+// 8 (pulled from the row above) for two rows, planes 2, 5, 6 (pulled from the row below) for
+// three; a plane row has 64 entries and the pull's neighbouring lane wraps round (again only for
+// discarded lanes).
 constexpr int kRing2Psi = 5 * 64 + 4, kRing2Rho = 4 * 64 + 4, kIn2Rows = 21;
 inline size_t step2_lds_bytes(int mode, int ns) {
   const size_t r = mode == MODE_F64 ? 8 : 4;
