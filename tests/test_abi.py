@@ -189,6 +189,8 @@ def test_null_contexts_fail_cleanly(B):
     assert lib.lb_adjoint_workspace_bytes(None, 10, 0, 0) == 0
     assert lib.lb_time(None) == -1
     assert lib.lb_batch_time(None) == -1
+    assert lib.lb_two_step_active(None) == -1
+    assert lib.lb_set_two_step(None, 1, 0) == B.LB_EINVAL
 
 
 def test_cooperative_length_fit_recovers_the_prediction(B):
