@@ -38,7 +38,7 @@ TOL = {"f64": (1e-12, 1e-11), "f32": (1e-5, 1e-5), "bf16dev": (1e-2, 5e-2)}
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16dev"])
 def test_emulsion_1024_full_size(storage):
     """Two-component emulsion, 1024 x 1024 periodic, volume fraction 0.8 (the headline
-    workload), 10 steps."""
+    workload), 10 steps; FP64 advances them two per launch (its default for this lattice)."""
     import bench
     rho, _, kw = bench.workload()
     kw = dict(kw, walls=False)
@@ -50,8 +50,8 @@ def test_emulsion_1024_full_size(storage):
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16dev"])
 def test_channel_4096x512_full_size(storage):
     """Confined emulsion channel 4096 x 512 (walls, wetting, g = 1e-6, fraction 0.85), 6 steps,
-    in the default launch shape and store policy (FP64 and FP32 buffers exceed the Infinity
-    Cache, so the streaming-store instantiation runs)."""
+    in the default launch shape and store policy: the FP64 and FP32 buffers exceed the Infinity
+    Cache, so FP64 runs the streaming-store single step and FP32 two steps per launch."""
     lx, ly = 4096, 512
     rho, _ = lbgen.emulsion(lx, ly, fraction=0.85, seed=3, walls=True)
     kw = dict(n_species=2, walls=True, g1=lbgen.EMULSION_G1, g2=lbgen.EMULSION_G2, gab=lbgen.EMULSION_GAB,
